@@ -1,0 +1,243 @@
+"""Reference implementation of the single-pulse fringe search, in complex128.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module; only the test suite, the smoke check and the CPU-baseline
+leg of the benchmark do.  It is deliberately slow and plain: every transform
+is the direct DFT written as a dense matrix product, every peak is found by a
+brute-force argmax, so that a reader can check it against the paper by eye.
+
+What is computed (paper: section "Fringe fitting", the search function G with
+its phase model Eq. (1); section "Code optimization", steps 5 and 6; section
+"Detection rate", the threshold on each window series):
+
+  For one baseline with visibilities x[t, f] (t = accumulation period, f the
+  concatenated IF x channel index, all IFs treated as one band), a window of
+  W consecutive APs starting at t0 gives the delay / delay-rate grid
+
+      G[k_t, k_f] = sum_{u<W} sum_{f<F} x[t0+u, f]
+                    * exp(-2 pi i (k_t u / M_t + k_f f / M_f)),
+
+  with M_f = pad_freq * F delay bins and M_t = pad_time * W rate bins (the
+  zero padding of the paper's delay FFT, and of the rate transform the
+  delay-rate search adds).  P = |G|^2; the peak is the argmax of P, ties broken
+  by the lowest flat index k_t * M_f + k_f; E = mean(P); amp = sqrt(P_peak);
+  SNR = amp / sqrt(E) (0 when E = 0).  A window is a candidate when SNR
+  exceeds the threshold.  Windows of length W start every max(1, W // 2) APs;
+  a tail shorter than W is dropped.
+
+Readings of points the paper leaves open (all channels are summed, IF
+calibration terms are zero, the rate axis and its padding, the stride, the
+SNR normalisation, tie-breaking, the all-zero window) are the ones listed in
+the design notes; each function below names the passage it follows.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "window_stride",
+    "window_starts",
+    "delay_dft_matrix",
+    "rate_dft_matrix",
+    "delay_spectra",
+    "window_grid",
+    "grid_peak",
+    "signed_bin",
+    "WindowResult",
+    "search_window",
+    "search_baseline",
+    "search_scan",
+    "TABLE_DTYPE",
+]
+
+
+def window_stride(window_ap: int) -> int:
+    """Start-to-start distance of windows of one length: half the length
+    (50 % overlap), and 1 for single-AP windows.
+
+    Paper: section "Fringe fitting" builds time segments of several window
+    sizes by summing APs; the stride is not stated there, so the half-window
+    overlap of the benchmark configurations is used.
+    """
+    return max(1, window_ap // 2)
+
+
+def window_starts(n_ap: int, window_ap: int) -> np.ndarray:
+    """All start APs t0 = j * stride with t0 + W <= n_ap, ascending."""
+    s = window_stride(window_ap)
+    if n_ap < window_ap:
+        return np.zeros(0, dtype=np.int64)
+    return np.arange(0, n_ap - window_ap + 1, s, dtype=np.int64)
+
+
+def delay_dft_matrix(n_freq: int, m_f: int) -> np.ndarray:
+    """A_f[f, k] = exp(-2 pi i k f / M_f) for f < F, k < M_f.
+
+    Paper: section "Fringe fitting", the search function G sums
+    S(n, j) exp(-i Phi) with Phi = 2 pi (f0_n + f_j - f_ref) dtau (Eq. 1,
+    calibration terms zero); evaluating Phi on the delay grid
+    dtau = k / (M_f * df) of an FFT zero-padded by M_f / F gives this matrix
+    (up to the constant phase of f0 - f_ref, which leaves |G| unchanged).
+    """
+    f = np.arange(n_freq, dtype=np.float64)[:, None]
+    k = np.arange(m_f, dtype=np.float64)[None, :]
+    return np.exp(-2j * np.pi * (f * k) / m_f)
+
+
+def rate_dft_matrix(window_ap: int, m_t: int) -> np.ndarray:
+    """A_t[k, u] = exp(-2 pi i k u / M_t) for k < M_t, u < W.
+
+    The delay-rate axis: the transform over the window's APs, zero-padded
+    to M_t = pad_time * W.  Its row k = 0 is the plain coherent sum of the
+    window's APs, which is the paper's own combination (section "Code
+    optimization", step 6).
+    """
+    k = np.arange(m_t, dtype=np.float64)[:, None]
+    u = np.arange(window_ap, dtype=np.float64)[None, :]
+    return np.exp(-2j * np.pi * (k * u) / m_t)
+
+
+def delay_spectra(x_b: np.ndarray, pad_freq: int) -> np.ndarray:
+    """Y[t, k_f] = sum_f x[t, f] exp(-2 pi i k_f f / M_f), every AP.
+
+    Paper: section "Code optimization", step 5 (a transform along frequency
+    for each AP, zero-padded by the padding factor of section "Fringe
+    fitting").  x_b has shape (T, F); the result is complex128 (T, M_f).
+    """
+    x_b = np.asarray(x_b, dtype=np.complex128)
+    n_freq = x_b.shape[1]
+    return x_b @ delay_dft_matrix(n_freq, pad_freq * n_freq)
+
+
+def window_grid(y: np.ndarray, t0: int, window_ap: int, pad_time: int) -> np.ndarray:
+    """G[k_t, k_f] for the window [t0, t0 + W) from the delay spectra Y.
+
+    The time sum of step 6 (section "Code optimization"), generalised from
+    the rate-0 sum to all M_t rate bins.  Shape (M_t, M_f), complex128.
+    """
+    seg = y[t0:t0 + window_ap]
+    if seg.shape[0] != window_ap:
+        raise ValueError("window runs past the end of the data")
+    return rate_dft_matrix(window_ap, pad_time * window_ap) @ seg
+
+
+@dataclass
+class WindowResult:
+    k_rate: int
+    k_delay: int
+    amp: float
+    snr: float
+    energy: float
+    peak_power: float
+    margin: float  # (P1 - P2) / P1 over distinct bins, 1.0 if undefined
+
+
+def grid_peak(g: np.ndarray, duplicate_rate_rows: bool = False) -> WindowResult:
+    """Peak of |G|^2 with lowest-flat-index tie-break, mean power, SNR.
+
+    Paper: section "Code optimization", step 6 (maximum amplitude over the
+    delay axis, here over the delay-rate grid) and section "Detection rate"
+    (a normalised power compared with a threshold; its normalisation is not
+    given, and the grid's own mean power is used).
+
+    `duplicate_rate_rows` marks grids whose rows are identical by
+    construction (a one-AP window padded to two rate bins); the margin to
+    the runner-up is then taken over the first row only, since the second
+    row repeats it exactly in any arithmetic.
+    """
+    p = (g.real * g.real) + (g.imag * g.imag)
+    m_f = p.shape[1]
+    flat = int(np.argmax(p))  # first occurrence == lowest flat index
+    k_t, k_f = divmod(flat, m_f)
+    p1 = float(p.flat[flat])
+    e = float(p.mean())
+    amp = math.sqrt(p1)
+    snr = amp / math.sqrt(e) if e > 0.0 else 0.0
+    if e == 0.0:
+        # all-zero window: peak at (0, 0), amplitude 0, never a candidate
+        k_t, k_f, amp, snr = 0, 0, 0.0, 0.0
+    q = p[:1] if duplicate_rate_rows else p
+    if q.size > 1 and p1 > 0.0:
+        second = np.partition(q.ravel(), -2)[-2]
+        margin = (p1 - float(second)) / p1
+    else:
+        margin = 1.0
+    return WindowResult(k_t, k_f, amp, snr, e, p1, margin)
+
+
+def signed_bin(k: int, m: int) -> int:
+    """FFT-frequency convention: bins at or above M/2 are negative."""
+    return k - m if k >= m // 2 else k
+
+
+def search_window(x_b: np.ndarray, t0: int, window_ap: int,
+                  pad_freq: int, pad_time: int) -> WindowResult:
+    """One window straight from the raw visibilities (both DFTs direct)."""
+    seg = np.asarray(x_b[t0:t0 + window_ap], dtype=np.complex128)
+    y = delay_spectra(seg, pad_freq)
+    g = window_grid(y, 0, window_ap, pad_time)
+    return grid_peak(g, duplicate_rate_rows=(window_ap == 1 and pad_time > 1))
+
+
+TABLE_DTYPE = np.dtype([
+    ("scan", np.int32), ("baseline", np.int32), ("window_ap", np.int32),
+    ("t_start", np.int32), ("k_rate", np.int32), ("k_delay", np.int32),
+    ("amp", np.float64), ("snr", np.float64), ("energy", np.float64),
+    ("delay_s", np.float64), ("rate_hz", np.float64),
+    ("margin", np.float64),
+])
+
+
+def search_baseline(x_b: np.ndarray, window_aps, pad_freq: int, pad_time: int,
+                    ap_seconds: float, chan_width_hz: float,
+                    scan: int = 0, baseline: int = 0) -> np.ndarray:
+    """Every window of one baseline, in (window length, start) order.
+
+    The delay transform is done once per AP and shared by all windows
+    (section "Code optimization": step 5 once, step 6 per window size).
+    """
+    x_b = np.asarray(x_b)
+    n_ap, n_freq = x_b.shape
+    m_f = pad_freq * n_freq
+    y = delay_spectra(x_b, pad_freq)
+    rows = []
+    for w in sorted(int(v) for v in window_aps):
+        m_t = pad_time * w
+        a_t = rate_dft_matrix(w, m_t)
+        for t0 in window_starts(n_ap, w):
+            g = a_t @ y[t0:t0 + w]
+            r = grid_peak(g, duplicate_rate_rows=(w == 1 and pad_time > 1))
+            rows.append((scan, baseline, w, int(t0), r.k_rate, r.k_delay,
+                         r.amp, r.snr, r.energy,
+                         signed_bin(r.k_delay, m_f) / (m_f * chan_width_hz),
+                         signed_bin(r.k_rate, m_t) / (m_t * ap_seconds),
+                         r.margin))
+    return np.array(rows, dtype=TABLE_DTYPE)
+
+
+def search_scan(vis: np.ndarray, window_aps, pad_freq: int, pad_time: int,
+                snr_threshold: float, ap_seconds: float, chan_width_hz: float,
+                scan: int = 0, baselines=None):
+    """Full search of one scan.
+
+    vis has shape (B, T, n_if, n_chan) (or (B, T, F)); the frequency index
+    is f = n * n_chan + c, so all IFs form one band (section "Fringe
+    fitting": one delay across all IFs).  Returns (table, candidates): the
+    per-window table in key order (baseline, window length, start) and the
+    windows whose SNR exceeds the threshold (strictly), same order.
+    """
+    vis = np.asarray(vis)
+    b_count, n_ap = vis.shape[0], vis.shape[1]
+    flat = vis.reshape(b_count, n_ap, -1)
+    if baselines is None:
+        baselines = range(b_count)
+    tables = [search_baseline(flat[b], window_aps, pad_freq, pad_time,
+                              ap_seconds, chan_width_hz, scan=scan, baseline=b)
+              for b in baselines]
+    table = np.concatenate(tables) if tables else np.zeros(0, TABLE_DTYPE)
+    cands = table[table["snr"] > snr_threshold]
+    return table, cands

@@ -1,0 +1,319 @@
+"""Pins of the CPU reference against facts fixed by the paper and by the
+mathematics of the DFT, not against itself.
+
+Each check is a plain function of the reference module so that the
+planted-mistake tests at the bottom can run the same checks against a
+deliberately broken copy and confirm that some check catches it.
+"""
+
+import json
+import math
+import os
+import types
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+import oracle.fringe_oracle as fo
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_x(rng, w, f):
+    return rng.standard_normal((w, f)) + 1j * rng.standard_normal((w, f))
+
+
+def _grid(mod, x, pad_f, pad_t):
+    w = x.shape[0]
+    y = mod.delay_spectra(x, pad_f)
+    return mod.window_grid(y, 0, w, pad_t)
+
+
+# ---------------------------------------------------------------- checks ---
+
+def check_c1_closed_form(mod):
+    """Noise-free C1: exact peak bins, amplitudes, SNRs, candidate list."""
+    gold = json.load(open(os.path.join(GOLDEN, "c1_noise_free.json")))
+    spec = synth.c1(noise=False)
+    v = spec.full()
+    table, cands = mod.search_scan(v, [gold["window_ap"]], gold["pad_freq"],
+                                   gold["pad_time"], gold["snr_threshold"],
+                                   spec.ap_seconds, spec.chan_width_hz)
+    assert len(table) == gold["n_windows"]
+    assert list(table["t_start"]) == list(range(0, 61, gold["stride"]))
+    assert [int(c) for c in cands["t_start"]] == [c["t_start"] for c in gold["candidates"]]
+    for row, g in zip(cands, gold["candidates"]):
+        assert (int(row["k_rate"]), int(row["k_delay"])) == (g["k_rate"], g["k_delay"])
+        assert row["amp"] == pytest.approx(g["amp"], rel=1e-6)
+        assert row["snr"] == pytest.approx(g["snr"], rel=1e-6)
+        assert row["energy"] == pytest.approx(g["energy"], rel=1e-6)
+    rest = table[~np.isin(table["t_start"], cands["t_start"])]
+    o = gold["other_windows"]
+    assert np.all(rest["k_rate"] == o["k_rate"]) and np.all(rest["k_delay"] == o["k_delay"])
+    assert np.all(rest["amp"] == 0.0) and np.all(rest["snr"] == 0.0)
+
+
+def check_library_fft(mod):
+    """G equals numpy's 2-D FFT of the zero-padded window (P3) and row 0
+    equals the FFT of the coherent AP sum, the paper's own scheme (P4)."""
+    rng = np.random.default_rng(7)
+    for w, f, pf, pt in [(1, 8, 4, 2), (2, 4, 4, 2), (4, 32, 4, 2), (8, 16, 2, 2),
+                         (4, 16, 1, 1), (16, 8, 4, 1), (3, 5, 4, 2)]:
+        x = _rand_x(rng, w, f)
+        g = _grid(mod, x, pf, pt)
+        ref = np.fft.fft2(x, s=(pt * w, pf * f))
+        assert g.shape == ref.shape
+        assert np.allclose(g, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+        row0 = np.fft.fft(x.sum(axis=0), n=pf * f)
+        assert np.allclose(g[0], row0, rtol=0, atol=1e-10 * np.abs(row0).max())
+
+
+def check_parseval_and_energy(mod):
+    """sum |G|^2 = M_t M_f sum |x|^2, and E (the mean power) = sum |x|^2 (P2)."""
+    rng = np.random.default_rng(11)
+    for w, f, pf, pt in [(4, 32, 4, 2), (1, 16, 4, 2), (8, 8, 2, 1)]:
+        x = _rand_x(rng, w, f)
+        g = _grid(mod, x, pf, pt)
+        ex = float(np.sum(np.abs(x) ** 2))
+        assert float(np.sum(np.abs(g) ** 2)) == pytest.approx(pt * w * pf * f * ex, rel=1e-12)
+        r = mod.grid_peak(g)
+        assert r.energy == pytest.approx(ex, rel=1e-12)
+
+
+def check_on_grid_fringe(mod):
+    """A unit fringe on grid bin (a, b) over all W APs peaks there with
+    amplitude W*F and SNR sqrt(W*F) (P1 in general form)."""
+    for w, f, pf, pt, a, b in [(4, 32, 4, 2, 3, 50), (8, 16, 4, 2, 13, 7),
+                               (2, 64, 2, 2, 0, 100), (16, 8, 1, 1, 5, 3)]:
+        mt, mf = pt * w, pf * f
+        u = np.arange(w)[:, None]
+        ff = np.arange(f)[None, :]
+        x = np.exp(2j * np.pi * (a * u / mt + b * ff / mf))
+        r = mod.search_window(x, 0, w, pf, pt)
+        assert (r.k_rate, r.k_delay) == (a, b)
+        assert r.amp == pytest.approx(w * f, rel=1e-12)
+        assert r.snr == pytest.approx(math.sqrt(w * f), rel=1e-12)
+
+
+def check_ties_and_zero(mod):
+    """W = 1 rows are identical: the lower rate bin wins; an all-zero window
+    gives peak (0, 0), amplitude 0, SNR 0."""
+    rng = np.random.default_rng(3)
+    x = _rand_x(rng, 1, 16)
+    r = mod.search_window(x, 0, 1, 4, 2)
+    assert r.k_rate == 0
+    g = _grid(mod, x, 4, 2)
+    assert np.array_equal(g[0], g[1])
+    z = mod.search_window(np.zeros((4, 8), complex), 0, 4, 4, 2)
+    assert (z.k_rate, z.k_delay, z.amp, z.snr, z.energy) == (0, 0, 0.0, 0.0, 0.0)
+
+
+def check_window_counts(mod):
+    """Window enumeration against the closed form floor((T-W)/s)+1 summed
+    over lengths: 172132 per baseline for the EVN-like scan (T=58600,
+    W=1..32) and 349761 for the large dense scan (T=117200, W=1..128)."""
+    def closed(t, ws):
+        return sum((t - w) // max(1, w // 2) + 1 for w in ws)
+    for t, ws, expect in [(58600, [1, 2, 4, 8, 16, 32], 172132),
+                          (117200, [1, 2, 4, 8, 16, 32, 64, 128], 349761),
+                          (64, [4], 31)]:
+        assert closed(t, ws) == expect
+        assert sum(len(mod.window_starts(t, w)) for w in ws) == expect
+    st = mod.window_starts(64, 4)
+    assert st[0] == 0 and st[-1] == 60 and np.all(np.diff(st) == 2)
+    assert list(mod.window_starts(5, 1)) == [0, 1, 2, 3, 4]
+    assert len(mod.window_starts(3, 4)) == 0
+
+
+ALL_CHECKS = [check_c1_closed_form, check_library_fft, check_parseval_and_energy,
+              check_on_grid_fringe, check_ties_and_zero, check_window_counts]
+
+
+@pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda c: c.__name__)
+def test_pin(check):
+    check(fo)
+
+
+# ---------------------------------------------------- statistical laws -----
+
+def test_noise_bin_law():
+    """Noise only: at a fixed bin, SNR^2 / N ~ Beta(1, N-1), N = W*F, for any
+    padding (P5).  KS over 2000 seeds."""
+    w, f, pf, pt = 2, 4, 4, 2
+    n = w * f
+    vals = []
+    for s in range(2000):
+        x = _rand_x(np.random.default_rng([123, s]), w, f)
+        g = _grid(fo, x, pf, pt)
+        e = fo.grid_peak(g).energy
+        vals.append(abs(g[1, 3]) ** 2 / e / n)
+    p = stats.kstest(vals, stats.beta(1, n - 1).cdf).pvalue
+    assert p > 1e-3
+
+
+def _fisher_g_sf(x, m):
+    j = np.arange(1, int(math.floor(1.0 / x)) + 1)
+    return float(np.sum((-1.0) ** (j - 1) * special.comb(m, j) * (1 - j * x) ** (m - 1)))
+
+
+def test_noise_max_fisher_g():
+    """Noise only, unpadded grid: SNR_max^2 / M follows Fisher's g for M
+    complex ordinates (P6).  KS over 2000 seeds."""
+    w, f = 2, 4
+    m = w * f
+    gs = []
+    for s in range(2000):
+        x = _rand_x(np.random.default_rng([321, s]), w, f)
+        r = fo.search_window(x, 0, w, 1, 1)
+        gs.append(r.snr ** 2 / m)
+    p = stats.kstest(gs, lambda v: np.array([1.0 - _fisher_g_sf(t, m) if t > 0 else 0.0
+                                             for t in np.atleast_1d(v)])).pvalue
+    assert p > 1e-3
+
+
+# ---------------------------------------------------------- invariances ----
+
+def test_shift_invariance():
+    """x * exp(+2 pi i (a u / M_t + b f / M_f)) moves the peak by (a, b) (P8)."""
+    rng = np.random.default_rng(5)
+    w, f, pf, pt = 8, 16, 4, 2
+    mt, mf = pt * w, pf * f
+    x = _rand_x(rng, w, f)
+    r0 = fo.search_window(x, 0, w, pf, pt)
+    for a, b in [(1, 0), (0, 1), (5, 40), (15, 63)]:
+        u = np.arange(w)[:, None]
+        ff = np.arange(f)[None, :]
+        xs = x * np.exp(2j * np.pi * (a * u / mt + b * ff / mf))
+        r = fo.search_window(xs, 0, w, pf, pt)
+        assert (r.k_rate, r.k_delay) == ((r0.k_rate + a) % mt, (r0.k_delay + b) % mf)
+        assert r.amp == pytest.approx(r0.amp, rel=1e-12)
+        assert r.snr == pytest.approx(r0.snr, rel=1e-12)
+
+
+def test_scale_invariance():
+    """x -> c x keeps the peak and SNR, scales amp by |c| (P9)."""
+    rng = np.random.default_rng(9)
+    x = _rand_x(rng, 4, 32)
+    r0 = fo.search_window(x, 0, 4, 4, 2)
+    c = 3.7 * np.exp(1j * 0.3)
+    r = fo.search_window(c * x, 0, 4, 4, 2)
+    assert (r.k_rate, r.k_delay) == (r0.k_rate, r0.k_delay)
+    assert r.snr == pytest.approx(r0.snr, rel=1e-12)
+    assert r.amp == pytest.approx(abs(c) * r0.amp, rel=1e-12)
+
+
+def test_partial_overlap():
+    """A fringe over q of the W APs at an on-grid rate peaks at a*q*F (P10)."""
+    w, f, pf, pt = 8, 16, 4, 2
+    mt, mf = pt * w, pf * f
+    for q, first in [(3, 0), (5, 3), (1, 7)]:
+        x = np.zeros((w, f), complex)
+        u = np.arange(first, first + q)[:, None]
+        ff = np.arange(f)[None, :]
+        x[first:first + q] = 0.25 * np.exp(2j * np.pi * (2 * u / mt + 9 * ff / mf))
+        r = fo.search_window(x, 0, w, pf, pt)
+        # one AP is flat across rate bins: the tie goes to rate bin 0
+        assert (r.k_rate, r.k_delay) == ((2 if q > 1 else 0), 9)
+        assert r.amp == pytest.approx(0.25 * q * f, rel=1e-12)
+        assert r.snr == pytest.approx(math.sqrt(q * f), rel=1e-12)
+
+
+def test_signed_bins_and_units():
+    assert fo.signed_bin(0, 8) == 0 and fo.signed_bin(3, 8) == 3
+    assert fo.signed_bin(4, 8) == -4 and fo.signed_bin(7, 8) == -1
+    spec = synth.c1(noise=False)
+    _, c = fo.search_scan(spec.full(), [4], 4, 2, 3.0, spec.ap_seconds, spec.chan_width_hz)
+    # k_f = 13 of 128 bins, df = 1/32: tau = 13 / (128 / 32) = 3.25 (the injected delay)
+    assert c["delay_s"][1] == pytest.approx(3.25)
+    # k_t = 1 of 8 bins, T_ap = 1: nu = 1/8 (the injected rate)
+    assert c["rate_hz"][1] == pytest.approx(0.125)
+
+
+def test_generator_determinism():
+    """Any baseline regenerates alone, bit for bit; the threaded full scan
+    equals the per-baseline arrays."""
+    spec = synth.c2(n_stations=4, n_ap=300)
+    full = spec.full(threads=3)
+    for b in range(spec.n_baselines):
+        assert np.array_equal(full[b], spec.baseline(b))
+    assert np.array_equal(spec.baseline(2, 100, 140), full[2, 100:140])
+
+
+# ------------------------------------------------------ planted mistakes ---
+
+def _mutant(**overrides):
+    m = types.ModuleType("mutant_oracle")
+    m.__dict__.update({k: getattr(fo, k) for k in dir(fo) if not k.startswith("__")})
+    m.__dict__.update(overrides)
+    # rebind functions so their globals see the overrides
+    for name in ("delay_spectra", "window_grid", "search_window", "search_baseline",
+                 "search_scan", "window_starts", "grid_peak"):
+        f = getattr(fo, name)
+        if name in overrides:
+            continue
+        g = types.FunctionType(f.__code__, m.__dict__, name, f.__defaults__, f.__closure__)
+        setattr(m, name, g)
+    return m
+
+
+def _fails(mod):
+    for c in ALL_CHECKS:
+        try:
+            c(mod)
+        except AssertionError:
+            return True
+    return False
+
+
+def _flip_sign_delay(n_freq, m_f):
+    return np.conj(fo.delay_dft_matrix(n_freq, m_f))
+
+
+def _rate_no_pad(window_ap, m_t):
+    return fo.rate_dft_matrix(window_ap, window_ap)[:, :] if m_t == window_ap else \
+        np.vstack([fo.rate_dft_matrix(window_ap, window_ap)] * (m_t // window_ap))
+
+
+def _peak_sum_energy(g, duplicate_rate_rows=False):
+    r = fo.grid_peak(g, duplicate_rate_rows)
+    e = r.energy * g.size
+    r.energy = e
+    r.snr = r.amp / math.sqrt(e) if e > 0 else 0.0
+    return r
+
+
+def _peak_last_tie(g, duplicate_rate_rows=False):
+    p = np.abs(g) ** 2
+    flat = p.size - 1 - int(np.argmax(p.ravel()[::-1]))
+    r = fo.grid_peak(g, duplicate_rate_rows)
+    r.k_rate, r.k_delay = divmod(flat, p.shape[1])
+    return r
+
+
+def _starts_full_stride(n_ap, w):
+    return np.arange(0, n_ap - w + 1, w) if n_ap >= w else np.zeros(0, int)
+
+
+def _transposed_freq(x_b, pad_freq):
+    x_b = np.asarray(x_b, complex)
+    # IF-major mistake: channel and IF axes swapped inside each AP
+    t, f = x_b.shape
+    return fo.delay_spectra(x_b.reshape(t, 2, f // 2).transpose(0, 2, 1).reshape(t, f), pad_freq)
+
+
+@pytest.mark.parametrize("overrides", [
+    dict(delay_dft_matrix=_flip_sign_delay),
+    dict(rate_dft_matrix=_rate_no_pad),
+    dict(grid_peak=_peak_sum_energy),
+    dict(grid_peak=_peak_last_tie),
+    dict(window_starts=_starts_full_stride),
+    dict(delay_spectra=_transposed_freq),
+], ids=["delay-sign", "rate-pad", "energy-sum", "tie-last", "stride", "freq-order"])
+def test_planted_mistake_is_caught(overrides):
+    assert _fails(_mutant(**overrides))
+
+
+def test_unmutated_reference_passes_all_checks():
+    assert not _fails(fo)
