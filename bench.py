@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Fringe-search benchmark on one MI355X.
+
+Workload: the EVN-like single scan (10 stations = 45 baselines, 58600 APs of
+1.024 ms = 60 s, 8 IF x 32 channels of 0.5 MHz, Gaussian noise, 20 pulses,
+10 narrowband RFI tones), windows of 1, 2, 4, 8, 16, 32 APs at 50 % overlap,
+4x delay padding, 2x rate padding, threshold 4.5: 7,745,940 windows.
+
+A step is one full search of the resident cube (delay transform, rate
+transform + peak, finalize, candidate compaction) plus the copy of the
+candidate list to the host.  Prints one JSON line on stdout; progress goes
+to stderr.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector, published
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def window_levels(n_ap, window_aps):
+    out = []
+    for w in window_aps:
+        s = max(1, w // 2)
+        out.append((w, s, (n_ap - w) // s + 1 if n_ap >= w else 0))
+    return out
+
+
+def algorithmic_flops(n_bl, n_ap, n_freq, window_aps, pad_f, pad_t):
+    """Radix-2 operation counts: 5 N log2 N per N-point complex FFT, 5 per
+    grid point for |G|^2, the max and the energy.  Returns (delay, rate,
+    peak) flops of one full search."""
+    m_f = pad_f * n_freq
+    delay = n_bl * n_ap * 5.0 * m_f * math.log2(m_f)
+    rate = peak = 0.0
+    for w, s, n in window_levels(n_ap, window_aps):
+        m_t = pad_t * w
+        rate += n_bl * n * m_f * 5.0 * m_t * max(1.0, math.log2(m_t))
+        peak += n_bl * n * m_f * m_t * 5.0
+    return delay, rate, peak
+
+
+def cpu_baseline(spec, params, n_bl=8, n_ap=4096):
+    """The CPU reference, as it stands, on a bounded sample of the same scan."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import fringe_oracle as fo
+    xs = [spec.baseline(b, 0, n_ap).reshape(n_ap, -1) for b in range(n_bl)]
+    t0 = time.perf_counter()
+    n = 0
+    for b, x in enumerate(xs):
+        n += len(fo.search_baseline(x, params["window_aps"], params["pad_freq"],
+                                    params["pad_time"], spec.ap_seconds, spec.chan_width_hz,
+                                    baseline=b))
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": n / dt, "unit": "windows/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"baselines 0-{n_bl - 1} x APs 0-{n_ap - 1} of the same scan, all "
+                      f"{len(params['window_aps'])} window lengths: {n} windows in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--stations", type=int, default=10, help="(smaller values: quick check only)")
+    ap.add_argument("--n-ap", type=int, default=58600, help="(smaller values: quick check only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2108_05602_amd as F
+    import synth
+
+    params = dict(synth.C2_PARAMS)
+    spec = synth.c2(n_stations=args.stations, n_ap=args.n_ap)
+    full = args.stations == 10 and args.n_ap == 58600
+    log(f"generating {spec.n_baselines} BL x {spec.n_ap} AP x {spec.n_freq} ch "
+        f"({spec.nbytes() / 1e9:.2f} GB)")
+    t0 = time.perf_counter()
+    v = spec.full(threads=min(16, os.cpu_count() or 1))
+    log(f"generated in {time.perf_counter() - t0:.1f} s; copying to cuda:0")
+    dev = torch.from_numpy(v).to("cuda:0")
+    del v
+    torch.cuda.synchronize()
+    desc = spec.desc()
+    plan = F.Plan([desc], params["window_aps"], pad_freq=params["pad_freq"],
+                  pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],
+                  max_candidates=1 << 20, flags=F.FRINGE_PROFILE)
+    info = plan.info()
+    n_win = info["n_windows"]
+    stream = torch.cuda.current_stream()
+    log(f"plan: {n_win} windows, {info['device_bytes'] / 1e9:.2f} GB device, "
+        f"{info['slab_baselines']} baselines per slab")
+    for i in range(args.warmup):
+        plan.search([dev.data_ptr()], stream.cuda_stream)
+        c = plan.candidates()
+        log(f"warmup {i}: {len(c)} candidates")
+    torch.cuda.synchronize()
+    kern = {"delay_ms": 0.0, "rate_ms": 0.0, "finalize_ms": 0.0, "compact_ms": 0.0,
+            "rate_launches": 0}
+    t_wall = time.perf_counter()
+    for i in range(args.steps):
+        plan.search([dev.data_ptr()], stream.cuda_stream)
+        cands = plan.candidates()
+        prof = plan.profile()
+        for k in ("delay_ms", "rate_ms", "finalize_ms", "compact_ms"):
+            kern[k] += prof[k]
+        kern["rate_launches"] += prof["rate_launches"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms_per_step = wall / args.steps * 1e3
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {len(cands)} candidates")
+    per_step = {k: kern[k] / args.steps for k in ("delay_ms", "rate_ms", "finalize_ms", "compact_ms")}
+    log("kernel ms/step " + json.dumps({k: round(x, 3) for k, x in per_step.items()}))
+
+    d_fl, r_fl, p_fl = algorithmic_flops(spec.n_baselines, spec.n_ap, spec.n_freq,
+                                         params["window_aps"], params["pad_freq"],
+                                         params["pad_time"])
+    # dominant kernel: rate transform + peak (all flops except the delay FFT)
+    launches = kern["rate_launches"]
+    avg_launch_s = kern["rate_ms"] / max(1, launches) / 1e3
+    flops_per_launch = (r_fl + p_fl) * args.steps / max(1, launches)
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    cube_bytes = spec.nbytes()
+    out = {
+        "metric": "fringe-fit windows/s + HBM GB/s vs roofline; p50/p99 window latency",
+        "value": n_win / (ms_per_step / 1e3),
+        "unit": "windows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("EVN-like single scan: 45 baselines x 58600 AP x 8 IF x 32 chan complex64, "
+                         "windows 1-32 AP at 50% overlap, 4x delay / 2x rate padding, SNR > 4.5")
+            if full else f"reduced EVN-like scan: {spec.n_baselines} BL x {spec.n_ap} AP (quick check)",
+            "windows": n_win,
+            "cube_bytes": cube_bytes,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "rate_peak_kernel (rate transform + |G|^2 peak)",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "algorithmic_flops_per_launch": flops_per_launch,
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "launches_per_step": launches / args.steps,
+        },
+        "hbm_gbs_algorithmic": cube_bytes / (ms_per_step / 1e3) / 1e9,
+        "hbm_frac_algorithmic": cube_bytes / (ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBS,
+        "tflops_algorithmic_step": (d_fl + r_fl + p_fl) / (ms_per_step / 1e3) / 1e12,
+        "kernel_ms_per_step": per_step,
+        "candidates": int(len(cands)),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU reference on its sample")
+        out["cpu_baseline"] = cpu_baseline(spec, params)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * fringe.h -- C ABI of the MI355X single-pulse fringe search (libfringe.so).
+ *
+ * The library searches complex visibilities for single pulses the way the
+ * VOLKS2 pipeline does (paper, section "Fringe fitting" and section "Code
+ * optimization", steps 5 and 6): for every baseline and every window of W
+ * consecutive accumulation periods (APs), the visibilities x[t, f] of the
+ * window (f = IF * n_chan + channel: all IFs form one band, one delay is
+ * searched across them) are transformed to the delay / delay-rate grid
+ *
+ *   G[k_t, k_f] = sum_{u<W} sum_{f<F} x[t0+u, f]
+ *                 * exp(-2 pi i (k_t u / M_t + k_f f / M_f)),
+ *
+ *   M_f = pad_freq * F   (the paper zero-pads its delay FFT 4x),
+ *   M_t = pad_time * W   (rate axis; pad_time = 1 with k_t = 0 alone is the
+ *                         paper's plain coherent sum over the window).
+ *
+ * The peak of P = |G|^2 (ties: lowest flat index k_t * M_f + k_f), the mean
+ * power E = mean(P) (equal to sum |x|^2 by Parseval), amp = sqrt(P_peak) and
+ * SNR = amp / sqrt(E) (0 when E = 0) are taken per window, and a window is a
+ * candidate when SNR > snr_threshold (section "Detection rate": windows whose
+ * normalised power exceeds a threshold).  Windows of length W start every
+ * max(1, W/2) APs; a tail shorter than W is dropped.  Cross-window and
+ * cross-baseline matching and localization are not part of this library.
+ *
+ * Every computation runs in HIP kernels on the GPU; there is no CPU path.
+ *
+ * Conventions for every entry point:
+ *   - returns 0 (FRINGE_OK) or a negative FRINGE_E_* code; never aborts or
+ *     throws across the ABI; fringe_last_error() gives a detail message for
+ *     the calling thread's last failure;
+ *   - a plan is not thread-safe; separate plans may be used concurrently
+ *     from separate threads on separate streams;
+ *   - visibilities must be finite; NaN / Inf inputs give undefined results.
+ */
+#ifndef FRINGE_H
+#define FRINGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes --------------------------------------------------------- */
+#define FRINGE_OK             0
+#define FRINGE_E_INVALID     -1  /* bad pointer, shape or parameter value          */
+#define FRINGE_E_UNSUPPORTED -2  /* valid but not built: non power-of-two F or W,   */
+                                 /* pad factors other than pad_freq 1/2/4,          */
+                                 /* pad_time 1/2, M_f outside [64, 4096], W > 128   */
+#define FRINGE_E_NOMEM       -3  /* the plan does not fit hbm_budget_bytes or HBM  */
+#define FRINGE_E_HIP         -4  /* a HIP runtime call failed                       */
+#define FRINGE_E_CAPACITY    -5  /* output capacity too small; *n_total is exact   */
+#define FRINGE_E_STATE       -6  /* call out of order (e.g. results before search) */
+
+/* ---- flags (fringe_params.flags) ----------------------------------------- */
+#define FRINGE_STREAMING  0x1u   /* each fringe_search call is the next chunk      */
+#define FRINGE_DUMP_GRID  0x2u   /* keep every window's full grid (tests; small)   */
+#define FRINGE_PROFILE    0x4u   /* time every kernel launch with HIP events       */
+
+/* One complex64 sample, identical in layout to torch.complex64 / numpy.complex64. */
+typedef struct { float re, im; } fringe_cf32;
+
+/* Opaque plan; owned by the library, released by fringe_plan_destroy. */
+typedef struct fringe_plan_s* fringe_plan_t;
+
+/* Shape of one scan (or, with FRINGE_STREAMING, of one chunk of a subarray's
+ * stream).  Its visibility cube is complex64, C order
+ * [n_baselines][n_ap][n_if][n_chan]; F = n_if * n_chan must be a power of
+ * two.  ap_seconds (AP length) and chan_width_hz (channel width) only set the
+ * physical units of the reported delay and rate. */
+typedef struct {
+  int32_t n_baselines, n_ap, n_if, n_chan;
+  double ap_seconds, chan_width_hz;
+} fringe_scan_desc;
+
+/* Search parameters, shared by every scan of a plan. */
+typedef struct {
+  const int32_t* window_aps;   /* window lengths W in APs, strictly ascending powers of two, <= 128 */
+  int32_t n_window_lengths;    /* 1..8                                                              */
+  int32_t pad_freq;            /* M_f / F: 1, 2 or 4 (the paper uses 4)                             */
+  int32_t pad_time;            /* M_t / W: 1 or 2                                                   */
+  float snr_threshold;         /* candidate iff SNR > snr_threshold (strict), >= 0                  */
+  uint64_t hbm_budget_bytes;   /* device bytes the plan may own; 0 = no limit beyond free HBM       */
+  int64_t max_candidates;      /* device candidate buffer length (>= 0)                             */
+  uint32_t flags;              /* FRINGE_* flags                                                    */
+} fringe_params;
+
+/* One window's result (a candidate, or any window via fringe_windows_get).
+ * k_rate in [0, M_t), k_delay in [0, M_f); delay_s and rate_hz use signed
+ * bins (bin >= M/2 means bin - M): delay_s = sk_delay / (M_f * chan_width_hz),
+ * rate_hz = sk_rate / (M_t * ap_seconds).  energy is E (= sum |x|^2). */
+typedef struct {
+  int32_t scan, baseline, window_ap, t_start, k_rate, k_delay;
+  float amp, snr, energy;
+  int32_t reserved;
+  double delay_s, rate_hz;
+} fringe_candidate;
+
+/* Sizes of a plan, from fringe_plan_check (no device work) or fringe_plan_info. */
+typedef struct {
+  int64_t n_windows;           /* windows of one full search (all scans, baselines, lengths) */
+  int64_t device_bytes;        /* device memory the plan owns                                 */
+  int64_t scratch_bytes;       /* of which transient work buffers                             */
+  int32_t max_window_ap;       /* largest W                                                   */
+  int32_t slab_baselines;      /* baselines processed per pass over the scratch               */
+} fringe_plan_summary;
+
+/* Validate scans and params and size the plan, without touching the GPU.
+ * Returns FRINGE_OK and fills *out, or the error fringe_plan would return
+ * for the same arguments (FRINGE_E_NOMEM only for an explicit budget). */
+int fringe_plan_check(const fringe_scan_desc* scans, int32_t n_scans,
+                      const fringe_params* params, fringe_plan_summary* out);
+
+/* Build a plan on the current HIP device: validate, enumerate windows,
+ * allocate all device memory within params->hbm_budget_bytes, upload the
+ * twiddle tables.  scans[0..n_scans) and params (including window_aps) are
+ * copied; the caller may free them afterwards.  *out receives the plan. */
+int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans,
+                const fringe_params* params, fringe_plan_t* out);
+
+/* Enqueue one search on hip_stream (a hipStream_t; NULL = default stream).
+ * d_vis[s] is the device address of scan s's cube (layout above); the
+ * caller owns it and keeps it valid and unchanged until the work on the
+ * stream has completed.  With FRINGE_STREAMING, d_vis[s] is the next chunk
+ * of subarray s (NULL: no chunk this call) and the windows reported are
+ * those whose last AP lies in that chunk, windows spanning the previous
+ * chunk included; start APs count from the first chunk.  Asynchronous:
+ * returns once the kernels are enqueued. */
+int fringe_search(fringe_plan_t plan, const fringe_cf32* const* d_vis, void* hip_stream);
+
+/* Wait for the plan's last search and copy its candidates, sorted by
+ * (scan, baseline, window_ap, t_start), into host_out[0..capacity).
+ * *n_total receives the number of candidates found.  If n_total exceeds
+ * capacity or params->max_candidates, the first min(capacity,
+ * max_candidates) in order are copied and FRINGE_E_CAPACITY is returned. */
+int candidates_get(fringe_plan_t plan, fringe_candidate* host_out,
+                   int64_t capacity, int64_t* n_total);
+
+/* Results of chosen windows of the last search.  Window ids number the
+ * windows in (scan, baseline, window length, start) order: id = scan_offset
+ * + baseline * n_per_baseline + level_offset + j, j = t_start / stride.
+ * (With FRINGE_STREAMING the ids number the windows of the last call.)
+ * Waits for the search; copies n records into host_out. */
+int fringe_windows_get(fringe_plan_t plan, const int64_t* window_ids, int64_t n,
+                       fringe_candidate* host_out);
+
+/* Window id <-> (scan, baseline, window_ap, t_start) for this plan. */
+int fringe_window_id(fringe_plan_t plan, int32_t scan, int32_t baseline,
+                     int32_t window_ap, int32_t t_start, int64_t* id);
+
+/* Full grid G of one window (plans made with FRINGE_DUMP_GRID only):
+ * M_t * M_f samples, row-major [k_t][k_f], into host_out[0..capacity). */
+int fringe_grid_get(fringe_plan_t plan, int64_t window_id, fringe_cf32* host_out,
+                    int64_t capacity);
+
+/* Kernel times of the last search of a plan made with FRINGE_PROFILE,
+ * measured with HIP events recorded on the search's stream around each
+ * launch (waits for the search).  Times in milliseconds, summed over the
+ * launches of each kernel; the counts are the launches. */
+typedef struct {
+  double delay_ms, rate_ms, finalize_ms, compact_ms;
+  int32_t delay_launches, rate_launches, finalize_launches, compact_launches;
+} fringe_profile;
+
+int fringe_profile_get(fringe_plan_t plan, fringe_profile* out);
+
+/* Sizes of an existing plan. */
+int fringe_plan_info(fringe_plan_t plan, fringe_plan_summary* out);
+
+/* Release every resource of the plan (waits for its outstanding work).
+ * NULL is ignored. */
+void fringe_plan_destroy(fringe_plan_t plan);
+
+/* Static description of an error code. */
+const char* fringe_strerror(int code);
+
+/* Detail message of the calling thread's last failed call ("" if none). */
+const char* fringe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRINGE_H */

@@ -1,0 +1,315 @@
+"""ctypes binding of libfringe (include/fringe.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+computation of its own; all search work runs in the library's HIP kernels.
+Device buffers are passed as integer addresses (e.g. torch.Tensor.data_ptr())
+and streams as integer hipStream_t handles (torch.cuda.Stream.cuda_stream).
+The library must have been built (python -m paper_2108_05602_amd.build);
+loading fails loudly otherwise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, c_char_p, c_double, c_float, c_int, c_int32,
+                    c_int64, c_uint32, c_uint64, c_void_p)
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libfringe.so")
+
+FRINGE_OK = 0
+FRINGE_E_INVALID = -1
+FRINGE_E_UNSUPPORTED = -2
+FRINGE_E_NOMEM = -3
+FRINGE_E_HIP = -4
+FRINGE_E_CAPACITY = -5
+FRINGE_E_STATE = -6
+
+FRINGE_STREAMING = 0x1
+FRINGE_DUMP_GRID = 0x2
+FRINGE_PROFILE = 0x4
+
+ENTRY_POINTS = (
+    "fringe_plan_check", "fringe_plan", "fringe_search", "candidates_get",
+    "fringe_windows_get", "fringe_window_id", "fringe_grid_get", "fringe_profile_get",
+    "fringe_plan_info",
+    "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
+)
+
+
+class fringe_scan_desc(Structure):
+    _fields_ = [("n_baselines", c_int32), ("n_ap", c_int32), ("n_if", c_int32),
+                ("n_chan", c_int32), ("ap_seconds", c_double), ("chan_width_hz", c_double)]
+
+
+class fringe_params(Structure):
+    _fields_ = [("window_aps", POINTER(c_int32)), ("n_window_lengths", c_int32),
+                ("pad_freq", c_int32), ("pad_time", c_int32), ("snr_threshold", c_float),
+                ("hbm_budget_bytes", c_uint64), ("max_candidates", c_int64),
+                ("flags", c_uint32)]
+
+
+class fringe_candidate(Structure):
+    _fields_ = [("scan", c_int32), ("baseline", c_int32), ("window_ap", c_int32),
+                ("t_start", c_int32), ("k_rate", c_int32), ("k_delay", c_int32),
+                ("amp", c_float), ("snr", c_float), ("energy", c_float),
+                ("reserved", c_int32), ("delay_s", c_double), ("rate_hz", c_double)]
+
+
+class fringe_plan_summary(Structure):
+    _fields_ = [("n_windows", c_int64), ("device_bytes", c_int64), ("scratch_bytes", c_int64),
+                ("max_window_ap", c_int32), ("slab_baselines", c_int32)]
+
+
+class fringe_profile(Structure):
+    _fields_ = [("delay_ms", c_double), ("rate_ms", c_double), ("finalize_ms", c_double),
+                ("compact_ms", c_double), ("delay_launches", c_int32),
+                ("rate_launches", c_int32), ("finalize_launches", c_int32),
+                ("compact_launches", c_int32)]
+
+
+CANDIDATE_DTYPE = np.dtype([
+    ("scan", np.int32), ("baseline", np.int32), ("window_ap", np.int32),
+    ("t_start", np.int32), ("k_rate", np.int32), ("k_delay", np.int32),
+    ("amp", np.float32), ("snr", np.float32), ("energy", np.float32),
+    ("reserved", np.int32), ("delay_s", np.float64), ("rate_hz", np.float64),
+], align=True)
+assert CANDIDATE_DTYPE.itemsize == ctypes.sizeof(fringe_candidate) == 56
+
+
+class FringeError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        self.code = code
+        super().__init__(f"{where}: {fringe_strerror(code)} ({code}): {detail}")
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libfringe.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2108_05602_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.fringe_plan_check.argtypes = [POINTER(fringe_scan_desc), c_int32, POINTER(fringe_params),
+                                      POINTER(fringe_plan_summary)]
+    lib.fringe_plan.argtypes = [POINTER(fringe_scan_desc), c_int32, POINTER(fringe_params),
+                                POINTER(c_void_p)]
+    lib.fringe_search.argtypes = [c_void_p, POINTER(c_void_p), c_void_p]
+    lib.candidates_get.argtypes = [c_void_p, c_void_p, c_int64, POINTER(c_int64)]
+    lib.fringe_windows_get.argtypes = [c_void_p, POINTER(c_int64), c_int64, c_void_p]
+    lib.fringe_window_id.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, POINTER(c_int64)]
+    lib.fringe_grid_get.argtypes = [c_void_p, c_int64, c_void_p, c_int64]
+    lib.fringe_plan_info.argtypes = [c_void_p, POINTER(fringe_plan_summary)]
+    lib.fringe_profile_get.argtypes = [c_void_p, POINTER(fringe_profile)]
+    lib.fringe_plan_destroy.argtypes = [c_void_p]
+    lib.fringe_plan_destroy.restype = None
+    lib.fringe_strerror.argtypes = [c_int]
+    lib.fringe_strerror.restype = c_char_p
+    lib.fringe_last_error.argtypes = []
+    lib.fringe_last_error.restype = c_char_p
+    for name in ENTRY_POINTS:
+        if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error"):
+            getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def fringe_strerror(code: int) -> str:
+    return load().fringe_strerror(code).decode()
+
+
+def fringe_last_error() -> str:
+    return load().fringe_last_error().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != FRINGE_OK:
+        raise FringeError(rc, where, fringe_last_error())
+
+
+# ------------------------------------------------------------ marshalling --
+
+def _scan_array(scans: Sequence[dict]):
+    arr = (fringe_scan_desc * len(scans))()
+    for i, s in enumerate(scans):
+        arr[i] = fringe_scan_desc(int(s["n_baselines"]), int(s["n_ap"]), int(s["n_if"]),
+                                  int(s["n_chan"]), float(s["ap_seconds"]),
+                                  float(s["chan_width_hz"]))
+    return arr
+
+
+def _params(window_aps: Iterable[int], pad_freq: int, pad_time: int, snr_threshold: float,
+            hbm_budget_bytes: int, max_candidates: int, flags: int):
+    w = list(int(v) for v in window_aps)
+    warr = (c_int32 * max(1, len(w)))(*w)
+    p = fringe_params(ctypes.cast(warr, POINTER(c_int32)) if w else None, len(w), int(pad_freq),
+                      int(pad_time), float(snr_threshold), int(hbm_budget_bytes),
+                      int(max_candidates), int(flags))
+    return p, warr
+
+
+def fringe_plan_check(scans: Sequence[dict], window_aps, pad_freq=4, pad_time=2,
+                      snr_threshold=4.5, hbm_budget_bytes=0, max_candidates=1 << 16,
+                      flags=0) -> dict:
+    """Validate and size without touching the GPU; raises FringeError."""
+    lib = load()
+    sa = _scan_array(scans)
+    p, keep = _params(window_aps, pad_freq, pad_time, snr_threshold, hbm_budget_bytes,
+                      max_candidates, flags)
+    out = fringe_plan_summary()
+    _check(lib.fringe_plan_check(sa, len(scans), ctypes.byref(p), ctypes.byref(out)),
+           "fringe_plan_check")
+    return {k: getattr(out, k) for k, _ in fringe_plan_summary._fields_}
+
+
+def fringe_plan(scans: Sequence[dict], window_aps, pad_freq=4, pad_time=2, snr_threshold=4.5,
+                hbm_budget_bytes=0, max_candidates=1 << 16, flags=0) -> int:
+    """Create a plan on the current HIP device; returns its handle."""
+    lib = load()
+    sa = _scan_array(scans)
+    p, keep = _params(window_aps, pad_freq, pad_time, snr_threshold, hbm_budget_bytes,
+                      max_candidates, flags)
+    h = c_void_p()
+    _check(lib.fringe_plan(sa, len(scans), ctypes.byref(p), ctypes.byref(h)), "fringe_plan")
+    return h.value
+
+
+def fringe_search(plan: int, vis_ptrs: Sequence[Optional[int]], stream: int = 0) -> None:
+    """Enqueue a search; vis_ptrs are device addresses (0/None = no chunk)."""
+    lib = load()
+    arr = (c_void_p * len(vis_ptrs))(*[int(v) if v else None for v in vis_ptrs])
+    _check(lib.fringe_search(c_void_p(plan), arr, c_void_p(int(stream) if stream else None)),
+           "fringe_search")
+
+
+def candidates_get(plan: int, capacity: Optional[int] = None) -> np.ndarray:
+    """All candidates of the last search, sorted (two-call pattern inside).
+    Raises FringeError(FRINGE_E_CAPACITY) if they overflowed the plan's
+    max_candidates."""
+    lib = load()
+    total = c_int64(0)
+    if capacity is None:
+        rc = lib.candidates_get(c_void_p(plan), None, 0, ctypes.byref(total))
+        if rc not in (FRINGE_OK, FRINGE_E_CAPACITY):
+            _check(rc, "candidates_get")
+        capacity = total.value
+    out = np.zeros(max(1, int(capacity)), dtype=CANDIDATE_DTYPE)
+    rc = lib.candidates_get(c_void_p(plan), out.ctypes.data_as(c_void_p), int(capacity),
+                            ctypes.byref(total))
+    _check(rc, "candidates_get")
+    return out[:min(int(capacity), total.value)]
+
+
+def candidates_get_raw(plan: int, capacity: int, max_candidates: int):
+    """(return code, n_total, copied records) without raising on
+    FRINGE_E_CAPACITY; the library copies min(capacity, max_candidates,
+    n_total) records."""
+    lib = load()
+    total = c_int64(0)
+    out = np.zeros(max(1, int(capacity)), dtype=CANDIDATE_DTYPE)
+    rc = lib.candidates_get(c_void_p(plan), out.ctypes.data_as(c_void_p), int(capacity),
+                            ctypes.byref(total))
+    n = max(0, min(int(capacity), int(max_candidates), total.value))
+    return rc, total.value, out[:n]
+
+
+def fringe_windows_get(plan: int, ids) -> np.ndarray:
+    lib = load()
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int64))
+    out = np.zeros(max(1, ids.size), dtype=CANDIDATE_DTYPE)
+    _check(lib.fringe_windows_get(c_void_p(plan), ids.ctypes.data_as(POINTER(c_int64)),
+                                  ids.size, out.ctypes.data_as(c_void_p)),
+           "fringe_windows_get")
+    return out[:ids.size]
+
+
+def fringe_window_id(plan: int, scan: int, baseline: int, window_ap: int, t_start: int) -> int:
+    lib = load()
+    out = c_int64(0)
+    _check(lib.fringe_window_id(c_void_p(plan), scan, baseline, window_ap, t_start,
+                                ctypes.byref(out)), "fringe_window_id")
+    return out.value
+
+
+def fringe_grid_get(plan: int, window_id: int, m_t: int, m_f: int) -> np.ndarray:
+    lib = load()
+    out = np.zeros((m_t, m_f), dtype=np.complex64)
+    _check(lib.fringe_grid_get(c_void_p(plan), int(window_id), out.ctypes.data_as(c_void_p),
+                               out.size), "fringe_grid_get")
+    return out
+
+
+def fringe_profile_get(plan: int) -> dict:
+    lib = load()
+    out = fringe_profile()
+    _check(lib.fringe_profile_get(c_void_p(plan), ctypes.byref(out)), "fringe_profile_get")
+    return {k: getattr(out, k) for k, _ in fringe_profile._fields_}
+
+
+def fringe_plan_info(plan: int) -> dict:
+    lib = load()
+    out = fringe_plan_summary()
+    _check(lib.fringe_plan_info(c_void_p(plan), ctypes.byref(out)), "fringe_plan_info")
+    return {k: getattr(out, k) for k, _ in fringe_plan_summary._fields_}
+
+
+def fringe_plan_destroy(plan: int) -> None:
+    if plan:
+        load().fringe_plan_destroy(c_void_p(plan))
+
+
+class Plan:
+    """Owning wrapper of a plan handle (destroyed on close / garbage collection)."""
+
+    def __init__(self, scans: Sequence[dict], window_aps, **kw):
+        self.scans = [dict(s) for s in scans]
+        self.window_aps = list(window_aps)
+        self.kw = dict(kw)
+        self.handle = fringe_plan(self.scans, self.window_aps, **kw)
+
+    def search(self, vis_ptrs, stream: int = 0):
+        fringe_search(self.handle, vis_ptrs, stream)
+
+    def candidates(self, capacity=None):
+        return candidates_get(self.handle, capacity)
+
+    def windows(self, ids):
+        return fringe_windows_get(self.handle, ids)
+
+    def window_id(self, scan, baseline, window_ap, t_start):
+        return fringe_window_id(self.handle, scan, baseline, window_ap, t_start)
+
+    def grid(self, window_id, m_t, m_f):
+        return fringe_grid_get(self.handle, window_id, m_t, m_f)
+
+    def info(self):
+        return fringe_plan_info(self.handle)
+
+    def profile(self):
+        return fringe_profile_get(self.handle)
+
+    def close(self):
+        if self.handle:
+            fringe_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

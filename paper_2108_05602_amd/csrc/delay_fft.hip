@@ -1,0 +1,204 @@
+// Delay transform: for every AP of every baseline, the zero-padded DFT
+// over the concatenated IF x channel axis (paper, section "Code
+// optimization", step 5; padding factor of section "Fringe fitting"):
+//   X_t[k] = sum_{f<F} x_t[f] exp(-2 pi i k f / M),  M = pad_f * F,
+// plus the AP energy e_t = sum_f |x_t[f]|^2 that the window SNR divides by.
+//
+// One wavefront per work group.  A wave transforms NAP = max(1, 1024 / M)
+// APs at a time with a self-sorting (Stockham) FFT: radix-16 passes, then
+// one radix-2/4/8 pass if log2(M) is not a multiple of 4.  The first pass
+// reads the visibilities straight from HBM (coalesced, the zero half /
+// three quarters of the padded input never loaded or multiplied), middle
+// passes go through LDS, and the last pass writes X to HBM in natural order.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace fringe {
+
+namespace {
+
+// DIF FFT of N points whose inputs beyond the first NZ are zero: stages
+// whose upper half is all zero only copy and twiddle the lower half.
+template <int N, int NZ, int LEN, int BLK, int J>
+__device__ __forceinline__ void pruned_stage_bf(float2* v) {
+  if constexpr (J < NZ) {
+    v[BLK + J + LEN / 2] = twiddle_mul<LEN, J>(v[BLK + J]);
+    pruned_stage_bf<N, NZ, LEN, BLK, J + 1>(v);
+  }
+}
+
+template <int N, int NZ, int LEN, int BLK>
+__device__ __forceinline__ void pruned_stage(float2* v) {
+  if constexpr (BLK < N) {
+    pruned_stage_bf<N, NZ, LEN, BLK, 0>(v);
+    pruned_stage<N, NZ, LEN, BLK + LEN>(v);
+  }
+}
+
+template <int N, int NZ, int LEN = N>
+__device__ __forceinline__ void fft_dif_pruned(float2* v) {
+  if constexpr (LEN >= 2) {
+    if constexpr (LEN / 2 >= NZ) {
+      pruned_stage<N, NZ, LEN, 0>(v);
+      fft_dif_pruned<N, NZ, LEN / 2>(v);
+    } else {
+      fft_dif<N, LEN>(v);
+    }
+  }
+}
+
+constexpr int first_radix(int log_m) { return log_m >= 4 ? 16 : (1 << log_m); }
+
+// One Stockham pass over NAP transforms of M points held in `lds`
+// (or, for the first pass, read from `xin`; for the last, written to `xout`).
+// Pass p has radix R and NS = product of the earlier radices:
+//   v[r] = in[j + r M/R] * w_{NS R}^{(j mod NS) r},  V = DFT_R(v),
+//   out[(j / NS) NS R + (j mod NS) + k NS] = V[k].
+template <int M, int NAP, int R, int NS, int PF, bool FIRST, bool LAST>
+__device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ xin,
+                                              float2* __restrict__ xout,
+                                              const float2* __restrict__ tw, int lane,
+                                              int n_valid_ap, int F, float* esum) {
+  constexpr int NBF = NAP * M / R;   // butterflies in this pass
+  constexpr int BPL = NBF / 64;      // per lane
+  static_assert(BPL >= 1 && NBF % 64 == 0, "pass does not fill the wave");
+  constexpr int SPAN = M / R;        // butterflies per transform
+  constexpr int NZ = FIRST ? (R / PF > 0 ? R / PF : 1) : R;
+  float2 v[BPL][R];
+#pragma unroll
+  for (int i = 0; i < BPL; ++i) {
+    const int jj = lane + 64 * i;
+    const int a = jj / SPAN;
+    const int j = jj % SPAN;
+    if constexpr (FIRST) {
+      const bool ok = a < n_valid_ap;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (r < NZ) {
+          const int idx = j + r * SPAN;
+          float2 x = make_float2(0.f, 0.f);
+          if (ok && idx < F) x = xin[static_cast<int64_t>(a) * F + idx];
+          v[i][r] = x;
+          *esum += c_norm(x);
+        } else {
+          v[i][r] = make_float2(0.f, 0.f);
+        }
+      }
+    } else {
+      const int jm = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = lds[a * M + j + r * SPAN];
+        if (r > 0) x = c_mul(x, tw[(jm * r) * (M / (NS * R))]);
+        v[i][r] = x;
+      }
+    }
+  }
+  if constexpr (!FIRST) __syncthreads();  // every read of the pass before any write
+#pragma unroll
+  for (int i = 0; i < BPL; ++i) {
+    const int jj = lane + 64 * i;
+    const int a = jj / SPAN;
+    const int j = jj % SPAN;
+    fft_dif_pruned<R, NZ>(v[i]);
+    const int idxd = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const float2 y = v[i][bitrev(k, ilog2(R))];
+      if constexpr (LAST) {
+        if (a < n_valid_ap) xout[static_cast<int64_t>(a) * M + idxd + k * NS] = y;
+      } else {
+        lds[a * M + idxd + k * NS] = y;
+      }
+    }
+  }
+  if constexpr (!LAST) __syncthreads();
+}
+
+// Passes after the first: radix 16 while at least 4 bits remain, then the rest.
+template <int M, int NAP, int PF, int NS>
+__device__ __forceinline__ void later_passes(float2* lds, float2* xout, const float2* tw,
+                                             int lane, int n_valid_ap, int F) {
+  if constexpr (NS < M) {
+    constexpr int rem = ilog2(M / NS);
+    constexpr int R = rem >= 4 ? 16 : (1 << rem);
+    constexpr bool LAST = (NS * R == M);
+    stockham_pass<M, NAP, R, NS, PF, false, LAST>(lds, nullptr, xout, tw, lane, n_valid_ap,
+                                                  F, nullptr);
+    later_passes<M, NAP, PF, NS * R>(lds, xout, tw, lane, n_valid_ap, F);
+  }
+}
+
+template <int LOGM, int PF>
+__global__ void __launch_bounds__(64) delay_fft_kernel(DelayArgs a) {
+  constexpr int M = 1 << LOGM;
+  constexpr int NAP = M >= 1024 ? 1 : 1024 / M;
+  constexpr int R0 = first_radix(LOGM);
+  constexpr int GROUP = (M / R0) < 64 ? (M / R0) : 64;  // lanes per AP in the first pass
+  extern __shared__ float2 lds[];
+  const int lane = threadIdx.x;
+  const int groups_per_bl = (a.T + NAP - 1) / NAP;
+  const int64_t n_groups = static_cast<int64_t>(a.nb) * groups_per_bl;
+  const int F = a.F;
+  for (int64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    const int b = static_cast<int>(g / groups_per_bl);
+    const int t0 = static_cast<int>(g % groups_per_bl) * NAP;
+    const int n_valid = min(NAP, a.T - t0);
+    const int64_t ap0 = static_cast<int64_t>(b) * a.T + t0;
+    const float2* xin = a.vis + ap0 * F;
+    float2* xout = a.X + ap0 * M;
+    float es = 0.f;
+    constexpr bool ONE_PASS = (R0 == M);
+    stockham_pass<M, NAP, R0, 1, PF, true, ONE_PASS>(lds, xin, xout, a.tw, lane, n_valid, F,
+                                                     &es);
+    // AP energies: lanes of one AP form an aligned group of GROUP lanes.
+#pragma unroll
+    for (int off = GROUP / 2; off >= 1; off >>= 1) es += __shfl_xor(es, off, 64);
+    if constexpr (NAP == 1) {
+      if (lane == 0) a.e[ap0] = es;
+    } else {
+      const int ap = lane / GROUP;
+      if ((lane % GROUP) == 0 && ap < n_valid) a.e[ap0 + ap] = es;
+    }
+    if constexpr (!ONE_PASS) later_passes<M, NAP, PF, R0>(lds, xout, a.tw, lane, n_valid, F);
+  }
+}
+
+template <int LOGM, int PF>
+hipError_t launch_one(const DelayArgs& a, hipStream_t st) {
+  constexpr int M = 1 << LOGM;
+  constexpr int NAP = M >= 1024 ? 1 : 1024 / M;
+  const int64_t groups = static_cast<int64_t>(a.nb) * ((a.T + NAP - 1) / NAP);
+  if (groups == 0) return hipSuccess;
+  const int grid = static_cast<int>(groups < 65536 ? groups : 65536);
+  const size_t lds = static_cast<size_t>(NAP) * M * sizeof(float2);
+  hipLaunchKernelGGL((delay_fft_kernel<LOGM, PF>), dim3(grid), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int PF>
+hipError_t launch_pf(const DelayArgs& a, hipStream_t st) {
+  switch (a.log_m) {
+    case 6: return launch_one<6, PF>(a, st);
+    case 7: return launch_one<7, PF>(a, st);
+    case 8: return launch_one<8, PF>(a, st);
+    case 9: return launch_one<9, PF>(a, st);
+    case 10: return launch_one<10, PF>(a, st);
+    case 11: return launch_one<11, PF>(a, st);
+    case 12: return launch_one<12, PF>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_delay_fft(const DelayArgs& a, hipStream_t st) {
+  switch (a.pad_f) {
+    case 1: return launch_pf<1>(a, st);
+    case 2: return launch_pf<2>(a, st);
+    case 4: return launch_pf<4>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fringe

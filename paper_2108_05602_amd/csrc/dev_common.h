@@ -1,0 +1,167 @@
+// Device helpers shared by the fringe-search kernels: complex arithmetic on
+// float2, unit roots evaluated at compile time, and a fully unrolled
+// radix-2 decimation-in-frequency FFT on a register array.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace fringe {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// ---------------------------------------------------------------- complex --
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float c_norm(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
+
+// ------------------------------------------------ compile-time unit roots --
+// exp(-2 pi i k / n) for n a power of two, from Taylor series on an octant-
+// reduced angle (|phi| <= pi/4, 13 terms: far below double rounding).
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int m = 1; m < 14; ++m) {
+    term *= -x2 / double((2 * m) * (2 * m + 1));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr double taylor_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int m = 1; m < 14; ++m) {
+    term *= -x2 / double((2 * m - 1) * (2 * m));
+    sum += term;
+  }
+  return sum;
+}
+
+struct CxD { double re, im; };
+
+constexpr CxD unit_root(long k, long n) {
+  k %= n;
+  if (k < 0) k += n;
+  // theta = 2 pi k / n = (pi / 4) * (oct + rem / n)
+  const long k8 = 8 * k;
+  const long oct = k8 / n;
+  const long rem = k8 - oct * n;
+  double c = 0, s = 0;
+  long quad = 0;
+  if ((oct & 1) == 0) {
+    const double phi = (kPi / 4) * double(rem) / double(n);
+    c = taylor_cos(phi);
+    s = taylor_sin(phi);
+    quad = oct / 2;
+  } else {  // theta = (oct + 1) pi / 4 - phi'
+    const double phi = (kPi / 4) * double(n - rem) / double(n);
+    c = taylor_cos(phi);
+    s = -taylor_sin(phi);
+    quad = (oct + 1) / 2;
+  }
+  double cr = c, sr = s;  // rotate by quad * 90 degrees
+  switch (quad & 3) {
+    case 1: cr = -s; sr = c; break;
+    case 2: cr = -c; sr = -s; break;
+    case 3: cr = s; sr = -c; break;
+    default: break;
+  }
+  // exp(-i theta) = cos - i sin; canonical +0 for exact zeros
+  return CxD{cr + 0.0, -sr + 0.0};
+}
+
+// d * exp(-2 pi i J / LEN), with the trivial angles done by moves.
+template <int LEN, int J>
+__device__ __forceinline__ float2 twiddle_mul(float2 d) {
+  constexpr int j = ((J % LEN) + LEN) % LEN;
+  if constexpr (j == 0) {
+    return d;
+  } else if constexpr (4 * j == LEN) {       // * (-i)
+    return make_float2(d.y, -d.x);
+  } else if constexpr (2 * j == LEN) {       // * (-1)
+    return make_float2(-d.x, -d.y);
+  } else if constexpr (4 * j == 3 * LEN) {   // * (+i)
+    return make_float2(-d.y, d.x);
+  } else {
+    constexpr CxD w = unit_root(j, LEN);
+    constexpr float wr = float(w.re), wi = float(w.im);
+    return make_float2(fmaf(d.x, wr, -d.y * wi), fmaf(d.x, wi, d.y * wr));
+  }
+}
+
+// -------------------------------------------------- register radix-2 FFT --
+// In-place DIF on v[0..N): afterwards v[i] holds X[bitrev(i)], where
+// X[k] = sum_n v_in[n] exp(-2 pi i k n / N).
+template <int N, int LEN, int BLK, int J>
+__device__ __forceinline__ void dif_butterflies(float2* v) {
+  if constexpr (J < LEN / 2) {
+    const float2 a = v[BLK + J];
+    const float2 b = v[BLK + J + LEN / 2];
+    v[BLK + J] = c_add(a, b);
+    v[BLK + J + LEN / 2] = twiddle_mul<LEN, J>(c_sub(a, b));
+    dif_butterflies<N, LEN, BLK, J + 1>(v);
+  }
+}
+
+template <int N, int LEN, int BLK>
+__device__ __forceinline__ void dif_blocks(float2* v) {
+  if constexpr (BLK < N) {
+    dif_butterflies<N, LEN, BLK, 0>(v);
+    dif_blocks<N, LEN, BLK + LEN>(v);
+  }
+}
+
+template <int N, int LEN = N>
+__device__ __forceinline__ void fft_dif(float2* v) {
+  if constexpr (LEN >= 2) {
+    dif_blocks<N, LEN, 0>(v);
+    fft_dif<N, LEN / 2>(v);
+  }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+constexpr int bitrev(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// ------------------------------------------------------ wave reductions --
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t key) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t lo = __shfl_xor(static_cast<uint32_t>(key), off, 64);
+    const uint32_t hi = __shfl_xor(static_cast<uint32_t>(key >> 32), off, 64);
+    const uint64_t other = (static_cast<uint64_t>(hi) << 32) | lo;
+    key = other > key ? other : key;
+  }
+  return key;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Peak key: larger power first, then lower flat index.  P >= 0, so its
+// IEEE bits order like the value.
+__device__ __forceinline__ uint64_t peak_key(float p, uint32_t flat) {
+  return (static_cast<uint64_t>(__float_as_uint(p)) << 32) | (0xFFFFFFFFu - flat);
+}
+
+}  // namespace fringe

@@ -1,0 +1,97 @@
+// Host-side interface of the fringe-search kernels (internal to libfringe).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fringe.h"
+
+namespace fringe {
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxWindowAp = 128;
+constexpr int kMinMf = 64;
+constexpr int kMaxMf = 4096;
+constexpr int kBinsPerWave = 64;
+
+// Window lengths of a plan, ascending; stride = max(1, W / 2).
+struct LevelTable {
+  int n;
+  int W[kMaxLevels];
+  int logW[kMaxLevels];
+  int s[kMaxLevels];
+};
+
+// Per-window result kept on the device: peak power's amplitude, SNR,
+// energy and the peak's flat index k_t * M_f + k_f.
+struct WindowRec {
+  float amp, snr, energy;
+  uint32_t flat;
+};
+
+// Per-scan constants on the device (window numbering and units).
+struct ScanDev {
+  int64_t win_off;                    // id of the scan's first window
+  int32_t nb, T, M_f, log_mf, nwb, pad_t;
+  double df, tap;
+  int32_t lvl_off[kMaxLevels + 1];    // per-baseline window offsets of each length
+};
+
+struct DelayArgs {
+  const float2* vis;   // [nb][T][F] visibilities of the slab
+  float2* X;           // [nb][T][M] delay spectra (out)
+  float* e;            // [nb][T] per-AP energy sum |x|^2 (out)
+  const float2* tw;    // [M] exp(-2 pi i k / M)
+  int nb, T, F, M, log_m, pad_f;
+};
+
+struct RateArgs {
+  const float2* X;     // [nb][T][M]
+  uint64_t* part;      // [n_kb][slab_windows] per bin-block peak keys (out)
+  float2* dump;        // full grids (FRINGE_DUMP_GRID) or nullptr
+  int64_t slab_windows;
+  int64_t dump_base;   // grid element offset of this slab's first baseline
+  int64_t grid_per_bl; // grid elements per baseline
+  int64_t lvl_goff[kMaxLevels];  // per-baseline grid offset of each length
+  int nb, T, M, log_m, n_kb, chunk, n_chunks, w_max, buf_slots, pad_t;
+  int nwb;
+  int lvl_off[kMaxLevels + 1];
+  LevelTable lv;
+};
+
+struct FinalizeArgs {
+  const uint64_t* part;
+  const float* e;
+  WindowRec* table;    // records of this slab's windows (already offset)
+  int64_t slab_windows;
+  int n_kb, nb, T, nwb;
+  int lvl_off[kMaxLevels + 1];
+  LevelTable lv;
+};
+
+struct CompactArgs {
+  const WindowRec* table;
+  int64_t n_windows;
+  float threshold;
+  int32_t* blk_counts;
+  int64_t* blk_offsets;
+  int64_t n_blocks;
+  fringe_candidate* out;
+  int64_t max_out;
+  int64_t* total;
+  const ScanDev* scans;
+  int n_scans;
+  LevelTable lv;
+};
+
+constexpr int kCompactBlock = 1024;  // windows per compaction block
+
+hipError_t launch_delay_fft(const DelayArgs& a, hipStream_t st);
+hipError_t launch_rate_peak(const RateArgs& a, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
+hipError_t launch_gather(const WindowRec* table, const int64_t* ids, int64_t n,
+                         fringe_candidate* out, const ScanDev* scans, int n_scans,
+                         const LevelTable& lv, hipStream_t st);
+
+}  // namespace fringe

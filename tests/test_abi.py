@@ -1,0 +1,106 @@
+"""CPU-only checks of the C ABI: the library loads, exports every entry
+point declared in include/fringe.h, and its host-side validation and
+sizing behave as documented (no device work is done here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2108_05602_amd as F
+from paper_2108_05602_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+C2 = dict(n_baselines=45, n_ap=58600, n_if=8, n_chan=32, ap_seconds=1.024e-3,
+          chan_width_hz=0.5e6)
+C2_W = [1, 2, 4, 8, 16, 32]
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fringe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.load()
+    decl = declared_functions()
+    assert set(decl) == set(B.ENTRY_POINTS), decl
+    for name in decl:
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(B.fringe_scan_desc) == 32
+    assert ctypes.sizeof(B.fringe_params) == 48
+    assert ctypes.sizeof(B.fringe_candidate) == 56
+    assert ctypes.sizeof(B.fringe_plan_summary) == 32
+
+
+def test_strerror():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert F.fringe_strerror(code)
+    assert F.fringe_strerror(-99) == "unknown error"
+
+
+def test_window_counts_match_closed_form():
+    s = F.fringe_plan_check([C2], C2_W, snr_threshold=4.5)
+    assert s["n_windows"] == 7745940
+    assert s["max_window_ap"] == 32
+    c5 = dict(n_baselines=66, n_ap=117200, n_if=16, n_chan=64, ap_seconds=0.512e-3,
+              chan_width_hz=0.25e6)
+    s5 = F.fringe_plan_check([c5], [1, 2, 4, 8, 16, 32, 64, 128], snr_threshold=4.5)
+    assert s5["n_windows"] == 23084226
+    c1 = dict(n_baselines=1, n_ap=64, n_if=2, n_chan=16, ap_seconds=1.0, chan_width_hz=1 / 32)
+    assert F.fringe_plan_check([c1], [4], snr_threshold=3.0)["n_windows"] == 31
+    # several scans add up; a scan shorter than every window has none
+    short = dict(c1, n_ap=3)
+    assert F.fringe_plan_check([c1, short, c1], [4], snr_threshold=3.0)["n_windows"] == 62
+
+
+def _code(fn):
+    with pytest.raises(F.FringeError) as e:
+        fn()
+    return e.value.code
+
+
+def test_validation_errors():
+    ok = dict(n_baselines=2, n_ap=100, n_if=4, n_chan=16, ap_seconds=1e-3, chan_width_hz=1e6)
+    chk = F.fringe_plan_check
+    assert _code(lambda: chk([dict(ok, n_chan=12)], [4])) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: chk([dict(ok, n_baselines=0)], [4])) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([dict(ok, ap_seconds=0.0)], [4])) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([ok], [3])) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: chk([ok], [256])) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: chk([ok], [4, 2])) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([ok], [4, 4])) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([ok], [])) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([ok], [4], pad_freq=3)) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: chk([ok], [4], pad_time=4)) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: chk([ok], [4], snr_threshold=-1.0)) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([ok], [4], snr_threshold=float("nan"))) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([ok], [4], max_candidates=-1)) == B.FRINGE_E_INVALID
+    assert _code(lambda: chk([ok], [4], flags=0x80)) == B.FRINGE_E_INVALID
+    # M_f = pad * F must lie in [64, 4096]
+    assert _code(lambda: chk([dict(ok, n_if=1, n_chan=8)], [4], pad_freq=4)) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: chk([dict(ok, n_if=16, n_chan=128)], [4], pad_freq=4)) == B.FRINGE_E_UNSUPPORTED
+    assert "power of two" in F.fringe_last_error() or F.fringe_last_error()
+
+
+def test_budget():
+    s = F.fringe_plan_check([C2], C2_W, snr_threshold=4.5)
+    # a generous budget fits; the plan stays inside it
+    b = F.fringe_plan_check([C2], C2_W, snr_threshold=4.5, hbm_budget_bytes=4 << 30)
+    assert b["device_bytes"] <= 4 << 30
+    assert b["slab_baselines"] < s["slab_baselines"]
+    # below the result buffers themselves: refused
+    assert _code(lambda: F.fringe_plan_check([C2], C2_W, hbm_budget_bytes=1 << 20)) == B.FRINGE_E_NOMEM
+
+
+def test_dump_grid_only_for_small_plans():
+    assert _code(lambda: F.fringe_plan_check([C2], C2_W, flags=B.FRINGE_DUMP_GRID)) == B.FRINGE_E_INVALID
