@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(64) delay_fft_kernel(DelayArgs a) {
     const int t0 = static_cast<int>(g % groups_per_bl) * NAP;
     const int n_valid = min(NAP, a.T - t0);
     const int64_t ap0 = static_cast<int64_t>(b) * a.T + t0;
-    const float2* xin = a.vis + ap0 * F;
+    const float2* xin = a.vis + static_cast<int64_t>(b) * a.vis_stride + static_cast<int64_t>(t0) * F;
     float2* xout = a.X + ap0 * M;
     float es = 0.f;
     constexpr bool ONE_PASS = (R0 == M);

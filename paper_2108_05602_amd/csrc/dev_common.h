@@ -140,28 +140,4 @@ constexpr int bitrev(int i, int bits) {
   return r;
 }
 
-// ------------------------------------------------------ wave reductions --
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t key) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const uint32_t lo = __shfl_xor(static_cast<uint32_t>(key), off, 64);
-    const uint32_t hi = __shfl_xor(static_cast<uint32_t>(key >> 32), off, 64);
-    const uint64_t other = (static_cast<uint64_t>(hi) << 32) | lo;
-    key = other > key ? other : key;
-  }
-  return key;
-}
-
-__device__ __forceinline__ float wave_sum_f32(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Peak key: larger power first, then lower flat index.  P >= 0, so its
-// IEEE bits order like the value.
-__device__ __forceinline__ uint64_t peak_key(float p, uint32_t flat) {
-  return (static_cast<uint64_t>(__float_as_uint(p)) << 32) | (0xFFFFFFFFu - flat);
-}
-
 }  // namespace fringe

@@ -1,6 +1,7 @@
 // Window results and candidate list.
 //
-// finalize: per window, the max of the bin-block peak keys, the window
+// finalize: per window, the max of the bin-block peak keys (window_key.h),
+//   the window
 //   energy E = sum of its APs' energies (= mean |G|^2 by Parseval),
 //   amp = sqrt(P_peak), SNR = amp / sqrt(E) (0 when E = 0).
 // compact: the windows with SNR > threshold (paper, section "Detection
@@ -27,14 +28,20 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalizeArgs a) {
   const int rem = static_cast<int>(w - static_cast<int64_t>(b) * a.nwb);
   int li = 0;
   while (li + 1 < a.lv.n && rem >= a.lvl_off[li + 1]) ++li;
-  const int j = rem - a.lvl_off[li];
+  const int j = rem - a.lvl_off[li] + a.lvl_j0[li];
   const int t0 = j * a.lv.s[li];
   const float* eb = a.e + static_cast<int64_t>(b) * a.T + t0;
   double energy = 0.0;
   for (int u = 0; u < a.lv.W[li]; ++u) energy += eb[u];
-  const float p = __uint_as_float(static_cast<uint32_t>(key >> 32));
+  // key = (rate key << 32) | (0xFFFFFFFF - k_f); rate key = power bits
+  // with the low log2(M_t) bits replaced by M_t - 1 - k_t
+  const uint32_t mask = static_cast<uint32_t>(a.pad_t * a.lv.W[li] - 1);
+  const uint32_t hi = static_cast<uint32_t>(key >> 32);
+  const float p = __uint_as_float(hi & ~mask);
+  const uint32_t k_t = mask - (hi & mask);
+  const uint32_t k_f = 0xFFFFFFFFu - static_cast<uint32_t>(key);
   WindowRec r;
-  r.flat = 0xFFFFFFFFu - static_cast<uint32_t>(key);
+  r.flat = k_t * static_cast<uint32_t>(a.M) + k_f;
   const double amp = sqrt(static_cast<double>(p));
   if (energy > 0.0) {
     r.amp = static_cast<float>(amp);
@@ -62,7 +69,7 @@ __device__ void decode_window(int64_t w, const WindowRec& rec, const ScanDev* sc
   const int rem = static_cast<int>(loc - static_cast<int64_t>(b) * sc.nwb);
   int li = 0;
   while (li + 1 < lv.n && rem >= sc.lvl_off[li + 1]) ++li;
-  const int j = rem - sc.lvl_off[li];
+  const int j = rem - sc.lvl_off[li] + sc.lvl_j0[li];
   const int wl = lv.W[li];
   const int m_t = sc.pad_t * wl;
   const int k_t = static_cast<int>(rec.flat >> sc.log_mf);
@@ -73,7 +80,7 @@ __device__ void decode_window(int64_t w, const WindowRec& rec, const ScanDev* sc
   c.scan = lo;
   c.baseline = b;
   c.window_ap = wl;
-  c.t_start = j * lv.s[li];
+  c.t_start = static_cast<int32_t>(sc.t_origin + static_cast<int64_t>(j) * lv.s[li]);
   c.k_rate = k_t;
   c.k_delay = k_f;
   c.amp = rec.amp;

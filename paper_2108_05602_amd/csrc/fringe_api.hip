@@ -1,10 +1,13 @@
 // Host side of libfringe: parameter validation, window enumeration, plan
-// sizing and device memory, and the launch sequence of one search.
+// sizing and device memory, streaming state, and the launch sequence of one
+// search.
 //
 // Window numbering (the order of every table and of the candidate list):
 //   id = scan_offset + baseline * n_per_baseline + level_offset[level] + j,
-//   t_start = j * stride(W),  stride(W) = max(1, W / 2),
-// for window lengths in ascending order and starts t with t + W <= n_ap.
+//   t_start = t_origin + (j0[level] + j) * stride(W),  stride(W) = max(1, W / 2),
+// for window lengths in ascending order.  A batch search numbers all windows
+// of each scan (t_origin = 0, j0 = 0); a streaming call numbers the windows
+// whose last AP lies in the call's chunk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,38 +50,73 @@ int log2i(int64_t v) {
   while ((int64_t(1) << r) < v) ++r;
   return r;
 }
+int64_t floor_to(int64_t v, int64_t m) { return v >= 0 ? (v / m) * m : -(((-v) + m - 1) / m) * m; }
+int64_t ceil_to(int64_t v, int64_t m) { return -floor_to(-v, m); }
 
 constexpr uint64_t kDefaultScratchCap = 8ull << 30;  // work buffers when no budget is given
 constexpr uint64_t kMaxDumpBytes = 1ull << 30;
 
+// Windows of one scan in one search: their numbering and where their data is.
+struct CallScan {
+  int T = 0;                          // APs of the searched data
+  int t_emit = 0;                     // windows end at or after this AP
+  int64_t t_origin = 0;               // absolute AP of the data's AP 0
+  int64_t nwb = 0;                    // windows per baseline
+  int64_t lvl_off[kMaxLevels + 1] = {};
+  int lvl_j0[kMaxLevels] = {};
+  int64_t win_off = 0;                // first window id
+};
+
+// Windows of every length in the data [0, T) that end at or after t_emit.
+void enumerate(CallScan* c, const LevelTable& lv) {
+  int64_t off = 0;
+  for (int l = 0; l < lv.n; ++l) {
+    const int64_t w = lv.W[l], s = lv.s[l];
+    const int64_t first = ceil_to(std::max<int64_t>(0, c->t_emit - w + 1), s);
+    const int64_t last = floor_to(int64_t(c->T) - w, s);
+    const int64_t n = last >= first ? (last - first) / s + 1 : 0;
+    c->lvl_off[l] = off;
+    c->lvl_j0[l] = int(first / s);
+    off += n;
+  }
+  for (int l = lv.n; l <= kMaxLevels; ++l) c->lvl_off[l] = off;
+  for (int l = lv.n; l < kMaxLevels; ++l) c->lvl_j0[l] = 0;
+  c->nwb = off;
+}
+
 struct ScanInfo {
   fringe_scan_desc d;
   int F, M, log_m, n_kb, pad_t;
-  int64_t nwb;                        // windows per baseline
-  int64_t lvl_off[kMaxLevels + 1];
-  int64_t n_windows;                  // nb * nwb
-  int64_t win_off;                    // first window id
+  CallScan full;                      // batch search: every window of the scan
+  int64_t nwb_max;                    // windows per baseline of any one call
   int64_t grid_per_bl;                // grid elements per baseline (dump)
   int64_t lvl_goff[kMaxLevels];
   int64_t grid_off;                   // first grid element of the scan (dump)
+  int stage_len;                      // streaming: APs of halo + chunk
   int slab_nb;                        // baselines per pass
-  int chunk, n_chunks;                // rate-kernel time tiling
+  int chunk;                          // search-kernel time tiling
 };
 
 struct Sizing {
   std::vector<ScanInfo> scans;
   LevelTable lv;
   int w_max = 0;
-  int64_t n_windows = 0;
+  bool fused = false;                 // fused kernel (w_max <= kFusedMaxWindow)
+  bool streaming = false;
+  int align = 1;                      // streaming: stage origins are multiples of this
+  int64_t n_windows = 0;              // windows of one call, at most
   int64_t n_blocks = 0;
-  uint64_t scratch_x = 0, scratch_e = 0, scratch_part = 0;
+  uint64_t scratch_x = 0, scratch_e = 0, scratch_part = 0, stage_bytes = 0;
   uint64_t table_bytes = 0, blk_bytes = 0, cand_bytes = 0, grid_bytes = 0, fixed_bytes = 0;
   uint64_t total = 0;
 };
 
-uint64_t per_baseline_scratch(const ScanInfo& s) {
-  return uint64_t(s.d.n_ap) * s.M * sizeof(float2) + uint64_t(s.d.n_ap) * sizeof(float) +
-         uint64_t(s.n_kb) * s.nwb * sizeof(uint64_t);
+int data_len(const ScanInfo& s, bool streaming) { return streaming ? s.stage_len : s.d.n_ap; }
+
+uint64_t per_baseline_scratch(const ScanInfo& s, bool fused, bool streaming) {
+  const uint64_t t = uint64_t(data_len(s, streaming));
+  const uint64_t x = fused ? 0 : t * s.M * sizeof(float2);
+  return x + t * sizeof(float) + uint64_t(s.n_kb) * s.nwb_max * sizeof(uint64_t);
 }
 
 int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* p,
@@ -90,8 +128,8 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     return fail(FRINGE_E_INVALID, "n_window_lengths must be in [1, %d]", kMaxLevels);
   if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE))
     return fail(FRINGE_E_INVALID, "unknown flag bits 0x%x", p->flags);
-  if (p->flags & FRINGE_STREAMING)
-    return fail(FRINGE_E_UNSUPPORTED, "FRINGE_STREAMING is not available in this build");
+  if ((p->flags & FRINGE_STREAMING) && (p->flags & FRINGE_DUMP_GRID))
+    return fail(FRINGE_E_INVALID, "FRINGE_DUMP_GRID is for batch plans only");
   if (!(p->snr_threshold >= 0.f) || !std::isfinite(p->snr_threshold))
     return fail(FRINGE_E_INVALID, "snr_threshold must be finite and >= 0");
   if (p->max_candidates < 0) return fail(FRINGE_E_INVALID, "max_candidates must be >= 0");
@@ -101,6 +139,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     return fail(FRINGE_E_UNSUPPORTED, "pad_time must be 1 or 2 (got %d)", p->pad_time);
 
   Sizing sz;
+  sz.streaming = (p->flags & FRINGE_STREAMING) != 0;
   sz.lv.n = p->n_window_lengths;
   for (int i = 0; i < sz.lv.n; ++i) {
     const int w = p->window_aps[i];
@@ -116,6 +155,10 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   }
   for (int i = sz.lv.n; i < kMaxLevels; ++i) sz.lv.W[i] = sz.lv.logW[i] = sz.lv.s[i] = 0;
   sz.w_max = sz.lv.W[sz.lv.n - 1];
+  sz.fused = sz.w_max <= kFusedMaxWindow;
+  // the kernels count window strides (and the fused kernel its period) from
+  // AP 0 of the data they read, so streaming stages start on multiples
+  sz.align = std::max(std::max(1, sz.w_max / 2), sz.fused ? fused_period(sz.w_max) : 1);
 
   int64_t win_off = 0, grid_off = 0;
   for (int s = 0; s < n_scans; ++s) {
@@ -140,27 +183,35 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     si.log_m = log2i(M);
     si.n_kb = int(M / kBinsPerWave);
     si.pad_t = p->pad_time;
-    int64_t off = 0, goff = 0;
+    si.full.T = d.n_ap;
+    enumerate(&si.full, sz.lv);
+    int64_t goff = 0;
     for (int l = 0; l < sz.lv.n; ++l) {
-      const int w = sz.lv.W[l];
-      const int64_t nl = d.n_ap >= w ? (int64_t(d.n_ap) - w) / sz.lv.s[l] + 1 : 0;
-      si.lvl_off[l] = off;
       si.lvl_goff[l] = goff;
-      off += nl;
-      goff += nl * int64_t(p->pad_time) * w * M;
+      goff += (si.full.lvl_off[l + 1] - si.full.lvl_off[l]) * int64_t(p->pad_time) * sz.lv.W[l] * M;
     }
-    for (int l = sz.lv.n; l <= kMaxLevels; ++l) si.lvl_off[l] = off;
-    si.nwb = off;
     si.grid_per_bl = goff;
-    si.n_windows = off * d.n_baselines;
-    if (si.nwb > (int64_t(1) << 30) || si.n_windows > (int64_t(1) << 40))
+    if (sz.streaming) {
+      // halo: the last W_max - 1 APs, plus up to align - 1 to start aligned
+      si.stage_len = (sz.w_max - 1) + (sz.align - 1) + d.n_ap;
+      int64_t nmax = 0;
+      for (int l = 0; l < sz.lv.n; ++l) nmax += (int64_t(d.n_ap) - 1) / sz.lv.s[l] + 1;
+      si.nwb_max = nmax;
+    } else {
+      si.nwb_max = si.full.nwb;
+    }
+    const int64_t nw = si.nwb_max * d.n_baselines;
+    if (si.nwb_max > (int64_t(1) << 30) || nw > (int64_t(1) << 40) ||
+        int64_t(data_len(si, sz.streaming)) > (int64_t(1) << 30))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: too many windows", s);
-    si.win_off = win_off;
+    si.full.win_off = win_off;
     si.grid_off = grid_off;
-    win_off += si.n_windows;
+    win_off += nw;
     grid_off += si.grid_per_bl * d.n_baselines;
-    si.chunk = std::min(1024, std::max(128, 8 * sz.w_max));
-    si.n_chunks = int((int64_t(d.n_ap) + si.chunk - 1) / si.chunk);
+    // time chunk of one work item: a multiple of the fused kernel's period
+    si.chunk = sz.fused ? 256 : std::min(1024, std::max(128, 8 * sz.w_max));
+    if (sz.streaming)
+      sz.stage_bytes += 2 * uint64_t(d.n_baselines) * si.stage_len * F * sizeof(float2);
     sz.scans.push_back(si);
   }
   sz.n_windows = win_off;
@@ -179,18 +230,19 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     for (auto& si : sz.scans)
       if (si.log_m == lm) { tw_bytes += (uint64_t(1) << lm) * sizeof(float2); break; }
   sz.fixed_bytes = sz.table_bytes + sz.blk_bytes + sz.cand_bytes + sz.grid_bytes + tw_bytes +
-                   uint64_t(n_scans) * sizeof(ScanDev) + 64;
+                   sz.stage_bytes + uint64_t(n_scans) * sizeof(ScanDev) + 64;
 
   // Work buffers: process each scan in slabs of baselines that fit.
   uint64_t cap = kDefaultScratchCap;
   if (p->hbm_budget_bytes > 0) {
     if (p->hbm_budget_bytes <= sz.fixed_bytes)
-      return fail(FRINGE_E_NOMEM, "hbm_budget_bytes %llu below the %llu bytes of results",
-                  (unsigned long long)p->hbm_budget_bytes, (unsigned long long)sz.fixed_bytes);
+      return fail(FRINGE_E_NOMEM, "hbm_budget_bytes %llu below the %llu bytes of results%s",
+                  (unsigned long long)p->hbm_budget_bytes, (unsigned long long)sz.fixed_bytes,
+                  sz.streaming ? " and stream history" : "");
     cap = p->hbm_budget_bytes - sz.fixed_bytes;
   }
   for (auto& si : sz.scans) {
-    const uint64_t per = per_baseline_scratch(si);
+    const uint64_t per = per_baseline_scratch(si, sz.fused, sz.streaming);
     int64_t nb = int64_t(cap / per);
     if (nb < 1) {
       if (p->hbm_budget_bytes > 0)
@@ -199,16 +251,44 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
       nb = 1;
     }
     si.slab_nb = int(std::min<int64_t>(nb, si.d.n_baselines));
-    sz.scratch_x = std::max<uint64_t>(sz.scratch_x, uint64_t(si.slab_nb) * si.d.n_ap * si.M * sizeof(float2));
-    sz.scratch_e = std::max<uint64_t>(sz.scratch_e, uint64_t(si.slab_nb) * si.d.n_ap * sizeof(float));
-    sz.scratch_part = std::max<uint64_t>(sz.scratch_part, uint64_t(si.slab_nb) * si.nwb * si.n_kb * sizeof(uint64_t));
+    const uint64_t t = uint64_t(data_len(si, sz.streaming));
+    if (!sz.fused) sz.scratch_x = std::max<uint64_t>(sz.scratch_x, uint64_t(si.slab_nb) * t * si.M * sizeof(float2));
+    sz.scratch_e = std::max<uint64_t>(sz.scratch_e, uint64_t(si.slab_nb) * t * sizeof(float));
+    sz.scratch_part = std::max<uint64_t>(sz.scratch_part, uint64_t(si.slab_nb) * si.nwb_max * si.n_kb * sizeof(uint64_t));
   }
   sz.total = sz.fixed_bytes + sz.scratch_x + sz.scratch_e + sz.scratch_part;
   *out = std::move(sz);
   return FRINGE_OK;
 }
 
+ScanDev make_scan_dev(const ScanInfo& si, const CallScan& c) {
+  ScanDev d{};
+  d.win_off = c.win_off;
+  d.t_origin = c.t_origin;
+  d.nb = si.d.n_baselines;
+  d.T = c.T;
+  d.M_f = si.M;
+  d.log_mf = si.log_m;
+  d.nwb = int32_t(c.nwb);
+  d.pad_t = si.pad_t;
+  d.df = si.d.chan_width_hz;
+  d.tap = si.d.ap_seconds;
+  for (int l = 0; l <= kMaxLevels; ++l) d.lvl_off[l] = int32_t(c.lvl_off[l]);
+  for (int l = 0; l < kMaxLevels; ++l) d.lvl_j0[l] = c.lvl_j0[l];
+  return d;
+}
+
 }  // namespace
+
+// Per-subarray state of a streaming plan: the last APs received, on the
+// device, in one of two stage buffers [nb][stage_len][F].
+struct StreamState {
+  float2* stage[2] = {nullptr, nullptr};
+  int cur = 0;            // stage holding the newest data
+  int64_t consumed = 0;   // APs received so far
+  int64_t origin = 0;     // absolute AP of stage[cur] AP 0
+  int len = 0;            // APs held in stage[cur]
+};
 
 struct fringe_plan_s {
   Sizing sz;
@@ -233,6 +313,14 @@ struct fringe_plan_s {
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool searched = false;
+  // streaming
+  std::vector<StreamState> streams;
+  ScanDev* h_scans[2] = {nullptr, nullptr};  // pinned staging of the per-call scan table
+  hipEvent_t h_scans_free[2] = {nullptr, nullptr};
+  int h_scans_cur = 0;
+  std::vector<CallScan> call;      // numbering of the last search
+  std::vector<char> call_present;
+  int64_t call_windows = 0;
   // FRINGE_PROFILE: an event pair per launch, kind 0..3 = delay, rate, finalize, compact
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_kind;
@@ -250,6 +338,13 @@ void release(fringe_plan_t p) {
     if (b) (void)hipFree(b);
   for (auto* t : p->tw)
     if (t) (void)hipFree(t);
+  for (auto& st : p->streams)
+    for (auto* b : st.stage)
+      if (b) (void)hipFree(b);
+  for (int k = 0; k < 2; ++k) {
+    if (p->h_scans[k]) (void)hipHostFree(p->h_scans[k]);
+    if (p->h_scans_free[k]) (void)hipEventDestroy(p->h_scans_free[k]);
+  }
   if (p->h_total) (void)hipHostFree(p->h_total);
   for (auto ev : p->prof_ev) (void)hipEventDestroy(ev);
   if (p->done) (void)hipEventDestroy(p->done);
@@ -291,20 +386,58 @@ hipError_t prof_end(fringe_plan_s* p, hipStream_t st) {
   return e;
 }
 
+// Window id of the last search -> (scan, baseline, level, j relative to j0).
 int decode_id(const fringe_plan_s* p, int64_t id, int* scan, int* b, int* li, int64_t* j) {
-  if (id < 0 || id >= p->sz.n_windows) return fail(FRINGE_E_INVALID, "window id %lld out of range", (long long)id);
-  int s = 0;
-  while (s + 1 < int(p->sz.scans.size()) && p->sz.scans[s + 1].win_off <= id) ++s;
-  const ScanInfo& si = p->sz.scans[s];
-  const int64_t loc = id - si.win_off;
-  const int64_t bb = loc / si.nwb;
-  const int64_t rem = loc - bb * si.nwb;
+  if (id < 0 || id >= p->call_windows)
+    return fail(FRINGE_E_INVALID, "window id %lld out of range", (long long)id);
+  int s = -1;
+  for (int k = 0; k < int(p->call.size()); ++k)
+    if (p->call_present[k] && p->call[k].win_off <= id) s = k;
+  const CallScan& c = p->call[s];
+  const int64_t loc = id - c.win_off;
+  const int64_t bb = loc / c.nwb;
+  const int64_t rem = loc - bb * c.nwb;
   int l = 0;
-  while (l + 1 < p->sz.lv.n && rem >= si.lvl_off[l + 1]) ++l;
+  while (l + 1 < p->sz.lv.n && rem >= c.lvl_off[l + 1]) ++l;
   *scan = s;
   *b = int(bb);
   *li = l;
-  *j = rem - si.lvl_off[l];
+  *j = rem - c.lvl_off[l];
+  return FRINGE_OK;
+}
+
+// Stream subarray s's next chunk into a stage: [halo | chunk], the stage
+// starting on an aligned absolute AP.  Fills the call's numbering.
+int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, CallScan* c,
+                const float2** data) {
+  const ScanInfo& si = p->sz.scans[s];
+  StreamState& ss = p->streams[s];
+  const int64_t A = ss.consumed;
+  const int C = si.d.n_ap;
+  const int64_t origin = std::max<int64_t>(0, floor_to(A - (p->sz.w_max - 1), p->sz.align));
+  const int halo = int(A - origin);
+  const int nxt = ss.cur ^ 1;
+  const size_t row = size_t(si.stage_len) * si.F * sizeof(float2);  // one baseline of a stage
+  const size_t ap_bytes = size_t(si.F) * sizeof(float2);
+  hipError_t he;
+  if (halo > 0) {
+    const float2* src = ss.stage[ss.cur] + (origin - ss.origin) * si.F;
+    he = hipMemcpy2DAsync(ss.stage[nxt], row, src, row, halo * ap_bytes, si.d.n_baselines,
+                          hipMemcpyDeviceToDevice, st);
+    if (he != hipSuccess) return hip_fail(he, "stream halo copy");
+  }
+  he = hipMemcpy2DAsync(ss.stage[nxt] + size_t(halo) * si.F, row, chunk, C * ap_bytes,
+                        C * ap_bytes, si.d.n_baselines, hipMemcpyDeviceToDevice, st);
+  if (he != hipSuccess) return hip_fail(he, "stream chunk copy");
+  ss.cur = nxt;
+  ss.origin = origin;
+  ss.len = halo + C;
+  ss.consumed = A + C;
+  c->T = halo + C;
+  c->t_emit = halo;
+  c->t_origin = origin;
+  enumerate(c, p->sz.lv);
+  *data = ss.stage[nxt];
   return FRINGE_OK;
 }
 
@@ -361,6 +494,7 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
     return hip_fail(he, "hipGetDevice");
   }
   const Sizing& z = p->sz;
+  const int ns = int(z.scans.size());
   if ((rc = dev_alloc(&p->X, z.scratch_x, "delay spectra")) ||
       (rc = dev_alloc(&p->e, z.scratch_e, "AP energies")) ||
       (rc = dev_alloc(&p->part, z.scratch_part, "bin-block peaks")) ||
@@ -369,10 +503,30 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
       (rc = dev_alloc(&p->blk_offsets, uint64_t(z.n_blocks) * sizeof(int64_t), "block offsets")) ||
       (rc = dev_alloc(&p->cands, z.cand_bytes, "candidates")) ||
       (rc = dev_alloc(&p->d_total, sizeof(int64_t), "candidate count")) ||
-      (rc = dev_alloc(&p->d_scans, z.scans.size() * sizeof(ScanDev), "scan table")) ||
+      (rc = dev_alloc(&p->d_scans, ns * sizeof(ScanDev), "scan table")) ||
       (rc = dev_alloc(&p->grid, z.grid_bytes, "grid dump"))) {
     release(p);
     return rc;
+  }
+  if (z.streaming) {
+    p->streams.resize(ns);
+    for (int s = 0; s < ns; ++s) {
+      const ScanInfo& si = z.scans[s];
+      const uint64_t bytes = uint64_t(si.d.n_baselines) * si.stage_len * si.F * sizeof(float2);
+      for (int k = 0; k < 2; ++k)
+        if ((rc = dev_alloc(&p->streams[s].stage[k], bytes, "stream stage"))) {
+          release(p);
+          return rc;
+        }
+    }
+    for (int k = 0; k < 2; ++k) {
+      if ((he = hipHostMalloc(reinterpret_cast<void**>(&p->h_scans[k]), ns * sizeof(ScanDev),
+                              hipHostMallocDefault)) != hipSuccess ||
+          (he = hipEventCreateWithFlags(&p->h_scans_free[k], hipEventDisableTiming)) != hipSuccess) {
+        release(p);
+        return hip_fail(he, "stream scan-table staging");
+      }
+    }
   }
   // twiddle tables exp(-2 pi i k / M), rounded from double
   for (auto& si : z.scans) {
@@ -392,26 +546,14 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
       return hip_fail(he, "hipMemcpy(twiddles)");
     }
   }
-  std::vector<ScanDev> sd(z.scans.size());
-  for (size_t s = 0; s < z.scans.size(); ++s) {
-    const ScanInfo& si = z.scans[s];
-    ScanDev d{};
-    d.win_off = si.win_off;
-    d.nb = si.d.n_baselines;
-    d.T = si.d.n_ap;
-    d.M_f = si.M;
-    d.log_mf = si.log_m;
-    d.nwb = int32_t(si.nwb);
-    d.pad_t = si.pad_t;
-    d.df = si.d.chan_width_hz;
-    d.tap = si.d.ap_seconds;
-    for (int l = 0; l <= kMaxLevels; ++l) d.lvl_off[l] = int32_t(si.lvl_off[l]);
-    sd[s] = d;
-  }
-  he = hipMemcpy(p->d_scans, sd.data(), sd.size() * sizeof(ScanDev), hipMemcpyHostToDevice);
-  if (he != hipSuccess) {
-    release(p);
-    return hip_fail(he, "hipMemcpy(scan table)");
+  if (!z.streaming) {  // the batch numbering never changes
+    std::vector<ScanDev> sd(ns);
+    for (int s = 0; s < ns; ++s) sd[s] = make_scan_dev(z.scans[s], z.scans[s].full);
+    he = hipMemcpy(p->d_scans, sd.data(), sd.size() * sizeof(ScanDev), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      release(p);
+      return hip_fail(he, "hipMemcpy(scan table)");
+    }
   }
   if ((he = hipHostMalloc(reinterpret_cast<void**>(&p->h_total), sizeof(int64_t), hipHostMallocDefault)) !=
           hipSuccess ||
@@ -428,8 +570,10 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   if (!d_vis) return fail(FRINGE_E_INVALID, "null visibility pointer array");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const Sizing& z = p->sz;
-  for (size_t s = 0; s < z.scans.size(); ++s)
-    if (!d_vis[s]) return fail(FRINGE_E_INVALID, "scan %zu: null visibility pointer", s);
+  const int ns = int(z.scans.size());
+  if (!z.streaming)
+    for (int s = 0; s < ns; ++s)
+      if (!d_vis[s]) return fail(FRINGE_E_INVALID, "scan %d: null visibility pointer", s);
   hipError_t he;
   p->prof_used = 0;
 #define FRINGE_TIMED(kind, call, what)                                        \
@@ -438,73 +582,151 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     if ((he = (call)) != hipSuccess) return hip_fail(he, what);               \
     if ((he = prof_end(p, st)) != hipSuccess) return hip_fail(he, "profiling event"); \
   } while (0)
-  for (size_t s = 0; s < z.scans.size(); ++s) {
+
+  // numbering of this call's windows and the data each scan's kernels read
+  p->call.assign(ns, CallScan{});
+  p->call_present.assign(ns, 0);
+  std::vector<const float2*> data(ns, nullptr);
+  int64_t win_off = 0;
+  for (int s = 0; s < ns; ++s) {
+    CallScan& c = p->call[s];
+    if (!d_vis[s]) {  // no chunk: an empty id range at the running offset
+      c.win_off = win_off;
+      continue;
+    }
+    if (z.streaming) {
+      const int rc = stage_chunk(p, s, reinterpret_cast<const float2*>(d_vis[s]), st, &c, &data[s]);
+      if (rc != FRINGE_OK) return rc;
+    } else {
+      c = z.scans[s].full;
+      data[s] = reinterpret_cast<const float2*>(d_vis[s]);
+    }
+    c.win_off = win_off;
+    win_off += c.nwb * z.scans[s].d.n_baselines;
+    p->call_present[s] = 1;
+  }
+  p->call_windows = win_off;
+  if (z.streaming) {  // this call's scan table, through a pinned double buffer
+    const int k = p->h_scans_cur;
+    if ((he = hipEventSynchronize(p->h_scans_free[k])) != hipSuccess)
+      return hip_fail(he, "scan-table staging");
+    for (int s = 0; s < ns; ++s) p->h_scans[k][s] = make_scan_dev(z.scans[s], p->call[s]);
+    if ((he = hipMemcpyAsync(p->d_scans, p->h_scans[k], ns * sizeof(ScanDev),
+                             hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (he = hipEventRecord(p->h_scans_free[k], st)) != hipSuccess)
+      return hip_fail(he, "scan-table upload");
+    p->h_scans_cur ^= 1;
+  }
+
+  for (int s = 0; s < ns; ++s) {
+    if (!p->call_present[s]) continue;
     const ScanInfo& si = z.scans[s];
-    const float2* vis = reinterpret_cast<const float2*>(d_vis[s]);
+    const CallScan& c = p->call[s];
+    const int n_chunks = (c.T + si.chunk - 1) / si.chunk;
     for (int b0 = 0; b0 < si.d.n_baselines; b0 += si.slab_nb) {
       const int nb = std::min(si.slab_nb, si.d.n_baselines - b0);
-      DelayArgs da{};
-      da.vis = vis + int64_t(b0) * si.d.n_ap * si.F;
-      da.X = p->X;
-      da.e = p->e;
-      da.tw = p->tw[si.log_m];
-      da.nb = nb;
-      da.T = si.d.n_ap;
-      da.F = si.F;
-      da.M = si.M;
-      da.log_m = si.log_m;
-      da.pad_f = p->params.pad_freq;
-      FRINGE_TIMED(0, launch_delay_fft(da, st), "delay transform launch");
+      const int64_t slab_windows = int64_t(nb) * c.nwb;
+      if (slab_windows == 0) continue;
+      const float2* vis = data[s] + int64_t(b0) * (z.streaming ? si.stage_len : c.T) * si.F;
+      if (z.fused) {
+        FusedArgs fu{};
+        fu.vis = vis;
+        fu.vis_stride = int64_t(z.streaming ? si.stage_len : c.T) * si.F;
+        fu.part = p->part;
+        fu.e = p->e;
+        fu.dump = p->grid;
+        fu.tw = p->tw[si.log_m];
+        fu.slab_windows = slab_windows;
+        fu.dump_base = si.grid_off + int64_t(b0) * si.grid_per_bl;
+        fu.grid_per_bl = si.grid_per_bl;
+        for (int l = 0; l < kMaxLevels; ++l) fu.lvl_goff[l] = si.lvl_goff[l];
+        fu.nb = nb;
+        fu.T = c.T;
+        fu.F = si.F;
+        fu.M = si.M;
+        fu.R = si.n_kb;
+        fu.hf = (si.F + kBinsPerWave - 1) / kBinsPerWave;
+        fu.chunk = si.chunk;
+        fu.n_chunks = n_chunks;
+        fu.n_pairs = nb * n_chunks;
+        fu.nwb = int(c.nwb);
+        fu.t_emit = c.t_emit;
+        for (int l = 0; l <= kMaxLevels; ++l) fu.lvl_off[l] = int(c.lvl_off[l]);
+        for (int l = 0; l < kMaxLevels; ++l) fu.lvl_j0[l] = c.lvl_j0[l];
+        for (int L = 0; L < 8; ++L) fu.lvl_of_log[L] = -1;
+        for (int l = 0; l < z.lv.n; ++l) fu.lvl_of_log[z.lv.logW[l]] = l;
+        FRINGE_TIMED(1, launch_fused(fu, si.pad_t, z.w_max, p->grid != nullptr, st),
+                     "fused search launch");
+      } else {
+        DelayArgs da{};
+        da.vis = vis;
+        da.vis_stride = int64_t(z.streaming ? si.stage_len : c.T) * si.F;
+        da.X = p->X;
+        da.e = p->e;
+        da.tw = p->tw[si.log_m];
+        da.nb = nb;
+        da.T = c.T;
+        da.F = si.F;
+        da.M = si.M;
+        da.log_m = si.log_m;
+        da.pad_f = p->params.pad_freq;
+        FRINGE_TIMED(0, launch_delay_fft(da, st), "delay transform launch");
 
-      RateArgs ra{};
-      ra.X = p->X;
-      ra.part = p->part;
-      ra.dump = p->grid;
-      ra.slab_windows = int64_t(nb) * si.nwb;
-      ra.dump_base = si.grid_off + int64_t(b0) * si.grid_per_bl;
-      ra.grid_per_bl = si.grid_per_bl;
-      for (int l = 0; l < kMaxLevels; ++l) ra.lvl_goff[l] = si.lvl_goff[l];
-      ra.nb = nb;
-      ra.T = si.d.n_ap;
-      ra.M = si.M;
-      ra.log_m = si.log_m;
-      ra.n_kb = si.n_kb;
-      ra.chunk = si.chunk;
-      ra.n_chunks = si.n_chunks;
-      ra.w_max = z.w_max;
-      ra.buf_slots = rate_buffer_slots(z.w_max);
-      ra.pad_t = si.pad_t;
-      ra.nwb = int(si.nwb);
-      for (int l = 0; l <= kMaxLevels; ++l) ra.lvl_off[l] = int(si.lvl_off[l]);
-      ra.lv = z.lv;
-      FRINGE_TIMED(1, launch_rate_peak(ra, st), "rate transform launch");
+        RateArgs ra{};
+        ra.X = p->X;
+        ra.part = p->part;
+        ra.dump = p->grid;
+        ra.slab_windows = slab_windows;
+        ra.dump_base = si.grid_off + int64_t(b0) * si.grid_per_bl;
+        ra.grid_per_bl = si.grid_per_bl;
+        for (int l = 0; l < kMaxLevels; ++l) ra.lvl_goff[l] = si.lvl_goff[l];
+        ra.nb = nb;
+        ra.T = c.T;
+        ra.M = si.M;
+        ra.log_m = si.log_m;
+        ra.n_kb = si.n_kb;
+        ra.chunk = si.chunk;
+        ra.n_chunks = n_chunks;
+        ra.w_max = z.w_max;
+        ra.buf_slots = rate_buffer_slots(z.w_max);
+        ra.pad_t = si.pad_t;
+        ra.nwb = int(c.nwb);
+        ra.t_emit = c.t_emit;
+        for (int l = 0; l <= kMaxLevels; ++l) ra.lvl_off[l] = int(c.lvl_off[l]);
+        for (int l = 0; l < kMaxLevels; ++l) ra.lvl_j0[l] = c.lvl_j0[l];
+        ra.lv = z.lv;
+        FRINGE_TIMED(1, launch_rate_peak(ra, st), "rate transform launch");
+      }
 
       FinalizeArgs fa{};
       fa.part = p->part;
       fa.e = p->e;
-      fa.table = p->table + si.win_off + int64_t(b0) * si.nwb;
-      fa.slab_windows = ra.slab_windows;
+      fa.table = p->table + c.win_off + int64_t(b0) * c.nwb;
+      fa.slab_windows = slab_windows;
       fa.n_kb = si.n_kb;
       fa.nb = nb;
-      fa.T = si.d.n_ap;
-      fa.nwb = int(si.nwb);
-      for (int l = 0; l <= kMaxLevels; ++l) fa.lvl_off[l] = int(si.lvl_off[l]);
+      fa.T = c.T;
+      fa.nwb = int(c.nwb);
+      fa.pad_t = si.pad_t;
+      fa.M = si.M;
+      for (int l = 0; l <= kMaxLevels; ++l) fa.lvl_off[l] = int(c.lvl_off[l]);
+      for (int l = 0; l < kMaxLevels; ++l) fa.lvl_j0[l] = c.lvl_j0[l];
       fa.lv = z.lv;
       FRINGE_TIMED(2, launch_finalize(fa, st), "finalize launch");
     }
   }
   CompactArgs ca{};
   ca.table = p->table;
-  ca.n_windows = z.n_windows;
+  ca.n_windows = p->call_windows;
   ca.threshold = p->params.snr_threshold;
   ca.blk_counts = p->blk_counts;
   ca.blk_offsets = p->blk_offsets;
-  ca.n_blocks = z.n_blocks;
+  ca.n_blocks = (p->call_windows + kCompactBlock - 1) / kCompactBlock;
   ca.out = p->cands;
   ca.max_out = p->params.max_candidates;
   ca.total = p->d_total;
   ca.scans = p->d_scans;
-  ca.n_scans = int(z.scans.size());
+  ca.n_scans = ns;
   ca.lv = z.lv;
   FRINGE_TIMED(3, launch_compact(ca, st), "compaction launch");
 #undef FRINGE_TIMED
@@ -546,7 +768,7 @@ int fringe_windows_get(fringe_plan_t p, const int64_t* ids, int64_t n, fringe_ca
   if (n < 0 || (n > 0 && (!ids || !host_out))) return fail(FRINGE_E_INVALID, "bad id list");
   if (!p->searched) return fail(FRINGE_E_STATE, "fringe_windows_get before fringe_search");
   for (int64_t i = 0; i < n; ++i)
-    if (ids[i] < 0 || ids[i] >= p->sz.n_windows)
+    if (ids[i] < 0 || ids[i] >= p->call_windows)
       return fail(FRINGE_E_INVALID, "window id %lld out of range", (long long)ids[i]);
   if (n == 0) return FRINGE_OK;
   hipError_t he = hipEventSynchronize(p->done);
@@ -588,10 +810,20 @@ int fringe_window_id(fringe_plan_t p, int32_t scan, int32_t baseline, int32_t wi
   for (int l = 0; l < p->sz.lv.n; ++l)
     if (p->sz.lv.W[l] == window_ap) li = l;
   if (li < 0) return fail(FRINGE_E_INVALID, "window length %d not in the plan", window_ap);
+  // the batch numbering, or the last streaming call's
+  const CallScan* c = &si.full;
+  if (p->sz.streaming) {
+    if (!p->searched || !p->call_present[scan])
+      return fail(FRINGE_E_STATE, "scan %d had no chunk in the last search", scan);
+    c = &p->call[scan];
+  }
   const int s = p->sz.lv.s[li];
-  if (t_start < 0 || t_start % s != 0 || int64_t(t_start) + window_ap > si.d.n_ap)
+  const int64_t rel = int64_t(t_start) - c->t_origin;
+  const int64_t j = (rel >= 0 ? rel / s : -1) - c->lvl_j0[li];
+  const int64_t n_l = c->lvl_off[li + 1] - c->lvl_off[li];
+  if (rel < 0 || rel % s != 0 || j < 0 || j >= n_l)
     return fail(FRINGE_E_INVALID, "no window of length %d starts at %d", window_ap, t_start);
-  *id = si.win_off + int64_t(baseline) * si.nwb + si.lvl_off[li] + t_start / s;
+  *id = c->win_off + int64_t(baseline) * c->nwb + c->lvl_off[li] + j;
   return FRINGE_OK;
 }
 
@@ -643,7 +875,7 @@ int fringe_profile_get(fringe_plan_t p, fringe_profile* out) {
 
 int fringe_plan_info(fringe_plan_t p, fringe_plan_summary* out) {
   if (!p || !out) return fail(FRINGE_E_INVALID, "null argument");
-  out->n_windows = p->sz.n_windows;
+  out->n_windows = p->sz.streaming ? p->call_windows : p->sz.n_windows;
   out->device_bytes = int64_t(p->sz.total);
   out->scratch_bytes = int64_t(p->sz.scratch_x + p->sz.scratch_e + p->sz.scratch_part);
   out->max_window_ap = p->sz.w_max;

@@ -1,0 +1,204 @@
+// Fused fringe search for window lengths up to 32 APs: delay transform,
+// rate transform and grid peak in one pass over the visibilities.
+//
+// Work item = (baseline b, time chunk, residue class c of the delay bins):
+// the wave owns the 64 bins k_f = R m + c (R = M / 64), lane m holding bin
+// R m + c.  Per AP t (paper, section "Code optimization", step 5):
+//   z[f'] = w_M^{c f'} sum_h x_t[f' + 64 h] w_R^{c h}      (f' < 64)
+//   X_t[R m + c] = sum_{f'} z[f'] w_64^{m f'}
+// lane l folds f' = bitrev6(l), then six radix-2 decimation-in-time stages
+// across the wave (DPP, ds_swizzle and permlane swaps, no LDS) leave X_t of
+// lane m's bin in lane m.  Each lane keeps the last W_max APs of its bin's
+// spectrum in registers: the APs come in periods of P = W_max / 2 that are
+// unrolled, so every window that ends in a period has compile-time register
+// positions; after the period the newer half moves down.  Every window that
+// ends at the AP is searched at once (window_key: rate transform + peak
+// key) and reduced over the 64 bins with DPP (wave_peak); one lane stores
+// the class's partial peak.  Waves of class 0 also store the AP energies.
+//
+// Block g runs on XCD g mod 8; the R classes of one (baseline, chunk) are
+// given the same XCD and consecutive slots, so the chunk's visibilities are
+// fetched from HBM once and served to the other classes from that XCD's L2.
+#pragma once
+
+#include "kernels.h"
+#include "window_key.h"
+
+namespace fringe {
+
+namespace fused {
+
+// Partner exchange across lanes lane ^ D (D <= 8) on one float.
+template <int D>
+__device__ __forceinline__ float xchg(float v) {
+  if constexpr (D == 1) return dpp_f32<kDppXor1>(v);
+  else if constexpr (D == 2) return dpp_f32<kDppXor2>(v);
+  else if constexpr (D == 4)
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+  else return dpp_f32<kDppRor8>(v);
+}
+
+// One DIT stage of half-span D.  Lanes with bit D set ("b" lanes) first
+// multiply their value by w (w = 1 on "a" lanes); then a' = a + w b and
+// b' = a - w b, i.e. new = s * own + partner with s = +1 on a lanes, -1 on
+// b lanes (for D <= 8), or new = a + s * b with the two halves a, b that a
+// permlane swap delivers (D = 16, 32).
+template <int D>
+__device__ __forceinline__ float2 dit_stage(float2 v, float2 w, float s) {
+  const float2 t = (D == 1) ? v : c_mul(v, w);
+  if constexpr (D <= 8) {
+    const float px = xchg<D>(t.x), py = xchg<D>(t.y);
+    return make_float2(fmaf(s, t.x, px), fmaf(s, t.y, py));
+  } else {
+    int ax, bx, ay, by;
+    if constexpr (D == 16) {
+      const auto rx = __builtin_amdgcn_permlane16_swap(__float_as_int(t.x), __float_as_int(t.x), false, false);
+      const auto ry = __builtin_amdgcn_permlane16_swap(__float_as_int(t.y), __float_as_int(t.y), false, false);
+      ax = rx[0]; bx = rx[1]; ay = ry[0]; by = ry[1];
+    } else {
+      const auto rx = __builtin_amdgcn_permlane32_swap(__float_as_int(t.x), __float_as_int(t.x), false, false);
+      const auto ry = __builtin_amdgcn_permlane32_swap(__float_as_int(t.y), __float_as_int(t.y), false, false);
+      ax = rx[0]; bx = rx[1]; ay = ry[0]; by = ry[1];
+    }
+    return make_float2(fmaf(s, __int_as_float(bx), __int_as_float(ax)),
+                       fmaf(s, __int_as_float(by), __int_as_float(ay)));
+  }
+}
+
+struct LaneConsts {
+  float2 w[6];   // stage twiddles (index log2 D)
+  float s[6];    // stage signs
+  float2 wfold;  // w_M^{c f'} of this lane's f'
+};
+
+__device__ __forceinline__ float2 xlane_dit(float2 v, const LaneConsts& k) {
+  v = dit_stage<1>(v, k.w[0], k.s[0]);
+  v = dit_stage<2>(v, k.w[1], k.s[1]);
+  v = dit_stage<4>(v, k.w[2], k.s[2]);
+  v = dit_stage<8>(v, k.w[3], k.s[3]);
+  v = dit_stage<16>(v, k.w[4], k.s[4]);
+  v = dit_stage<32>(v, k.w[5], k.s[5]);
+  return v;
+}
+
+}  // namespace fused
+
+template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
+__global__ void __launch_bounds__(64) fused_search_kernel(FusedArgs a) {
+  constexpr int WMAX = 1 << LOGWMAX;
+  constexpr int P = WMAX / 2;          // APs per unrolled period
+  constexpr int HS = 2 * P;            // history registers (complex)
+  constexpr int PD = HFMAX <= 4 ? 4 : 1;  // prefetch depth in APs
+  static_assert(P % PD == 0 && P >= 4, "period");
+
+  const int lane = threadIdx.x;
+  const int g = blockIdx.x;
+  const int cls = (g >> 3) % a.R;
+  const int q = ((g >> 3) / a.R) * 8 + (g & 7);
+  if (q >= a.n_pairs) return;
+  const int b = q / a.n_chunks;
+  const int chunk = q - b * a.n_chunks;
+  const int T = a.T, F = a.F, M = a.M, hf = a.hf;
+  const int own_lo = chunk * a.chunk;
+  const int own_hi = min(T, own_lo + a.chunk);
+  const int t_end = min(T, own_hi + WMAX - 1);
+
+  // lane constants
+  const int fl = static_cast<int>(__builtin_bitreverse32(static_cast<uint32_t>(lane)) >> 26);
+  fused::LaneConsts kc;
+  kc.wfold = a.tw[(cls * fl) & (M - 1)];
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int d = 1 << st;
+    const bool bl = (lane & d) != 0;
+    kc.s[st] = bl ? -1.f : 1.f;
+    kc.w[st] = bl ? a.tw[(lane & (d - 1)) * (M / (2 * d))] : make_float2(1.f, 0.f);
+  }
+  float2 wh[HFMAX];  // fold twiddles w_R^{c h} (uniform)
+#pragma unroll
+  for (int h = 0; h < HFMAX; ++h) wh[h] = a.tw[((cls * h) * 64) & (M - 1)];
+
+  const float2* __restrict__ xb = a.vis + static_cast<int64_t>(b) * a.vis_stride;
+  auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
+#pragma unroll
+    for (int h = 0; h < HFMAX; ++h) {
+      const int f = fl + 64 * h;
+      float2 v = make_float2(0.f, 0.f);
+      if (h < hf && t < T && f < F) v = xb[static_cast<int64_t>(t) * F + f];
+      dst[h] = v;
+    }
+  };
+
+  float2 pre[PD][HFMAX];
+  static_for<0, PD>([&](auto di) {
+    constexpr int d = decltype(di)::value;
+    load_ap(own_lo + d, pre[d]);
+  });
+  float2 hist[HS];
+#pragma unroll
+  for (int k = 0; k < HS; ++k) hist[k] = make_float2(0.f, 0.f);
+
+  float* __restrict__ eb = a.e + static_cast<int64_t>(b) * T;
+  const int64_t part_base = static_cast<int64_t>(cls) * a.slab_windows + static_cast<int64_t>(b) * a.nwb;
+
+  for (int p0 = own_lo; p0 < t_end; p0 += P) {
+    static_for<0, P>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      constexpr int fs = i % PD;
+      const int t = p0 + i;
+      // delay transform of AP t for this class: fold, then across the wave
+      float2 z = pre[fs][0];
+      float es = c_norm(pre[fs][0]);
+#pragma unroll
+      for (int h = 1; h < HFMAX; ++h) {
+        z = c_add(z, c_mul(pre[fs][h], wh[h]));
+        es += c_norm(pre[fs][h]);
+      }
+      load_ap(t + PD, pre[fs]);
+      if (cls == 0) {
+        const float e = wave_sum_dpp(es);
+        if (lane == 0 && t < own_hi) eb[t] = e;
+      }
+      hist[P + i] = fused::xlane_dit(c_mul(z, kc.wfold), kc);
+
+      // every window that ends at AP t
+      static_for<0, LOGWMAX + 1>([&](auto li) {
+        constexpr int L = decltype(li)::value;
+        constexpr int W = 1 << L;
+        constexpr int s = W > 1 ? W / 2 : 1;
+        constexpr int base = P + i + 1 - W;  // register of the window's first AP
+        if constexpr (base >= 0 && ((i + 1 - W) % s + s) % s == 0) {
+          const int lvl = a.lvl_of_log[L];
+          const int start = t + 1 - W;
+          if (lvl >= 0 && start >= own_lo && start < own_hi && t < T && t >= a.t_emit) {
+            float2* dump = nullptr;
+            const int j = start / s;
+            if constexpr (DUMP)
+              dump = a.dump + a.dump_base + static_cast<int64_t>(b) * a.grid_per_bl +
+                     a.lvl_goff[lvl] + static_cast<int64_t>(j - a.lvl_j0[lvl]) * (PT * W) * M +
+                     (cls + a.R * lane);
+            const uint32_t key = window_key<L, PT, DUMP>(
+                [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
+            const uint64_t pk = wave_peak(key, cls, a.R);
+            if (lane == 0) a.part[part_base + a.lvl_off[lvl] + (j - a.lvl_j0[lvl])] = pk;
+          }
+        }
+      });
+    });
+#pragma unroll
+    for (int k = 0; k < P; ++k) hist[k] = hist[P + k];
+  }
+}
+
+template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
+hipError_t launch_fused_t(const FusedArgs& a, hipStream_t st) {
+  if (a.n_pairs == 0) return hipSuccess;
+  const int64_t groups = (a.n_pairs + 7) / 8;
+  const int64_t blocks = groups * 8 * a.R;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP>),
+                     dim3(static_cast<unsigned>(blocks)), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace fringe

@@ -32,13 +32,16 @@ struct WindowRec {
 // Per-scan constants on the device (window numbering and units).
 struct ScanDev {
   int64_t win_off;                    // id of the scan's first window
+  int64_t t_origin;                   // absolute AP of the searched data's first AP
   int32_t nb, T, M_f, log_mf, nwb, pad_t;
   double df, tap;
   int32_t lvl_off[kMaxLevels + 1];    // per-baseline window offsets of each length
+  int32_t lvl_j0[kMaxLevels];         // start / stride of each length's first window
 };
 
 struct DelayArgs {
   const float2* vis;   // [nb][T][F] visibilities of the slab
+  int64_t vis_stride;  // elements between baselines of vis (>= T * F)
   float2* X;           // [nb][T][M] delay spectra (out)
   float* e;            // [nb][T] per-AP energy sum |x|^2 (out)
   const float2* tw;    // [M] exp(-2 pi i k / M)
@@ -55,8 +58,28 @@ struct RateArgs {
   int64_t lvl_goff[kMaxLevels];  // per-baseline grid offset of each length
   int nb, T, M, log_m, n_kb, chunk, n_chunks, w_max, buf_slots, pad_t;
   int nwb;
+  int t_emit;          // windows must end at or after this AP (streaming)
   int lvl_off[kMaxLevels + 1];
+  int lvl_j0[kMaxLevels];
   LevelTable lv;
+};
+
+struct FusedArgs {
+  const float2* vis;   // [nb][T][F] visibilities of the slab
+  int64_t vis_stride;  // elements between baselines of vis (>= T * F)
+  uint64_t* part;      // [R][slab_windows] per residue-class peak keys (out)
+  float* e;            // [nb][T] per-AP energies (out)
+  float2* dump;        // full grids (FRINGE_DUMP_GRID) or nullptr
+  const float2* tw;    // [M] exp(-2 pi i k / M)
+  int64_t slab_windows;
+  int64_t dump_base;
+  int64_t grid_per_bl;
+  int64_t lvl_goff[kMaxLevels];
+  int nb, T, F, M, R, hf, chunk, n_chunks, n_pairs, nwb;
+  int t_emit;          // windows must end at or after this AP (streaming)
+  int lvl_off[kMaxLevels + 1];
+  int lvl_j0[kMaxLevels];
+  int lvl_of_log[8];   // level index of the length 2^L, -1 if not searched
 };
 
 struct FinalizeArgs {
@@ -64,8 +87,9 @@ struct FinalizeArgs {
   const float* e;
   WindowRec* table;    // records of this slab's windows (already offset)
   int64_t slab_windows;
-  int n_kb, nb, T, nwb;
+  int n_kb, nb, T, nwb, pad_t, M;
   int lvl_off[kMaxLevels + 1];
+  int lvl_j0[kMaxLevels];
   LevelTable lv;
 };
 
@@ -88,6 +112,10 @@ constexpr int kCompactBlock = 1024;  // windows per compaction block
 
 hipError_t launch_delay_fft(const DelayArgs& a, hipStream_t st);
 hipError_t launch_rate_peak(const RateArgs& a, hipStream_t st);
+// Fused path for plans whose longest window is at most kFusedMaxWindow APs.
+constexpr int kFusedMaxWindow = 32;
+int fused_period(int w_max);
+hipError_t launch_fused(const FusedArgs& a, int pad_t, int w_max, bool dump, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
 hipError_t launch_gather(const WindowRec* table, const int64_t* ids, int64_t n,

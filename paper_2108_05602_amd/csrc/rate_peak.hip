@@ -14,92 +14,53 @@
 // last AP arrives in the batch is transformed in registers right away:
 //   k_t = S p + r,  G[S p + r] = FFT_N( y_r )[p],
 //   y_r[v] = w_{M_t}^{r v} sum_{h<H} x[v + N h] w_S^{r h},
-// with N = M_t / S <= 32 sub-transforms (S = max(pad_t, M_t / 32),
-// H = W / N), so a W = 128 window never needs more than 32 complex values
-// in flight.  The lane's best (P, k_t) goes through a 64-lane max of the
-// key (P bits, ~flat index) and one lane stores the bin-block's result.
-#include "dev_common.h"
+// with N = M_t / S <= 16 sub-transforms (S = max(pad_t, M_t / 16),
+// H = W / N), so a W = 128 window never needs more than 16 complex values
+// in flight.  The lane's rate key goes through a 64-lane DPP max and one
+// lane stores the bin-block's result (window_key.h).
+//
+// This kernel serves every plan; plans whose windows are at most 32 APs
+// long use the fused kernel (fused_search.h) instead, which also does the
+// delay transform and keeps the history in registers.
 #include "kernels.h"
+#include "window_key.h"
 
 namespace fringe {
 
 namespace {
 
-constexpr int kQ = 8;      // APs per load batch
-constexpr int kNmax = 32;  // largest register sub-transform
+constexpr int kQ = 8;  // APs per load batch
 
-template <int LOGW, int PT>
-struct WinShape {
-  static constexpr int W = 1 << LOGW;
-  static constexpr int MT = PT * W;
-  static constexpr int S = (MT / kNmax > PT) ? MT / kNmax : PT;
-  static constexpr int N = MT / S;
-  static constexpr int H = W / N;
-  static constexpr bool XREG = W <= 32;  // hold the window's samples in registers
-};
-
-template <int LOGW, int PT, bool DUMP>
-__device__ __forceinline__ void window_peak(const float2* __restrict__ col, float& best_p,
-                                            int& best_k, float2* __restrict__ dump, int m_f) {
-  using Sh = WinShape<LOGW, PT>;
-  constexpr int W = Sh::W, MT = Sh::MT, S = Sh::S, N = Sh::N, H = Sh::H;
-  float2 xr[Sh::XREG ? W : 1];
-  if constexpr (Sh::XREG) {
+// One window of one lane's bin: samples from the lane's LDS column (copied
+// to registers first for short windows), then the shared rate transform
+// and peak key.
+template <int L, int PT, bool DUMP>
+__device__ __forceinline__ uint32_t window_key_lds(const float2* __restrict__ col,
+                                                   float2* __restrict__ dump, int m_f) {
+  constexpr int W = 1 << L;
+  if constexpr (W <= 32) {
+    float2 xr[W];
     static_for<0, W>([&](auto ui) {
       constexpr int u = decltype(ui)::value;
       xr[u] = col[u * kBinsPerWave];
     });
+    return window_key<L, PT, DUMP>([&](auto ui) { return xr[decltype(ui)::value]; }, dump, m_f);
+  } else {
+    return window_key<L, PT, DUMP>(
+        [&](auto ui) { return col[decltype(ui)::value * kBinsPerWave]; }, dump, m_f);
   }
-  best_p = -1.f;
-  best_k = 0;
-  static_for<0, S>([&](auto ri) {
-    constexpr int r = decltype(ri)::value;
-    float2 y[N];
-    static_for<0, N>([&](auto vi) {
-      constexpr int v = decltype(vi)::value;
-      float2 acc;
-      if constexpr (Sh::XREG) acc = xr[v]; else acc = col[v * kBinsPerWave];
-      static_for<1, H>([&](auto hi) {
-        constexpr int h = decltype(hi)::value;
-        float2 xv;
-        if constexpr (Sh::XREG) xv = xr[v + N * h]; else xv = col[(v + N * h) * kBinsPerWave];
-        acc = c_add(acc, twiddle_mul<S, r * h>(xv));
-      });
-      y[v] = twiddle_mul<MT, r * v>(acc);
-    });
-    fft_dif<N>(y);
-    float bp = -1.f;
-    int bk = 0;
-    static_for<0, N>([&](auto pi) {
-      constexpr int p = decltype(pi)::value;
-      const float2 val = y[bitrev(p, ilog2(N))];
-      const float pw = c_norm(val);
-      if (pw > bp) {
-        bp = pw;
-        bk = S * p + r;
-      }
-      if constexpr (DUMP) dump[static_cast<int64_t>(S * p + r) * m_f] = val;
-    });
-    if (r == 0 || bp > best_p || (bp == best_p && bk < best_k)) {
-      best_p = bp;
-      best_k = bk;
-    }
-  });
 }
 
 // Only the lengths up to 2^LOGWMAX are compiled into a kernel, so a plan
 // with short windows does not pay the registers of the long ones.
 template <int PT, bool DUMP, int LOGWMAX, int L = 0>
-__device__ __forceinline__ void window_peak_dispatch(int logw, const float2* col, float& bp,
-                                                     int& bk, float2* dump, int m_f) {
+__device__ __forceinline__ uint32_t window_key_dispatch(int logw, const float2* col,
+                                                        float2* dump, int m_f) {
   if constexpr (L < LOGWMAX) {
-    if (logw == L) {
-      window_peak<L, PT, DUMP>(col, bp, bk, dump, m_f);
-      return;
-    }
-    window_peak_dispatch<PT, DUMP, LOGWMAX, L + 1>(logw, col, bp, bk, dump, m_f);
+    if (logw == L) return window_key_lds<L, PT, DUMP>(col, dump, m_f);
+    return window_key_dispatch<PT, DUMP, LOGWMAX, L + 1>(logw, col, dump, m_f);
   } else {
-    window_peak<LOGWMAX, PT, DUMP>(col, bp, bk, dump, m_f);
+    return window_key_lds<LOGWMAX, PT, DUMP>(col, dump, m_f);
   }
 }
 
@@ -149,7 +110,7 @@ __global__ void __launch_bounds__(64) rate_peak_kernel(RateArgs a) {
     for (int li = 0; li < a.lv.n; ++li) {
       const int W = a.lv.W[li];
       const int s = a.lv.s[li];
-      const int lo = max(tb - W + 1, own_lo);
+      const int lo = max(max(tb, a.t_emit) - W + 1, own_lo);
       const int hi = min(min(tb + nq - W, own_hi - 1), T - W);
       if (lo > hi) continue;
       for (int start = ((lo + s - 1) / s) * s; start <= hi; start += s) {
@@ -157,16 +118,13 @@ __global__ void __launch_bounds__(64) rate_peak_kernel(RateArgs a) {
         float2* dump = nullptr;
         if constexpr (DUMP)
           dump = a.dump + a.dump_base + static_cast<int64_t>(b) * a.grid_per_bl + a.lvl_goff[li] +
-                 static_cast<int64_t>(j) * (PT * W) * M + kf;
-        float bp;
-        int bk;
-        window_peak_dispatch<PT, DUMP, LOGWMAX>(a.lv.logW[li], mycol + (start - tbuf0) * kBinsPerWave, bp,
-                                       bk, dump, M);
-        const uint32_t flat = static_cast<uint32_t>(bk) * static_cast<uint32_t>(M) + kf;
-        const uint64_t key = wave_max_u64(peak_key(bp, flat));
+                 static_cast<int64_t>(j - a.lvl_j0[li]) * (PT * W) * M + kf;
+        const uint32_t key = window_key_dispatch<PT, DUMP, LOGWMAX>(
+            a.lv.logW[li], mycol + (start - tbuf0) * kBinsPerWave, dump, M);
+        const uint64_t pk = wave_peak(key, kb * kBinsPerWave, 1);
         if (lane == 0)
           a.part[static_cast<int64_t>(kb) * a.slab_windows + static_cast<int64_t>(b) * a.nwb +
-                 a.lvl_off[li] + j] = key;
+                 a.lvl_off[li] + (j - a.lvl_j0[li])] = pk;
       }
     }
     wp += nq;
@@ -195,10 +153,10 @@ hipError_t launch_t(const RateArgs& a, hipStream_t st) {
 
 int rate_buffer_slots(int w_max) { return w_max - 1 + 2 * kQ; }
 
+// Plans with windows of at most kFusedMaxWindow APs go to the fused kernel.
 template <int PT, bool DUMP>
 hipError_t launch_w(const RateArgs& a, hipStream_t st) {
-  if (a.w_max <= 8) return launch_t<PT, DUMP, 3>(a, st);
-  if (a.w_max <= 32) return launch_t<PT, DUMP, 5>(a, st);
+  if (a.w_max <= kFusedMaxWindow) return hipErrorInvalidValue;
   if (a.w_max <= 64) return launch_t<PT, DUMP, 6>(a, st);
   return launch_t<PT, DUMP, 7>(a, st);
 }

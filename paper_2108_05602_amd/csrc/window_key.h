@@ -1,0 +1,178 @@
+// Per-window rate transform and peak key, shared by the search kernels.
+//
+// For one lane's delay bin and one window of W APs x[0..W) it forms every
+// rate bin of the M_t = PT * W point zero-padded DFT,
+//   G[k_t] = sum_{u<W} x[u] exp(-2 pi i k_t u / M_t),
+// as S interleaved sub-transforms of N = M_t / S <= 16 points,
+//   G[S p + r] = FFT_N(y_r)[p],   y_r[v] = w_{M_t}^{r v} sum_{h<H} x[v + N h] w_S^{r h},
+// (H = W / N), and reduces |G[k_t]|^2 over k_t to one 32-bit key
+//   key = (bits(|G|^2) with the low log2(M_t) bits cleared) | (M_t - 1 - k_t).
+// Keys order like (power, then lower rate bin): powers within 2^-(23 -
+// log2 M_t) of each other (< 2e-5 relative) count as ties, which go to the
+// lower bin, and the power the key carries is exact to that relative size.
+// A window-wide peak over the 64 delay bins of a wave is then one unsigned
+// max plus the lowest lane holding it (lanes are in ascending k_f order).
+#pragma once
+
+#include "dev_common.h"
+
+namespace fringe {
+
+template <int LOGW, int PT>
+struct RateShape {
+  static constexpr int W = 1 << LOGW;
+  static constexpr int MT = PT * W;
+  static constexpr int NMAX = 16;
+  static constexpr int S = (MT / NMAX > PT) ? MT / NMAX : PT;
+  static constexpr int N = MT / S > 0 ? MT / S : 1;
+  static constexpr int H = W / N > 0 ? W / N : 1;
+  static constexpr uint32_t MASK = static_cast<uint32_t>(MT - 1);
+};
+
+__device__ __forceinline__ uint32_t rate_key(float p, uint32_t mask, uint32_t kt) {
+  return (__float_as_uint(p) & ~mask) | (mask - kt);
+}
+
+// exp(-2 pi i k / 256), k < 256, for the sub-transform loop of long windows
+// (every M_t <= 256 and S <= 16 divides 256).
+constexpr int kTwN = 256;
+struct TwTable {
+  float2 v[kTwN];
+  constexpr TwTable() : v() {
+    for (int k = 0; k < kTwN; ++k) {
+      const CxD w = unit_root(k, kTwN);
+      v[k] = float2{float(w.re), float(w.im)};
+    }
+  }
+};
+static __constant__ TwTable kTw256{};
+
+// X(u) returns the window's u-th sample (compile-time u).  DUMP writes each
+// G[k_t] to dump[k_t * dump_stride].
+template <int LOGW, int PT, bool DUMP, typename XF>
+__device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump,
+                                               int dump_stride) {
+  using Sh = RateShape<LOGW, PT>;
+  constexpr int MT = Sh::MT, S = Sh::S, N = Sh::N, H = Sh::H;
+  constexpr uint32_t MASK = Sh::MASK;
+  if constexpr (Sh::W == 1) {
+    // one AP: every rate bin equals x[0]; the lowest bin wins the tie
+    const float2 x0 = X(std::integral_constant<int, 0>{});
+    if constexpr (DUMP) {
+      static_for<0, MT>([&](auto ki) {
+        dump[static_cast<int64_t>(decltype(ki)::value) * dump_stride] = x0;
+      });
+    }
+    return rate_key(c_norm(x0), MASK, 0);
+  } else if constexpr (S > 4) {
+    // long windows: the sub-transform index r runs at run time, its
+    // twiddles w_S^{r h} and w_{M_t}^{r v} come from the uniform table
+    uint32_t key = 0;
+    for (int r = 0; r < S; ++r) {
+      float2 y[N];
+      static_for<0, N>([&](auto vi) {
+        constexpr int v = decltype(vi)::value;
+        float2 acc = X(std::integral_constant<int, v>{});
+        static_for<1, H>([&](auto hi) {
+          constexpr int h = decltype(hi)::value;
+          const float2 w = kTw256.v[((r * h) * (kTwN / S)) & (kTwN - 1)];
+          acc = c_add(acc, c_mul(X(std::integral_constant<int, v + N * h>{}), w));
+        });
+        if constexpr (v == 0) y[v] = acc;
+        else y[v] = c_mul(acc, kTw256.v[((r * v) * (kTwN / MT)) & (kTwN - 1)]);
+      });
+      fft_dif<N>(y);
+      static_for<0, N>([&](auto pi) {
+        constexpr int p = decltype(pi)::value;
+        const uint32_t kt = static_cast<uint32_t>(S * p + r);
+        const float2 val = y[bitrev(p, ilog2(N))];
+        const uint32_t k = rate_key(c_norm(val), MASK, kt);
+        key = k > key ? k : key;
+        if constexpr (DUMP) dump[static_cast<int64_t>(kt) * dump_stride] = val;
+      });
+    }
+    return key;
+  } else {
+    uint32_t key = 0;
+    static_for<0, S>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      float2 y[N];
+      static_for<0, N>([&](auto vi) {
+        constexpr int v = decltype(vi)::value;
+        float2 acc = X(std::integral_constant<int, v>{});
+        static_for<1, H>([&](auto hi) {
+          constexpr int h = decltype(hi)::value;
+          acc = c_add(acc, twiddle_mul<S, r * h>(X(std::integral_constant<int, v + N * h>{})));
+        });
+        y[v] = twiddle_mul<MT, r * v>(acc);
+      });
+      fft_dif<N>(y);
+      static_for<0, N>([&](auto pi) {
+        constexpr int p = decltype(pi)::value;
+        constexpr uint32_t kt = static_cast<uint32_t>(S * p + r);
+        const float2 val = y[bitrev(p, ilog2(N))];
+        const uint32_t k = rate_key(c_norm(val), MASK, kt);
+        key = k > key ? k : key;
+        if constexpr (DUMP) dump[static_cast<int64_t>(kt) * dump_stride] = val;
+      });
+    });
+    return key;
+  }
+}
+
+// ------------------------------------------------------ DPP reductions --
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within 8
+constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within 16
+constexpr int kDppRor8 = 0x128;        // lane i <- (i + 8) mod 16 within 16
+
+// Max of v over the 64 lanes (uniform result).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, dpp_u32<kDppXor1>(v));
+  v = max(v, dpp_u32<kDppXor2>(v));
+  v = max(v, dpp_u32<kDppHalfMirror>(v));
+  v = max(v, dpp_u32<kDppMirror>(v));
+  const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+// Sum of v over the 64 lanes (uniform result).
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_f32<kDppXor1>(v);
+  v += dpp_f32<kDppXor2>(v);
+  v += dpp_f32<kDppHalfMirror>(v);
+  v += dpp_f32<kDppMirror>(v);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
+// Window key of a wave: the 64-lane max of the lanes' rate keys, and the
+// lowest lane holding it.  Returned as the bin-block partial
+//   (key << 32) | (0xFFFFFFFF - k_f)   with k_f = kf_base + kf_step * lane,
+// whose unsigned max over blocks is the window's peak (lowest flat index
+// among ties).
+__device__ __forceinline__ uint64_t wave_peak(uint32_t key, int kf_base, int kf_step) {
+  const uint32_t m = wave_max_u32(key);
+  const uint64_t holders = __ballot(key == m);
+  const int lane = __builtin_ctzll(holders);
+  const uint32_t kf = static_cast<uint32_t>(kf_base + kf_step * lane);
+  return (static_cast<uint64_t>(m) << 32) | (0xFFFFFFFFu - kf);
+}
+
+}  // namespace fringe

@@ -94,10 +94,18 @@ def test_validation_errors():
 
 def test_budget():
     s = F.fringe_plan_check([C2], C2_W, snr_threshold=4.5)
-    # a generous budget fits; the plan stays inside it
-    b = F.fringe_plan_check([C2], C2_W, snr_threshold=4.5, hbm_budget_bytes=4 << 30)
-    assert b["device_bytes"] <= 4 << 30
-    assert b["slab_baselines"] < s["slab_baselines"]
+    # a budget that does not hold every baseline's work buffers at once is
+    # met by processing the baselines in slabs
+    budget = 300 << 20
+    b = F.fringe_plan_check([C2], C2_W, snr_threshold=4.5, hbm_budget_bytes=budget)
+    assert b["device_bytes"] <= budget
+    assert 1 <= b["slab_baselines"] < s["slab_baselines"] == 45
+    # windows longer than 32 APs take the two-pass path, whose delay spectra
+    # (8 bytes per delay bin per AP) dominate the work buffers
+    c5 = dict(n_baselines=66, n_ap=117200, n_if=16, n_chan=64, ap_seconds=0.512e-3,
+              chan_width_hz=0.25e6)
+    s5 = F.fringe_plan_check([c5], [1, 2, 4, 8, 16, 32, 64, 128], snr_threshold=4.5)
+    assert s5["scratch_bytes"] >= s5["slab_baselines"] * 117200 * 4096 * 8
     # below the result buffers themselves: refused
     assert _code(lambda: F.fringe_plan_check([C2], C2_W, hbm_budget_bytes=1 << 20)) == B.FRINGE_E_NOMEM
 
