@@ -78,6 +78,35 @@ def cpu_baseline(spec, params, n_bl=8, n_ap=4096):
                       f"{len(params['window_aps'])} window lengths: {n} windows in {dt:.1f} s"}
 
 
+def plain_vs_batched(dev, spec, params, n_bl=3, n_ap=4096, reps=5):
+    """The one-window-per-launch path and the batched path on the same
+    subset of the resident scan (baselines 0..n_bl-1, APs 0..n_ap-1)."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    sub = dev[:n_bl, :n_ap].contiguous()
+    desc = dict(spec.desc(), n_baselines=n_bl, n_ap=n_ap)
+    st = torch.cuda.current_stream()
+    kw = dict(pad_freq=params["pad_freq"], pad_time=params["pad_time"],
+              snr_threshold=params["snr_threshold"], max_candidates=1 << 20)
+    out = {}
+    for name, flags, n in (("plain", F.FRINGE_PLAIN, 1), ("batched", 0, reps)):
+        with F.Plan([desc], params["window_aps"], flags=flags, **kw) as plan:
+            plan.search([sub.data_ptr()], st.cuda_stream)
+            plan.candidates()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                plan.search([sub.data_ptr()], st.cuda_stream)
+                plan.candidates()
+            dt = (time.perf_counter() - t0) / n
+            out[name] = plan.info()["n_windows"] / dt
+            out["windows"] = plan.info()["n_windows"]
+    out["speedup"] = out["batched"] / out["plain"]
+    out["subset"] = f"baselines 0-{n_bl - 1} x APs 0-{n_ap - 1} of the same scan"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +115,7 @@ def main():
     ap.add_argument("--stations", type=int, default=10, help="(smaller values: quick check only)")
     ap.add_argument("--n-ap", type=int, default=58600, help="(smaller values: quick check only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -143,10 +173,13 @@ def main():
     d_fl, r_fl, p_fl = algorithmic_flops(spec.n_baselines, spec.n_ap, spec.n_freq,
                                          params["window_aps"], params["pad_freq"],
                                          params["pad_time"])
-    # dominant kernel: rate transform + peak (all flops except the delay FFT)
+    # dominant kernel: the fused search kernel does the delay transform, rate
+    # transform and peak; on the two-pass path the rate kernel does the last two
+    fused = kern["delay_ms"] == 0.0
     launches = kern["rate_launches"]
     avg_launch_s = kern["rate_ms"] / max(1, launches) / 1e3
-    flops_per_launch = (r_fl + p_fl) * args.steps / max(1, launches)
+    kernel_flops = (d_fl if fused else 0.0) + r_fl + p_fl
+    flops_per_launch = kernel_flops * args.steps / max(1, launches)
     achieved = flops_per_launch / avg_launch_s / 1e12
     cube_bytes = spec.nbytes()
     out = {
@@ -172,7 +205,8 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "rate_peak_kernel (rate transform + |G|^2 peak)",
+            "kernel": ("fused_search_kernel (delay FFT + rate FFT + |G|^2 peak)" if fused
+                       else "rate_peak_kernel (rate FFT + |G|^2 peak)"),
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
@@ -188,6 +222,10 @@ def main():
         "kernel_ms_per_step": per_step,
         "candidates": int(len(cands)),
     }
+    if not args.no_plain:
+        log("timing the one-window-per-launch path against the batched path")
+        out["plain_vs_batched"] = plain_vs_batched(dev, spec, params)
+        log("plain vs batched: " + json.dumps(out["plain_vs_batched"]))
     if not args.no_cpu_baseline:
         log("timing the CPU reference on its sample")
         out["cpu_baseline"] = cpu_baseline(spec, params)

@@ -57,6 +57,8 @@ extern "C" {
 #define FRINGE_STREAMING  0x1u   /* each fringe_search call is the next chunk      */
 #define FRINGE_DUMP_GRID  0x2u   /* keep every window's full grid (tests; small)   */
 #define FRINGE_PROFILE    0x4u   /* time every kernel launch with HIP events       */
+#define FRINGE_PLAIN      0x8u   /* one window per launch (a baseline for timing;  */
+                                 /* batch plans with windows of at most 32 APs)    */
 
 /* One complex64 sample, identical in layout to torch.complex64 / numpy.complex64. */
 typedef struct { float re, im; } fringe_cf32;

@@ -16,9 +16,17 @@ namespace fringe {
 
 namespace {
 
-__global__ void __launch_bounds__(256) finalize_kernel(FinalizeArgs a) {
-  const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (w >= a.slab_windows) return;
+__global__ void __launch_bounds__(256) finalize_kernel(const FinalizeArgs* __restrict__ tab,
+                                                       int n_tab, int64_t n_windows) {
+  const int64_t wa = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (wa >= n_windows) return;
+  int e_lo = 0, e_hi = n_tab - 1;  // the entry owning window wa
+  while (e_lo < e_hi) {
+    const int mid = (e_lo + e_hi + 1) >> 1;
+    if (tab[mid].win_begin <= wa) e_lo = mid; else e_hi = mid - 1;
+  }
+  const FinalizeArgs& a = tab[e_lo];
+  const int64_t w = wa - a.win_begin;
   uint64_t key = 0;
   for (int kb = 0; kb < a.n_kb; ++kb) {
     const uint64_t k = a.part[static_cast<int64_t>(kb) * a.slab_windows + w];
@@ -188,10 +196,12 @@ __global__ void __launch_bounds__(256) gather_kernel(const WindowRec* table, con
 
 }  // namespace
 
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st) {
-  if (a.slab_windows == 0) return hipSuccess;
-  const int64_t blocks = (a.slab_windows + 255) / 256;
-  hipLaunchKernelGGL(finalize_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a);
+hipError_t launch_finalize(const FinalizeArgs* d_tab, int n_tab, int64_t n_windows,
+                           hipStream_t st) {
+  if (n_windows == 0 || n_tab == 0) return hipSuccess;
+  const int64_t blocks = (n_windows + 255) / 256;
+  hipLaunchKernelGGL(finalize_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                     d_tab, n_tab, n_windows);
   return hipGetLastError();
 }
 

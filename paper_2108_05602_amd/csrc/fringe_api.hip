@@ -97,8 +97,27 @@ struct ScanInfo {
   int chunk;                          // search-kernel time tiling
 };
 
+// A slab of baselines of one scan: one entry of a fused (or finalize)
+// launch, with its place in the work buffers.
+struct Unit {
+  int scan, b0, nb;
+  uint64_t e_off, part_off;           // element offsets in the energy / peak buffers
+};
+
+// Units [u0, u1) share one fused launch and one finalize launch.
+struct Group {
+  int u0, u1;
+};
+
+constexpr int64_t kMaxPlainWindows = int64_t(1) << 21;
+constexpr size_t kArenaAlign = 256;
+size_t align_up(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+
 struct Sizing {
   std::vector<ScanInfo> scans;
+  std::vector<Unit> units;
+  std::vector<Group> groups;
+  size_t arena_bytes = 0;             // per-call descriptor tables
   LevelTable lv;
   int w_max = 0;
   bool fused = false;                 // fused kernel (w_max <= kFusedMaxWindow)
@@ -126,10 +145,12 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   if (!p->window_aps) return fail(FRINGE_E_INVALID, "window_aps is null");
   if (p->n_window_lengths < 1 || p->n_window_lengths > kMaxLevels)
     return fail(FRINGE_E_INVALID, "n_window_lengths must be in [1, %d]", kMaxLevels);
-  if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE))
+  if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE | FRINGE_PLAIN))
     return fail(FRINGE_E_INVALID, "unknown flag bits 0x%x", p->flags);
   if ((p->flags & FRINGE_STREAMING) && (p->flags & FRINGE_DUMP_GRID))
     return fail(FRINGE_E_INVALID, "FRINGE_DUMP_GRID is for batch plans only");
+  if ((p->flags & FRINGE_PLAIN) && (p->flags & (FRINGE_STREAMING | FRINGE_DUMP_GRID)))
+    return fail(FRINGE_E_INVALID, "FRINGE_PLAIN is for batch plans without FRINGE_DUMP_GRID");
   if (!(p->snr_threshold >= 0.f) || !std::isfinite(p->snr_threshold))
     return fail(FRINGE_E_INVALID, "snr_threshold must be finite and >= 0");
   if (p->max_candidates < 0) return fail(FRINGE_E_INVALID, "max_candidates must be >= 0");
@@ -156,6 +177,8 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   for (int i = sz.lv.n; i < kMaxLevels; ++i) sz.lv.W[i] = sz.lv.logW[i] = sz.lv.s[i] = 0;
   sz.w_max = sz.lv.W[sz.lv.n - 1];
   sz.fused = sz.w_max <= kFusedMaxWindow;
+  if ((p->flags & FRINGE_PLAIN) && !sz.fused)
+    return fail(FRINGE_E_UNSUPPORTED, "FRINGE_PLAIN needs windows of at most %d APs", kFusedMaxWindow);
   // the kernels count window strides (and the fused kernel its period) from
   // AP 0 of the data they read, so streaming stages start on multiples
   sz.align = std::max(std::max(1, sz.w_max / 2), sz.fused ? fused_period(sz.w_max) : 1);
@@ -229,8 +252,11 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   for (int lm = 6; lm <= 12; ++lm)
     for (auto& si : sz.scans)
       if (si.log_m == lm) { tw_bytes += (uint64_t(1) << lm) * sizeof(float2); break; }
+  if ((p->flags & FRINGE_PLAIN) && sz.n_windows > kMaxPlainWindows)
+    return fail(FRINGE_E_UNSUPPORTED, "FRINGE_PLAIN is for at most %lld windows (timing subsets)",
+                (long long)kMaxPlainWindows);
   sz.fixed_bytes = sz.table_bytes + sz.blk_bytes + sz.cand_bytes + sz.grid_bytes + tw_bytes +
-                   sz.stage_bytes + uint64_t(n_scans) * sizeof(ScanDev) + 64;
+                   sz.stage_bytes + 64;
 
   // Work buffers: process each scan in slabs of baselines that fit.
   uint64_t cap = kDefaultScratchCap;
@@ -251,12 +277,39 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
       nb = 1;
     }
     si.slab_nb = int(std::min<int64_t>(nb, si.d.n_baselines));
-    const uint64_t t = uint64_t(data_len(si, sz.streaming));
-    if (!sz.fused) sz.scratch_x = std::max<uint64_t>(sz.scratch_x, uint64_t(si.slab_nb) * t * si.M * sizeof(float2));
-    sz.scratch_e = std::max<uint64_t>(sz.scratch_e, uint64_t(si.slab_nb) * t * sizeof(float));
-    sz.scratch_part = std::max<uint64_t>(sz.scratch_part, uint64_t(si.slab_nb) * si.nwb_max * si.n_kb * sizeof(uint64_t));
   }
-  sz.total = sz.fixed_bytes + sz.scratch_x + sz.scratch_e + sz.scratch_part;
+  // Units in scan and baseline order.  Fused plans pack consecutive units
+  // into groups whose work buffers fit the cap, so one launch serves many
+  // scans; two-pass plans give every unit a group of its own.
+  uint64_t g_e = 0, g_part = 0, max_e = 0, max_part = 0;
+  for (int s = 0; s < n_scans; ++s) {
+    const ScanInfo& si = sz.scans[s];
+    const uint64_t t = uint64_t(data_len(si, sz.streaming));
+    for (int b0 = 0; b0 < si.d.n_baselines; b0 += si.slab_nb) {
+      const int nb = std::min(si.slab_nb, si.d.n_baselines - b0);
+      const uint64_t e_u = uint64_t(nb) * t;
+      const uint64_t part_u = uint64_t(si.n_kb) * nb * si.nwb_max;
+      const bool open = !sz.groups.empty() && sz.groups.back().u1 == int(sz.units.size());
+      if (!sz.fused || !open || (g_e + e_u) * sizeof(float) + (g_part + part_u) * sizeof(uint64_t) > cap) {
+        sz.groups.push_back(Group{int(sz.units.size()), int(sz.units.size())});
+        g_e = g_part = 0;
+      }
+      sz.units.push_back(Unit{s, b0, nb, g_e, g_part});
+      sz.groups.back().u1 = int(sz.units.size());
+      g_e += e_u;
+      g_part += part_u;
+      max_e = std::max(max_e, g_e);
+      max_part = std::max(max_part, g_part);
+      if (!sz.fused)
+        sz.scratch_x = std::max<uint64_t>(sz.scratch_x, uint64_t(nb) * t * si.M * sizeof(float2));
+    }
+  }
+  sz.scratch_e = max_e * sizeof(float);
+  sz.scratch_part = max_part * sizeof(uint64_t);
+  const size_t entries = (p->flags & FRINGE_PLAIN) ? size_t(sz.n_windows) : sz.units.size();
+  sz.arena_bytes = align_up(size_t(n_scans) * sizeof(ScanDev)) +
+                   align_up(entries * sizeof(FusedArgs)) + align_up(entries * sizeof(FinalizeArgs));
+  sz.total = sz.fixed_bytes + sz.scratch_x + sz.scratch_e + sz.scratch_part + 2 * sz.arena_bytes;
   *out = std::move(sz);
   return FRINGE_OK;
 }
@@ -303,7 +356,7 @@ struct fringe_plan_s {
   int64_t* blk_offsets = nullptr;
   fringe_candidate* cands = nullptr;
   int64_t* d_total = nullptr;
-  ScanDev* d_scans = nullptr;
+  ScanDev* d_scans = nullptr;      // scan table of the last search (inside an arena)
   float2* grid = nullptr;
   float2* tw[13] = {};
   int64_t* h_total = nullptr;      // pinned
@@ -313,11 +366,18 @@ struct fringe_plan_s {
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool searched = false;
+  // per-call descriptor tables: built in host memory, staged through one of
+  // two pinned buffers into one of two device arenas (skipped when equal to
+  // the last upload); arena_free[k] fires when the last search reading
+  // d_arena[k] has finished
+  std::vector<char> tables;
+  std::vector<char> last_upload;
+  char* h_arena[2] = {nullptr, nullptr};
+  char* d_arena[2] = {nullptr, nullptr};
+  hipEvent_t arena_free[2] = {nullptr, nullptr};
+  int arena_last = -1;
   // streaming
   std::vector<StreamState> streams;
-  ScanDev* h_scans[2] = {nullptr, nullptr};  // pinned staging of the per-call scan table
-  hipEvent_t h_scans_free[2] = {nullptr, nullptr};
-  int h_scans_cur = 0;
   std::vector<CallScan> call;      // numbering of the last search
   std::vector<char> call_present;
   int64_t call_windows = 0;
@@ -333,7 +393,7 @@ void release(fringe_plan_t p) {
   if (!p) return;
   if (p->searched && p->done) (void)hipEventSynchronize(p->done);
   void* bufs[] = {p->X, p->e, p->part, p->table, p->blk_counts, p->blk_offsets, p->cands,
-                  p->d_total, p->d_scans, p->grid, p->d_ids, p->d_recs};
+                  p->d_total, p->grid, p->d_ids, p->d_recs, p->d_arena[0], p->d_arena[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto* t : p->tw)
@@ -342,8 +402,8 @@ void release(fringe_plan_t p) {
     for (auto* b : st.stage)
       if (b) (void)hipFree(b);
   for (int k = 0; k < 2; ++k) {
-    if (p->h_scans[k]) (void)hipHostFree(p->h_scans[k]);
-    if (p->h_scans_free[k]) (void)hipEventDestroy(p->h_scans_free[k]);
+    if (p->h_arena[k]) (void)hipHostFree(p->h_arena[k]);
+    if (p->arena_free[k]) (void)hipEventDestroy(p->arena_free[k]);
   }
   if (p->h_total) (void)hipHostFree(p->h_total);
   for (auto ev : p->prof_ev) (void)hipEventDestroy(ev);
@@ -441,6 +501,132 @@ int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, Ca
   return FRINGE_OK;
 }
 
+FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan& c,
+                      const Unit& u, const float2* data, int64_t vis_stride) {
+  const Sizing& z = p->sz;
+  FusedArgs fu{};
+  fu.vis = data ? data + int64_t(u.b0) * vis_stride : nullptr;
+  fu.vis_stride = vis_stride;
+  fu.part = p->part + u.part_off;
+  fu.e = p->e + u.e_off;
+  fu.dump = p->grid;
+  fu.tw = p->tw[si.log_m];
+  fu.slab_windows = int64_t(u.nb) * c.nwb;
+  fu.dump_base = si.grid_off + int64_t(u.b0) * si.grid_per_bl;
+  fu.grid_per_bl = si.grid_per_bl;
+  for (int l = 0; l < kMaxLevels; ++l) fu.lvl_goff[l] = si.lvl_goff[l];
+  fu.nb = u.nb;
+  fu.T = c.T;
+  fu.F = si.F;
+  fu.M = si.M;
+  fu.R = si.n_kb;
+  fu.hf = (si.F + kBinsPerWave - 1) / kBinsPerWave;
+  fu.chunk = si.chunk;
+  fu.n_chunks = (c.T + si.chunk - 1) / si.chunk;
+  fu.n_pairs = fu.slab_windows > 0 ? u.nb * fu.n_chunks : 0;
+  fu.nwb = int(c.nwb);
+  fu.t_emit = c.t_emit;
+  for (int l = 0; l <= kMaxLevels; ++l) fu.lvl_off[l] = int(c.lvl_off[l]);
+  for (int l = 0; l < kMaxLevels; ++l) fu.lvl_j0[l] = c.lvl_j0[l];
+  for (int L = 0; L < 8; ++L) fu.lvl_of_log[L] = -1;
+  for (int l = 0; l < z.lv.n; ++l) fu.lvl_of_log[z.lv.logW[l]] = l;
+  return fu;
+}
+
+FinalizeArgs finalize_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan& c,
+                            const Unit& u) {
+  FinalizeArgs fa{};
+  fa.part = p->part + u.part_off;
+  fa.e = p->e + u.e_off;
+  fa.table = p->table + c.win_off + int64_t(u.b0) * c.nwb;
+  fa.slab_windows = int64_t(u.nb) * c.nwb;
+  fa.n_kb = si.n_kb;
+  fa.nb = u.nb;
+  fa.T = c.T;
+  fa.nwb = int(c.nwb);
+  fa.pad_t = si.pad_t;
+  fa.M = si.M;
+  for (int l = 0; l <= kMaxLevels; ++l) fa.lvl_off[l] = int(c.lvl_off[l]);
+  for (int l = 0; l < kMaxLevels; ++l) fa.lvl_j0[l] = c.lvl_j0[l];
+  fa.lv = p->sz.lv;
+  return fa;
+}
+
+// Byte offsets of the three tables inside an arena.
+struct ArenaLayout {
+  size_t scans, fused, fin;
+};
+
+ArenaLayout arena_layout(const Sizing& z, size_t n_entries) {
+  ArenaLayout L;
+  L.scans = 0;
+  L.fused = align_up(z.scans.size() * sizeof(ScanDev));
+  L.fin = L.fused + align_up(n_entries * sizeof(FusedArgs));
+  return L;
+}
+
+// Upload the host tables into a device arena (unless they equal the last
+// upload) and return its index.
+int upload_tables(fringe_plan_s* p, hipStream_t st, int* k_out) {
+  hipError_t he;
+  if (p->arena_last >= 0 && p->tables == p->last_upload) {
+    *k_out = p->arena_last;
+    return FRINGE_OK;
+  }
+  const int k = p->arena_last < 0 ? 0 : (p->arena_last ^ 1);
+  if ((he = hipEventSynchronize(p->arena_free[k])) != hipSuccess)
+    return hip_fail(he, "descriptor staging");
+  std::memcpy(p->h_arena[k], p->tables.data(), p->tables.size());
+  if ((he = hipMemcpyAsync(p->d_arena[k], p->h_arena[k], p->tables.size(), hipMemcpyHostToDevice,
+                           st)) != hipSuccess)
+    return hip_fail(he, "descriptor upload");
+  p->last_upload = p->tables;
+  p->arena_last = k;
+  *k_out = k;
+  return FRINGE_OK;
+}
+
+// FRINGE_PLAIN: every window searched by its own launch of the fused kernel
+// (data = the window's W APs of one baseline, one length) and its own
+// finalize launch; the table and candidate list come out as in a batch
+// search.  A baseline for timing the batched launches against.
+int plain_tables(fringe_plan_s* p, const std::vector<const float2*>& data) {
+  const Sizing& z = p->sz;
+  const ArenaLayout L = arena_layout(z, size_t(p->call_windows));
+  auto* fus = reinterpret_cast<FusedArgs*>(p->tables.data() + L.fused);
+  auto* fin = reinterpret_cast<FinalizeArgs*>(p->tables.data() + L.fin);
+  int64_t i = 0;
+  for (size_t s = 0; s < z.scans.size(); ++s) {
+    const ScanInfo& si = z.scans[s];
+    const CallScan& c = p->call[s];
+    for (int b = 0; b < si.d.n_baselines; ++b) {
+      for (int li = 0; li < z.lv.n; ++li) {
+        const int w = z.lv.W[li], stride = z.lv.s[li];
+        const int64_t n_l = c.lvl_off[li + 1] - c.lvl_off[li];
+        for (int64_t j = 0; j < n_l; ++j, ++i) {
+          // a one-window "scan": W APs of baseline b from AP j * stride
+          CallScan one{};
+          one.T = w;
+          one.nwb = 1;
+          for (int l = 0; l <= kMaxLevels; ++l) one.lvl_off[l] = l <= li ? 0 : 1;
+          Unit u{int(s), 0, 1, 0, 0};
+          const float2* base = data[s] + (int64_t(b) * si.d.n_ap + j * stride) * si.F;
+          fus[i] = fused_entry(p, si, one, u, base, int64_t(si.d.n_ap) * si.F);
+          fus[i].block_off = 0;
+          // only this length: the shorter windows inside these W APs are
+          // other entries' work
+          for (int L = 0; L < 8; ++L) fus[i].lvl_of_log[L] = -1;
+          fus[i].lvl_of_log[z.lv.logW[li]] = li;
+          fin[i] = finalize_entry(p, si, one, u);
+          fin[i].table = p->table + c.win_off + int64_t(b) * c.nwb + c.lvl_off[li] + j;
+          fin[i].win_begin = 0;
+        }
+      }
+    }
+  }
+  return FRINGE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -503,7 +689,8 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
       (rc = dev_alloc(&p->blk_offsets, uint64_t(z.n_blocks) * sizeof(int64_t), "block offsets")) ||
       (rc = dev_alloc(&p->cands, z.cand_bytes, "candidates")) ||
       (rc = dev_alloc(&p->d_total, sizeof(int64_t), "candidate count")) ||
-      (rc = dev_alloc(&p->d_scans, ns * sizeof(ScanDev), "scan table")) ||
+      (rc = dev_alloc(&p->d_arena[0], z.arena_bytes, "descriptor arena")) ||
+      (rc = dev_alloc(&p->d_arena[1], z.arena_bytes, "descriptor arena")) ||
       (rc = dev_alloc(&p->grid, z.grid_bytes, "grid dump"))) {
     release(p);
     return rc;
@@ -519,13 +706,13 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
           return rc;
         }
     }
-    for (int k = 0; k < 2; ++k) {
-      if ((he = hipHostMalloc(reinterpret_cast<void**>(&p->h_scans[k]), ns * sizeof(ScanDev),
-                              hipHostMallocDefault)) != hipSuccess ||
-          (he = hipEventCreateWithFlags(&p->h_scans_free[k], hipEventDisableTiming)) != hipSuccess) {
-        release(p);
-        return hip_fail(he, "stream scan-table staging");
-      }
+  }
+  for (int k = 0; k < 2; ++k) {
+    if ((he = hipHostMalloc(reinterpret_cast<void**>(&p->h_arena[k]), z.arena_bytes,
+                            hipHostMallocDefault)) != hipSuccess ||
+        (he = hipEventCreateWithFlags(&p->arena_free[k], hipEventDisableTiming)) != hipSuccess) {
+      release(p);
+      return hip_fail(he, "descriptor staging");
     }
   }
   // twiddle tables exp(-2 pi i k / M), rounded from double
@@ -544,15 +731,6 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
     if (he != hipSuccess) {
       release(p);
       return hip_fail(he, "hipMemcpy(twiddles)");
-    }
-  }
-  if (!z.streaming) {  // the batch numbering never changes
-    std::vector<ScanDev> sd(ns);
-    for (int s = 0; s < ns; ++s) sd[s] = make_scan_dev(z.scans[s], z.scans[s].full);
-    he = hipMemcpy(p->d_scans, sd.data(), sd.size() * sizeof(ScanDev), hipMemcpyHostToDevice);
-    if (he != hipSuccess) {
-      release(p);
-      return hip_fail(he, "hipMemcpy(scan table)");
     }
   }
   if ((he = hipHostMalloc(reinterpret_cast<void**>(&p->h_total), sizeof(int64_t), hipHostMallocDefault)) !=
@@ -606,113 +784,111 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     p->call_present[s] = 1;
   }
   p->call_windows = win_off;
-  if (z.streaming) {  // this call's scan table, through a pinned double buffer
-    const int k = p->h_scans_cur;
-    if ((he = hipEventSynchronize(p->h_scans_free[k])) != hipSuccess)
-      return hip_fail(he, "scan-table staging");
-    for (int s = 0; s < ns; ++s) p->h_scans[k][s] = make_scan_dev(z.scans[s], p->call[s]);
-    if ((he = hipMemcpyAsync(p->d_scans, p->h_scans[k], ns * sizeof(ScanDev),
-                             hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (he = hipEventRecord(p->h_scans_free[k], st)) != hipSuccess)
-      return hip_fail(he, "scan-table upload");
-    p->h_scans_cur ^= 1;
-  }
-
-  for (int s = 0; s < ns; ++s) {
-    if (!p->call_present[s]) continue;
-    const ScanInfo& si = z.scans[s];
-    const CallScan& c = p->call[s];
-    const int n_chunks = (c.T + si.chunk - 1) / si.chunk;
-    for (int b0 = 0; b0 < si.d.n_baselines; b0 += si.slab_nb) {
-      const int nb = std::min(si.slab_nb, si.d.n_baselines - b0);
-      const int64_t slab_windows = int64_t(nb) * c.nwb;
-      if (slab_windows == 0) continue;
-      const float2* vis = data[s] + int64_t(b0) * (z.streaming ? si.stage_len : c.T) * si.F;
-      if (z.fused) {
-        FusedArgs fu{};
-        fu.vis = vis;
-        fu.vis_stride = int64_t(z.streaming ? si.stage_len : c.T) * si.F;
-        fu.part = p->part;
-        fu.e = p->e;
-        fu.dump = p->grid;
-        fu.tw = p->tw[si.log_m];
-        fu.slab_windows = slab_windows;
-        fu.dump_base = si.grid_off + int64_t(b0) * si.grid_per_bl;
-        fu.grid_per_bl = si.grid_per_bl;
-        for (int l = 0; l < kMaxLevels; ++l) fu.lvl_goff[l] = si.lvl_goff[l];
-        fu.nb = nb;
-        fu.T = c.T;
-        fu.F = si.F;
-        fu.M = si.M;
-        fu.R = si.n_kb;
-        fu.hf = (si.F + kBinsPerWave - 1) / kBinsPerWave;
-        fu.chunk = si.chunk;
-        fu.n_chunks = n_chunks;
-        fu.n_pairs = nb * n_chunks;
-        fu.nwb = int(c.nwb);
-        fu.t_emit = c.t_emit;
-        for (int l = 0; l <= kMaxLevels; ++l) fu.lvl_off[l] = int(c.lvl_off[l]);
-        for (int l = 0; l < kMaxLevels; ++l) fu.lvl_j0[l] = c.lvl_j0[l];
-        for (int L = 0; L < 8; ++L) fu.lvl_of_log[L] = -1;
-        for (int l = 0; l < z.lv.n; ++l) fu.lvl_of_log[z.lv.logW[l]] = l;
-        FRINGE_TIMED(1, launch_fused(fu, si.pad_t, z.w_max, p->grid != nullptr, st),
-                     "fused search launch");
-      } else {
-        DelayArgs da{};
-        da.vis = vis;
-        da.vis_stride = int64_t(z.streaming ? si.stage_len : c.T) * si.F;
-        da.X = p->X;
-        da.e = p->e;
-        da.tw = p->tw[si.log_m];
-        da.nb = nb;
-        da.T = c.T;
-        da.F = si.F;
-        da.M = si.M;
-        da.log_m = si.log_m;
-        da.pad_f = p->params.pad_freq;
-        FRINGE_TIMED(0, launch_delay_fft(da, st), "delay transform launch");
-
-        RateArgs ra{};
-        ra.X = p->X;
-        ra.part = p->part;
-        ra.dump = p->grid;
-        ra.slab_windows = slab_windows;
-        ra.dump_base = si.grid_off + int64_t(b0) * si.grid_per_bl;
-        ra.grid_per_bl = si.grid_per_bl;
-        for (int l = 0; l < kMaxLevels; ++l) ra.lvl_goff[l] = si.lvl_goff[l];
-        ra.nb = nb;
-        ra.T = c.T;
-        ra.M = si.M;
-        ra.log_m = si.log_m;
-        ra.n_kb = si.n_kb;
-        ra.chunk = si.chunk;
-        ra.n_chunks = n_chunks;
-        ra.w_max = z.w_max;
-        ra.buf_slots = rate_buffer_slots(z.w_max);
-        ra.pad_t = si.pad_t;
-        ra.nwb = int(c.nwb);
-        ra.t_emit = c.t_emit;
-        for (int l = 0; l <= kMaxLevels; ++l) ra.lvl_off[l] = int(c.lvl_off[l]);
-        for (int l = 0; l < kMaxLevels; ++l) ra.lvl_j0[l] = c.lvl_j0[l];
-        ra.lv = z.lv;
-        FRINGE_TIMED(1, launch_rate_peak(ra, st), "rate transform launch");
+  // descriptor tables of this call: scan table, then one fused and one
+  // finalize entry per unit (per window with FRINGE_PLAIN)
+  const bool plain = (p->params.flags & FRINGE_PLAIN) != 0;
+  const size_t n_entries = plain ? size_t(p->call_windows) : z.units.size();
+  const ArenaLayout L = arena_layout(z, n_entries);
+  p->tables.assign(L.fin + n_entries * sizeof(FinalizeArgs), 0);
+  auto* sdev = reinterpret_cast<ScanDev*>(p->tables.data() + L.scans);
+  for (int s = 0; s < ns; ++s) sdev[s] = make_scan_dev(z.scans[s], p->call[s]);
+  std::vector<int64_t> grp_blocks(z.groups.size(), 0), grp_windows(z.groups.size(), 0);
+  int hf_max = 1;
+  if (plain) {
+    plain_tables(p, data);
+  } else {
+    auto* fus = reinterpret_cast<FusedArgs*>(p->tables.data() + L.fused);
+    auto* fin = reinterpret_cast<FinalizeArgs*>(p->tables.data() + L.fin);
+    for (size_t g = 0; g < z.groups.size(); ++g) {
+      for (int ui = z.groups[g].u0; ui < z.groups[g].u1; ++ui) {
+        const Unit& u = z.units[ui];
+        const ScanInfo& si = z.scans[u.scan];
+        const CallScan& c = p->call[u.scan];
+        const int64_t stride = int64_t(z.streaming ? si.stage_len : si.d.n_ap) * si.F;
+        fus[ui] = fused_entry(p, si, c, u, data[u.scan], stride);
+        if (!p->call_present[u.scan]) fus[ui].n_pairs = 0;
+        fus[ui].block_off = grp_blocks[g];
+        grp_blocks[g] += z.fused ? fused_blocks(fus[ui]) : 0;
+        fin[ui] = finalize_entry(p, si, c, u);
+        if (!p->call_present[u.scan]) fin[ui].slab_windows = 0;
+        fin[ui].win_begin = grp_windows[g];
+        grp_windows[g] += fin[ui].slab_windows;
+        if (fus[ui].n_pairs > 0) hf_max = std::max(hf_max, fus[ui].hf);
       }
+    }
+  }
+  int k = 0;
+  {
+    const int rc = upload_tables(p, st, &k);
+    if (rc != FRINGE_OK) return rc;
+  }
+  char* arena = p->d_arena[k];
+  p->d_scans = reinterpret_cast<ScanDev*>(arena + L.scans);
+  const FusedArgs* d_fus = reinterpret_cast<const FusedArgs*>(arena + L.fused);
+  const FinalizeArgs* d_fin = reinterpret_cast<const FinalizeArgs*>(arena + L.fin);
 
-      FinalizeArgs fa{};
-      fa.part = p->part;
-      fa.e = p->e;
-      fa.table = p->table + c.win_off + int64_t(b0) * c.nwb;
-      fa.slab_windows = slab_windows;
-      fa.n_kb = si.n_kb;
-      fa.nb = nb;
-      fa.T = c.T;
-      fa.nwb = int(c.nwb);
-      fa.pad_t = si.pad_t;
-      fa.M = si.M;
-      for (int l = 0; l <= kMaxLevels; ++l) fa.lvl_off[l] = int(c.lvl_off[l]);
-      for (int l = 0; l < kMaxLevels; ++l) fa.lvl_j0[l] = c.lvl_j0[l];
-      fa.lv = z.lv;
-      FRINGE_TIMED(2, launch_finalize(fa, st), "finalize launch");
+  if (plain) {
+    for (int64_t i = 0; i < p->call_windows; ++i) {
+      const FusedArgs& h = reinterpret_cast<const FusedArgs*>(p->tables.data() + L.fused)[i];
+      FRINGE_TIMED(1, launch_fused(d_fus + i, 1, fused_blocks(h), z.scans[0].pad_t, z.w_max, h.hf,
+                                   false, st), "plain fused launch");
+      FRINGE_TIMED(2, launch_finalize(d_fin + i, 1, 1, st), "plain finalize launch");
+    }
+  } else if (z.fused) {
+    for (size_t g = 0; g < z.groups.size(); ++g) {
+      const int u0 = z.groups[g].u0, n = z.groups[g].u1 - z.groups[g].u0;
+      if (grp_windows[g] == 0) continue;
+      FRINGE_TIMED(1, launch_fused(d_fus + u0, n, grp_blocks[g], z.scans[0].pad_t, z.w_max, hf_max,
+                                   p->grid != nullptr, st), "fused search launch");
+      FRINGE_TIMED(2, launch_finalize(d_fin + u0, n, grp_windows[g], st), "finalize launch");
+    }
+  } else {
+    const auto* hfus = reinterpret_cast<const FusedArgs*>(p->tables.data() + L.fused);
+    for (size_t g = 0; g < z.groups.size(); ++g) {
+      const int ui = z.groups[g].u0;  // two-pass groups hold one unit
+      const Unit& u = z.units[ui];
+      const ScanInfo& si = z.scans[u.scan];
+      const CallScan& c = p->call[u.scan];
+      if (grp_windows[g] == 0) continue;
+      DelayArgs da{};
+      da.vis = hfus[ui].vis;
+      da.vis_stride = hfus[ui].vis_stride;
+      da.X = p->X;
+      da.e = p->e + u.e_off;
+      da.tw = p->tw[si.log_m];
+      da.nb = u.nb;
+      da.T = c.T;
+      da.F = si.F;
+      da.M = si.M;
+      da.log_m = si.log_m;
+      da.pad_f = p->params.pad_freq;
+      FRINGE_TIMED(0, launch_delay_fft(da, st), "delay transform launch");
+
+      RateArgs ra{};
+      ra.X = p->X;
+      ra.part = p->part + u.part_off;
+      ra.dump = p->grid;
+      ra.slab_windows = int64_t(u.nb) * c.nwb;
+      ra.dump_base = si.grid_off + int64_t(u.b0) * si.grid_per_bl;
+      ra.grid_per_bl = si.grid_per_bl;
+      for (int l = 0; l < kMaxLevels; ++l) ra.lvl_goff[l] = si.lvl_goff[l];
+      ra.nb = u.nb;
+      ra.T = c.T;
+      ra.M = si.M;
+      ra.log_m = si.log_m;
+      ra.n_kb = si.n_kb;
+      ra.chunk = si.chunk;
+      ra.n_chunks = (c.T + si.chunk - 1) / si.chunk;
+      ra.w_max = z.w_max;
+      ra.buf_slots = rate_buffer_slots(z.w_max);
+      ra.pad_t = si.pad_t;
+      ra.nwb = int(c.nwb);
+      ra.t_emit = c.t_emit;
+      for (int l = 0; l <= kMaxLevels; ++l) ra.lvl_off[l] = int(c.lvl_off[l]);
+      for (int l = 0; l < kMaxLevels; ++l) ra.lvl_j0[l] = c.lvl_j0[l];
+      ra.lv = z.lv;
+      FRINGE_TIMED(1, launch_rate_peak(ra, st), "rate transform launch");
+      FRINGE_TIMED(2, launch_finalize(d_fin + ui, 1, grp_windows[g], st), "finalize launch");
     }
   }
   CompactArgs ca{};
@@ -730,7 +906,9 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   ca.lv = z.lv;
   FRINGE_TIMED(3, launch_compact(ca, st), "compaction launch");
 #undef FRINGE_TIMED
-  if ((he = hipEventRecord(p->done, st)) != hipSuccess) return hip_fail(he, "hipEventRecord");
+  if ((he = hipEventRecord(p->done, st)) != hipSuccess ||
+      (he = hipEventRecord(p->arena_free[k], st)) != hipSuccess)
+    return hip_fail(he, "hipEventRecord");
   p->last_stream = st;
   p->searched = true;
   return FRINGE_OK;

@@ -3,18 +3,42 @@
 
 namespace fringe {
 
-hipError_t launch_fused_p1_w3(const FusedArgs& a, bool dump, hipStream_t st);
-hipError_t launch_fused_p1_w5(const FusedArgs& a, bool dump, hipStream_t st);
-hipError_t launch_fused_p2_w3(const FusedArgs& a, bool dump, hipStream_t st);
-hipError_t launch_fused_p2_w5(const FusedArgs& a, bool dump, hipStream_t st);
+hipError_t launch_fused_p1_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
+                              hipStream_t st);
+hipError_t launch_fused_p1_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
+                              hipStream_t st);
+hipError_t launch_fused_p2_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
+                              hipStream_t st);
+hipError_t launch_fused_p2_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
+                              hipStream_t st);
+hipError_t launch_fused_p1_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
+                              hipStream_t st);
+hipError_t launch_fused_p2_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
+                              hipStream_t st);
 
 // APs per unrolled period of the kernel that serves w_max.
-int fused_period(int w_max) { return w_max <= 8 ? 4 : 16; }
+int fused_period(int w_max) { return w_max <= 8 ? 4 : (w_max <= 32 ? 16 : 32); }
 
-hipError_t launch_fused(const FusedArgs& a, int pad_t, int w_max, bool dump, hipStream_t st) {
-  if (a.hf > 16 || w_max > kFusedMaxWindow) return hipErrorInvalidValue;
-  if (pad_t == 1) return w_max <= 8 ? launch_fused_p1_w3(a, dump, st) : launch_fused_p1_w5(a, dump, st);
-  if (pad_t == 2) return w_max <= 8 ? launch_fused_p2_w3(a, dump, st) : launch_fused_p2_w5(a, dump, st);
+// One block per (baseline, chunk, class); the classes of a (baseline, chunk)
+// pair and its XCD are fixed by the block index, so an entry spans
+// 8 * R * ceil(pairs / 8) blocks.
+int64_t fused_blocks(const FusedArgs& a) {
+  return a.n_pairs == 0 ? 0 : ((int64_t(a.n_pairs) + 7) / 8) * 8 * a.R;
+}
+
+hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
+                        int w_max, int hf_max, bool dump, hipStream_t st) {
+  if (hf_max > 16 || w_max > kFusedMaxWindow) return hipErrorInvalidValue;
+  if (pad_t == 1) {
+    if (w_max <= 8) return launch_fused_p1_w3(d_tab, n_tab, n_blocks, hf_max, dump, st);
+    if (w_max <= 32) return launch_fused_p1_w5(d_tab, n_tab, n_blocks, hf_max, dump, st);
+    return launch_fused_p1_w6(d_tab, n_tab, n_blocks, hf_max, dump, st);
+  }
+  if (pad_t == 2) {
+    if (w_max <= 8) return launch_fused_p2_w3(d_tab, n_tab, n_blocks, hf_max, dump, st);
+    if (w_max <= 32) return launch_fused_p2_w5(d_tab, n_tab, n_blocks, hf_max, dump, st);
+    return launch_fused_p2_w6(d_tab, n_tab, n_blocks, hf_max, dump, st);
+  }
   return hipErrorInvalidValue;
 }
 

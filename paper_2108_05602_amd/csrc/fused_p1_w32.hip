@@ -3,10 +3,11 @@
 
 namespace fringe {
 
-hipError_t launch_fused_p1_w5(const FusedArgs& a, bool dump, hipStream_t st) {
-  if (dump) return launch_fused_t<1, 5, 16, true>(a, st);
-  if (a.hf <= 4) return launch_fused_t<1, 5, 4, false>(a, st);
-  return launch_fused_t<1, 5, 16, false>(a, st);
+hipError_t launch_fused_p1_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                               bool dump, hipStream_t st) {
+  if (dump) return launch_fused_t<1, 5, 16, true>(tab, n, blocks, st);
+  if (hf_max <= 4) return launch_fused_t<1, 5, 4, false>(tab, n, blocks, st);
+  return launch_fused_t<1, 5, 16, false>(tab, n, blocks, st);
 }
 
 }  // namespace fringe

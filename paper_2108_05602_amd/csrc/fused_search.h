@@ -84,7 +84,8 @@ __device__ __forceinline__ float2 xlane_dit(float2 v, const LaneConsts& k) {
 }  // namespace fused
 
 template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
-__global__ void __launch_bounds__(64) fused_search_kernel(FusedArgs a) {
+__global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __restrict__ tab,
+                                                           int n_tab) {
   constexpr int WMAX = 1 << LOGWMAX;
   constexpr int P = WMAX / 2;          // APs per unrolled period
   constexpr int HS = 2 * P;            // history registers (complex)
@@ -92,7 +93,14 @@ __global__ void __launch_bounds__(64) fused_search_kernel(FusedArgs a) {
   static_assert(P % PD == 0 && P >= 4, "period");
 
   const int lane = threadIdx.x;
-  const int g = blockIdx.x;
+  // the entry (scan slab) that owns this block
+  int lo = 0, hi = n_tab - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].block_off <= static_cast<int64_t>(blockIdx.x)) lo = mid; else hi = mid - 1;
+  }
+  const FusedArgs& a = tab[lo];
+  const int g = static_cast<int>(static_cast<int64_t>(blockIdx.x) - a.block_off);
   const int cls = (g >> 3) % a.R;
   const int q = ((g >> 3) / a.R) * 8 + (g & 7);
   if (q >= a.n_pairs) return;
@@ -191,13 +199,11 @@ __global__ void __launch_bounds__(64) fused_search_kernel(FusedArgs a) {
 }
 
 template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
-hipError_t launch_fused_t(const FusedArgs& a, hipStream_t st) {
-  if (a.n_pairs == 0) return hipSuccess;
-  const int64_t groups = (a.n_pairs + 7) / 8;
-  const int64_t blocks = groups * 8 * a.R;
+hipError_t launch_fused_t(const FusedArgs* tab, int n_tab, int64_t blocks, hipStream_t st) {
+  if (blocks == 0 || n_tab == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL((fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP>),
-                     dim3(static_cast<unsigned>(blocks)), dim3(64), 0, st, a);
+                     dim3(static_cast<unsigned>(blocks)), dim3(64), 0, st, tab, n_tab);
   return hipGetLastError();
 }
 

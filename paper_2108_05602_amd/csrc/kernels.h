@@ -64,7 +64,10 @@ struct RateArgs {
   LevelTable lv;
 };
 
+// One entry of a fused launch: a slab of baselines of one scan.  A launch
+// covers several entries; entry k owns blocks [block_off, next block_off).
 struct FusedArgs {
+  int64_t block_off;   // first block of this entry in the launch (a multiple of 8)
   const float2* vis;   // [nb][T][F] visibilities of the slab
   int64_t vis_stride;  // elements between baselines of vis (>= T * F)
   uint64_t* part;      // [R][slab_windows] per residue-class peak keys (out)
@@ -82,7 +85,10 @@ struct FusedArgs {
   int lvl_of_log[8];   // level index of the length 2^L, -1 if not searched
 };
 
+// One entry of a finalize launch; entry k owns the launch's windows
+// [win_begin, next win_begin).
 struct FinalizeArgs {
+  int64_t win_begin;
   const uint64_t* part;
   const float* e;
   WindowRec* table;    // records of this slab's windows (already offset)
@@ -113,10 +119,15 @@ constexpr int kCompactBlock = 1024;  // windows per compaction block
 hipError_t launch_delay_fft(const DelayArgs& a, hipStream_t st);
 hipError_t launch_rate_peak(const RateArgs& a, hipStream_t st);
 // Fused path for plans whose longest window is at most kFusedMaxWindow APs.
-constexpr int kFusedMaxWindow = 32;
+constexpr int kFusedMaxWindow = 64;
 int fused_period(int w_max);
-hipError_t launch_fused(const FusedArgs& a, int pad_t, int w_max, bool dump, hipStream_t st);
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
+// Blocks that entry `a` occupies in a fused launch.
+int64_t fused_blocks(const FusedArgs& a);
+// d_tab: n_tab entries in device memory; hf_max: the largest entry hf.
+hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
+                        int w_max, int hf_max, bool dump, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs* d_tab, int n_tab, int64_t n_windows,
+                           hipStream_t st);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
 hipError_t launch_gather(const WindowRec* table, const int64_t* ids, int64_t n,
                          fringe_candidate* out, const ScanDev* scans, int n_scans,

@@ -19,9 +19,9 @@
 // in flight.  The lane's rate key goes through a 64-lane DPP max and one
 // lane stores the bin-block's result (window_key.h).
 //
-// This kernel serves every plan; plans whose windows are at most 32 APs
-// long use the fused kernel (fused_search.h) instead, which also does the
-// delay transform and keeps the history in registers.
+// This kernel serves plans with windows longer than 64 APs; shorter ones use
+// the fused kernel (fused_search.h), which also does the delay transform and
+// keeps the history in registers.
 #include "kernels.h"
 #include "window_key.h"
 
@@ -157,7 +157,6 @@ int rate_buffer_slots(int w_max) { return w_max - 1 + 2 * kQ; }
 template <int PT, bool DUMP>
 hipError_t launch_w(const RateArgs& a, hipStream_t st) {
   if (a.w_max <= kFusedMaxWindow) return hipErrorInvalidValue;
-  if (a.w_max <= 64) return launch_t<PT, DUMP, 6>(a, st);
   return launch_t<PT, DUMP, 7>(a, st);
 }
 

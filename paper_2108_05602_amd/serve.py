@@ -1,0 +1,198 @@
+"""Continuous-batching fringe search over streamed correlator chunks.
+
+Each subarray is a stream of fixed-length chunks (all baselines x chunk APs x
+channels, complex64).  The server keeps, per subarray, a streaming plan of
+libfringe (its device-resident history of the last APs, so windows that span
+chunk boundaries are searched exactly once) and a HIP stream of default
+priority.  Requests are admitted in arrival order as soon as
+
+  * a device input slot is free (slots are what the HBM budget leaves after
+    the plans' own memory, one chunk each), and
+  * the subarray's plan is idle (chunks of one subarray are searched in order),
+
+so chunks of different subarrays that arrive while others are on the GPU run
+concurrently on their own streams.  A request's latency is the time from its
+arrival to its candidate list being on the host.  All search work runs in
+libfringe's kernels; this module only moves data into slots, launches and
+polls.
+"""
+
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from .binding import FRINGE_STREAMING, Plan
+
+
+@dataclass
+class Request:
+    sub: int                 # subarray index
+    seq: int                 # chunk number within the subarray
+    arrival: float           # seconds on the server clock
+    payload: object          # torch tensor [nb][chunk][n_if][n_chan] complex64 (device or pinned host)
+
+
+@dataclass
+class Result:
+    sub: int
+    seq: int
+    arrival: float
+    done: float
+    candidates: np.ndarray
+    n_windows: int
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class ServeStats:
+    results: List[Result] = field(default_factory=list)
+    wall: float = 0.0
+    max_inflight: int = 0
+
+    def latencies_ms(self):
+        return np.array([r.latency * 1e3 for r in self.results])
+
+    def summary(self) -> dict:
+        lat = self.latencies_ms()
+        n_win = sum(r.n_windows for r in self.results)
+        return {
+            "chunks": len(self.results),
+            "wall_s": self.wall,
+            "chunks_per_s": len(self.results) / self.wall if self.wall > 0 else 0.0,
+            "windows_per_s": n_win / self.wall if self.wall > 0 else 0.0,
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "max_inflight": self.max_inflight,
+        }
+
+
+class FringeServer:
+    """Continuous-batching server over streaming fringe-search plans."""
+
+    def __init__(self, subarrays: Sequence[dict], window_aps, *, pad_freq: int = 4,
+                 pad_time: int = 2, snr_threshold: float = 4.5, hbm_budget_bytes: int = 0,
+                 max_candidates: int = 1 << 16, max_slots: Optional[int] = None,
+                 device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.subs = [dict(s) for s in subarrays]
+        self.plans = [Plan([s], window_aps, pad_freq=pad_freq, pad_time=pad_time,
+                           snr_threshold=snr_threshold, max_candidates=max_candidates,
+                           flags=FRINGE_STREAMING) for s in self.subs]
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in self.subs]
+        self.chunk_elems = [s["n_baselines"] * s["n_ap"] * s["n_if"] * s["n_chan"] for s in self.subs]
+        slot_elems = max(self.chunk_elems)
+        plan_bytes = sum(p.info()["device_bytes"] for p in self.plans)
+        n_slots = max_slots if max_slots is not None else 2 * len(self.subs)
+        if hbm_budget_bytes:
+            fit = (int(hbm_budget_bytes) - plan_bytes) // (slot_elems * 8)
+            if fit < 1:
+                raise MemoryError(f"HBM budget {hbm_budget_bytes} leaves no room for a "
+                                  f"{slot_elems * 8}-byte chunk after {plan_bytes} bytes of plans")
+            n_slots = min(n_slots, int(fit))
+        self.slots = [torch.empty(slot_elems, dtype=torch.complex64, device=self.device)
+                      for _ in range(n_slots)]
+        self.free = list(range(n_slots))
+        self.queue: collections.deque = collections.deque()
+        self.busy: Dict[int, tuple] = {}   # sub -> (request, slot, event)
+        self.clock0 = time.perf_counter()
+
+    # ---------------------------------------------------------------- api --
+    def now(self) -> float:
+        return time.perf_counter() - self.clock0
+
+    def submit(self, req: Request) -> None:
+        self.queue.append(req)
+
+    def inflight(self) -> int:
+        return len(self.busy)
+
+    def poll(self) -> List[Result]:
+        """Collect finished chunks, then admit waiting ones."""
+        out = []
+        for sub in list(self.busy):
+            req, slot, ev = self.busy[sub]
+            if ev.query():
+                plan = self.plans[sub]
+                cands = plan.candidates()
+                n_win = plan.info()["n_windows"]
+                out.append(Result(sub, req.seq, req.arrival, self.now(), cands, n_win))
+                self.free.append(slot)
+                del self.busy[sub]
+        self._admit()
+        return out
+
+    def close(self):
+        for p in self.plans:
+            p.close()
+
+    # ---------------------------------------------------------- internals --
+    def _admit(self):
+        if not self.queue or not self.free:
+            return
+        held = set(self.busy)
+        keep = collections.deque()
+        while self.queue:
+            req = self.queue.popleft()
+            if self.free and req.sub not in held:
+                self._launch(req, self.free.pop())
+                held.add(req.sub)
+            else:
+                keep.append(req)
+                held.add(req.sub)   # later chunks of this subarray wait behind it
+        self.queue = keep
+
+    def _launch(self, req: Request, slot: int):
+        torch = self.torch
+        st = self.streams[req.sub]
+        n = self.chunk_elems[req.sub]
+        dst = self.slots[slot][:n].view(req.payload.shape)
+        with torch.cuda.stream(st):
+            dst.copy_(req.payload, non_blocking=True)
+        self.plans[req.sub].search([dst.data_ptr()], st.cuda_stream)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        self.busy[req.sub] = (req, slot, ev)
+
+
+def run_schedule(server: FringeServer, schedule, payloads, idle_sleep: float = 20e-6) -> ServeStats:
+    """Play arrivals (t_seconds, sub, seq) in real time against the server.
+    payloads[sub][seq] is the chunk tensor.  Returns per-chunk results."""
+    sched = sorted(schedule)
+    stats = ServeStats()
+    i = 0
+    n = len(sched)
+    server.clock0 = time.perf_counter()
+    while len(stats.results) < n:
+        now = server.now()
+        while i < n and sched[i][0] <= now:
+            t, sub, seq = sched[i]
+            server.submit(Request(sub, seq, t, payloads[sub][seq]))
+            i += 1
+        got = server.poll()
+        stats.results.extend(got)
+        stats.max_inflight = max(stats.max_inflight, server.inflight())
+        if not got and (i >= n or sched[i][0] > server.now()):
+            time.sleep(idle_sleep)
+    stats.wall = server.now() - (sched[0][0] if sched else 0.0)
+    return stats
+
+
+def poisson_schedule(n_subs: int, n_chunks: int, rate_per_sub: float, seed: int = 0):
+    """Arrival times (Poisson per subarray, rate in chunks/s) of n_chunks
+    chunks per subarray, in order within each subarray."""
+    rng = np.random.default_rng(seed)
+    sched = []
+    for s in range(n_subs):
+        t = np.cumsum(rng.exponential(1.0 / rate_per_sub, n_chunks))
+        sched += [(float(t[k]), s, k) for k in range(n_chunks)]
+    return sched

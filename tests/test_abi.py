@@ -110,5 +110,22 @@ def test_budget():
     assert _code(lambda: F.fringe_plan_check([C2], C2_W, hbm_budget_bytes=1 << 20)) == B.FRINGE_E_NOMEM
 
 
+def test_plain_flag_rules():
+    c1 = dict(n_baselines=1, n_ap=64, n_if=2, n_chan=16, ap_seconds=1.0, chan_width_hz=1 / 32)
+    assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_PLAIN)["n_windows"] == 31
+    assert _code(lambda: F.fringe_plan_check([dict(c1, n_ap=256)], [128], flags=B.FRINGE_PLAIN)) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: F.fringe_plan_check([c1], [4], flags=B.FRINGE_PLAIN | B.FRINGE_STREAMING)) == B.FRINGE_E_INVALID
+
+
+def test_streaming_sizing():
+    # a 976-AP chunk of a 12-station subarray: windows ending in the chunk
+    sub = dict(n_baselines=66, n_ap=976, n_if=8, n_chan=32, ap_seconds=1.024e-3, chan_width_hz=0.5e6)
+    s = F.fringe_plan_check([sub], C2_W, flags=B.FRINGE_STREAMING)
+    # at most floor((C - 1) / stride) + 1 windows of each length end in a chunk of C APs
+    per_bl = sum((976 - 1) // max(1, w // 2) + 1 for w in C2_W)
+    assert s["n_windows"] == 66 * per_bl
+    assert _code(lambda: F.fringe_plan_check([sub], C2_W, flags=B.FRINGE_STREAMING | B.FRINGE_DUMP_GRID)) == B.FRINGE_E_INVALID
+
+
 def test_dump_grid_only_for_small_plans():
     assert _code(lambda: F.fringe_plan_check([C2], C2_W, flags=B.FRINGE_DUMP_GRID)) == B.FRINGE_E_INVALID

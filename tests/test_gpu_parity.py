@@ -277,3 +277,82 @@ def test_dense_mini_sampled():
             if abs(c["snr"] - p["snr_threshold"]) < 1e-4 * p["snr_threshold"]}
     assert (got ^ want) <= near
     plan.close()
+
+
+def test_plain_path_equals_batched():
+    """One window per launch (FRINGE_PLAIN) gives the batched records."""
+    import paper_2108_05602_amd as F
+    print("case: plain vs batched", flush=True)
+    spec = synth.c2(seed=12, n_stations=3, n_ap=300, n_pulses=3, n_tones=1)
+    v = spec.full()
+    p = synth.C2_PARAMS
+    args = ([spec.desc()], [v], p["window_aps"], p["pad_freq"], p["pad_time"], p["snr_threshold"])
+    pb, tb, cb = run_gpu(*args)
+    pp, tp, cp = run_gpu(*args, flags=F.FRINGE_PLAIN)
+    for k in ("baseline", "window_ap", "t_start", "k_rate", "k_delay", "amp", "snr", "energy"):
+        assert np.array_equal(tb[k], tp[k]), k
+    assert np.array_equal(cb["t_start"], cp["t_start"])
+    pb.close()
+    pp.close()
+
+
+def test_batched_uneven_scans_one_launch():
+    """Scans of uneven baselines, lengths and channel counts (8/16 IF x
+    16/32/64 chan, windows up to 64 APs) searched by one plan: one fused
+    launch per group of scans.  Equal to per-scan plans field by field, and
+    to the reference on sampled windows; a tight HBM budget splits the scans
+    into several groups with the same results."""
+    import paper_2108_05602_amd as F
+    print("case: batched uneven scans", flush=True)
+    specs = synth.c3(n_scans=6, max_ap=600, max_stations=5)
+    p = synth.C3_PARAMS
+    vis = [s.full() for s in specs]
+    descs = [s.desc() for s in specs]
+    args = (p["window_aps"], p["pad_freq"], p["pad_time"], p["snr_threshold"])
+    plan, table, cands = run_gpu(descs, vis, *args, flags=F.FRINGE_PROFILE)
+    prof = plan.profile()
+    assert prof["rate_launches"] == 1 and prof["finalize_launches"] == 1, prof
+    for s in range(len(specs)):
+        p1, t1, _ = run_gpu([descs[s]], [vis[s]], *args)
+        sub = table[table["scan"] == s]
+        for k in ("baseline", "window_ap", "t_start", "k_rate", "k_delay", "amp", "snr", "energy"):
+            assert np.array_equal(sub[k], t1[k]), (s, k)
+        p1.close()
+    need = plan.info()["device_bytes"] - plan.info()["scratch_bytes"]
+    tight, t2, c2 = run_gpu(descs, vis, *args, flags=F.FRINGE_PROFILE,
+                            max_candidates=1 << 16)
+    tight.close()
+    small = F.Plan(descs, p["window_aps"], pad_freq=p["pad_freq"], pad_time=p["pad_time"],
+                   snr_threshold=p["snr_threshold"], flags=F.FRINGE_PROFILE,
+                   hbm_budget_bytes=need + plan.info()["scratch_bytes"] // 3)
+    import torch
+    tens = [torch.from_numpy(v).cuda() for v in vis]
+    small.search([t.data_ptr() for t in tens], torch.cuda.current_stream().cuda_stream)
+    ts = small.windows(np.arange(small.info()["n_windows"]))
+    assert small.profile()["rate_launches"] > 1
+    for k in ("scan", "baseline", "window_ap", "t_start", "k_rate", "k_delay", "amp", "snr"):
+        assert np.array_equal(ts[k], table[k]), k
+    small.close()
+    # reference on samples of every scan
+    rng = np.random.default_rng(8)
+    idx = np.sort(rng.choice(len(table), 200, replace=False))
+    rows = []
+    for i in idx:
+        g = table[i]
+        spec = specs[int(g["scan"])]
+        fv = vis[int(g["scan"])].reshape(spec.n_baselines, spec.n_ap, -1)
+        r = fo.search_window(fv[g["baseline"]], int(g["t_start"]), int(g["window_ap"]),
+                             p["pad_freq"], p["pad_time"])
+        m_f = p["pad_freq"] * spec.n_freq
+        m_t = p["pad_time"] * int(g["window_ap"])
+        rows.append((g["scan"], g["baseline"], g["window_ap"], g["t_start"], r.k_rate, r.k_delay,
+                     r.amp, r.snr, r.energy,
+                     fo.signed_bin(r.k_delay, m_f) / (m_f * spec.chan_width_hz),
+                     fo.signed_bin(r.k_rate, m_t) / (m_t * spec.ap_seconds), r.margin))
+    ref = np.array(rows, dtype=fo.TABLE_DTYPE)
+
+    def xb(s, b):
+        sp = specs[s]
+        return vis[s].reshape(sp.n_baselines, sp.n_ap, -1)[b]
+    compare_windows(table[idx], ref, xb, p["pad_freq"], p["pad_time"], "batched")
+    plan.close()
