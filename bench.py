@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--n-ap", type=int, default=58600, help="(smaller values: quick check only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the search, copy a MIB-MiB device buffer once (a plain copy "
+                         "kernel of known size for scaling hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -139,6 +142,15 @@ def main():
     dev = torch.from_numpy(v).to("cuda:0")
     del v
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n} bytes read, {n} bytes written")
+        del src, dst
     desc = spec.desc()
     plan = F.Plan([desc], params["window_aps"], pad_freq=params["pad_freq"],
                   pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],

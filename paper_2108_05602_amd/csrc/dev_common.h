@@ -19,6 +19,24 @@ __device__ __forceinline__ void static_for(Fn&& f) {
   }
 }
 
+// Pointers read from descriptor tables are generic; these casts let the
+// compiler use global (not flat) memory instructions for them.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+// float2 is a class type whose copy constructor cannot bind a global-space
+// reference, so complex samples go through the native two-float vector.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_global(const float2* p) {
+  const f32x2_t v = *(const __attribute__((address_space(1))) f32x2_t*)(p);
+  return make_float2(v.x, v.y);
+}
+
 // ---------------------------------------------------------------- complex --
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

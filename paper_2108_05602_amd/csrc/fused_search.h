@@ -114,25 +114,33 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   // lane constants
   const int fl = static_cast<int>(__builtin_bitreverse32(static_cast<uint32_t>(lane)) >> 26);
   fused::LaneConsts kc;
-  kc.wfold = a.tw[(cls * fl) & (M - 1)];
+  const float2* tw = a.tw;
+  kc.wfold = ld_global(tw + ((cls * fl) & (M - 1)));
 #pragma unroll
   for (int st = 0; st < 6; ++st) {
     const int d = 1 << st;
     const bool bl = (lane & d) != 0;
     kc.s[st] = bl ? -1.f : 1.f;
-    kc.w[st] = bl ? a.tw[(lane & (d - 1)) * (M / (2 * d))] : make_float2(1.f, 0.f);
+    const float2 w = ld_global(tw + (lane & (d - 1)) * (M / (2 * d)));
+    kc.w[st] = bl ? w : make_float2(1.f, 0.f);
   }
   float2 wh[HFMAX];  // fold twiddles w_R^{c h} (uniform)
 #pragma unroll
-  for (int h = 0; h < HFMAX; ++h) wh[h] = a.tw[((cls * h) * 64) & (M - 1)];
+  for (int h = 0; h < HFMAX; ++h) wh[h] = ld_global(tw + (((cls * h) * 64) & (M - 1)));
 
-  const float2* __restrict__ xb = a.vis + static_cast<int64_t>(b) * a.vis_stride;
+  const float2* xb = a.vis + static_cast<int64_t>(b) * a.vis_stride;
+  // lane-dependent bounds by select, not by branch: out-of-range lanes read
+  // the AP's first sample and zero it
   auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
 #pragma unroll
     for (int h = 0; h < HFMAX; ++h) {
-      const int f = fl + 64 * h;
       float2 v = make_float2(0.f, 0.f);
-      if (h < hf && t < T && f < F) v = xb[static_cast<int64_t>(t) * F + f];
+      if (h < hf && t < T) {
+        const int f = fl + 64 * h;
+        const bool in = f < F;
+        const float2 x = ld_global(xb + static_cast<int64_t>(t) * F + (in ? f : 0));
+        v = make_float2(in ? x.x : 0.f, in ? x.y : 0.f);
+      }
       dst[h] = v;
     }
   };
@@ -146,8 +154,28 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
 #pragma unroll
   for (int k = 0; k < HS; ++k) hist[k] = make_float2(0.f, 0.f);
 
-  float* __restrict__ eb = a.e + static_cast<int64_t>(b) * T;
-  const int64_t part_base = static_cast<int64_t>(cls) * a.slab_windows + static_cast<int64_t>(b) * a.nwb;
+  const auto eb = gptr(a.e + static_cast<int64_t>(b) * T);
+  // per window length 2^L: searched or not, and the part index of the
+  // window with start index j is pidx[L] + j (fields read once, before the
+  // loop, so they live in scalar registers)
+  const auto part = gptr(a.part + static_cast<int64_t>(cls) * a.slab_windows +
+                         static_cast<int64_t>(b) * a.nwb);
+  const int t_emit = a.t_emit;
+  int pidx[LOGWMAX + 1];
+  bool on[LOGWMAX + 1];
+  int64_t gidx[LOGWMAX + 1];
+#pragma unroll
+  for (int L = 0; L <= LOGWMAX; ++L) {
+    const int lvl = a.lvl_of_log[L];
+    on[L] = lvl >= 0;
+    pidx[L] = lvl >= 0 ? a.lvl_off[lvl] - a.lvl_j0[lvl] : 0;
+    gidx[L] = 0;
+    if constexpr (DUMP) {
+      if (lvl >= 0)
+        gidx[L] = a.dump_base + static_cast<int64_t>(b) * a.grid_per_bl + a.lvl_goff[lvl] -
+                  static_cast<int64_t>(a.lvl_j0[lvl]) * (PT << L) * M + (cls + a.R * lane);
+    }
+  }
 
   for (int p0 = own_lo; p0 < t_end; p0 += P) {
     static_for<0, P>([&](auto ii) {
@@ -176,19 +204,15 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
         constexpr int s = W > 1 ? W / 2 : 1;
         constexpr int base = P + i + 1 - W;  // register of the window's first AP
         if constexpr (base >= 0 && ((i + 1 - W) % s + s) % s == 0) {
-          const int lvl = a.lvl_of_log[L];
           const int start = t + 1 - W;
-          if (lvl >= 0 && start >= own_lo && start < own_hi && t < T && t >= a.t_emit) {
+          if (on[L] && start >= own_lo && start < own_hi && t < T && t >= t_emit) {
             float2* dump = nullptr;
             const int j = start / s;
-            if constexpr (DUMP)
-              dump = a.dump + a.dump_base + static_cast<int64_t>(b) * a.grid_per_bl +
-                     a.lvl_goff[lvl] + static_cast<int64_t>(j - a.lvl_j0[lvl]) * (PT * W) * M +
-                     (cls + a.R * lane);
+            if constexpr (DUMP) dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
             const uint32_t key = window_key<L, PT, DUMP>(
                 [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
             const uint64_t pk = wave_peak(key, cls, a.R);
-            if (lane == 0) a.part[part_base + a.lvl_off[lvl] + (j - a.lvl_j0[lvl])] = pk;
+            if (lane == 0) part[pidx[L] + j] = pk;
           }
         }
       });

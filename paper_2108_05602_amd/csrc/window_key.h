@@ -121,15 +121,18 @@ __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump
 }
 
 // ------------------------------------------------------ DPP reductions --
+// Full-mask DPP moves with bound_ctrl set: every lane of the patterns used
+// here has a source lane, and the form lets the compiler fold the move into
+// the consuming max / add.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
   return static_cast<uint32_t>(
-      __builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, 0xF, 0xF, false));
+      __builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, 0xF, 0xF, true));
 }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
