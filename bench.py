@@ -107,6 +107,79 @@ def plain_vs_batched(dev, spec, params, n_bl=3, n_ap=4096, reps=5):
     return out
 
 
+class _Cycle:
+    """payloads[seq] for any seq: a subarray's distinct chunks, repeated."""
+
+    def __init__(self, chunks):
+        self.chunks = chunks
+
+    def __getitem__(self, i):
+        return self.chunks[i % len(self.chunks)]
+
+
+def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
+                    loads=(0.5, 1.0, 1.5, 2.0)):
+    """Streamed subarrays through the continuous-batching server.
+
+    Six subarrays of 3-12 stations (8 IF x 32 chan, 1.024 ms APs), chunks of
+    976 APs (1 s) staged in HBM (each subarray's first n_distinct chunks,
+    replayed in order).  R* = chunks/s with every chunk queued at t = 0; then
+    Poisson arrivals per subarray at x * R* / n_sub for each load x, and the
+    p50 / p99 of arrival -> candidates-on-host latency.  A last point feeds
+    the chunks from pinned host memory (H2D copy inside the latency)."""
+    import torch
+
+    import synth
+    from paper_2108_05602_amd.serve import FringeServer, poisson_schedule, run_schedule
+    specs = synth.c4_subarrays(n_sub, n_chunks=n_distinct, chunk_ap=chunk_ap)
+    dev, host = [], []
+    for s in specs:
+        v = s.full(threads=min(16, os.cpu_count() or 1))
+        t = torch.from_numpy(v)
+        dev.append([t[:, k * chunk_ap:(k + 1) * chunk_ap].contiguous().to("cuda:0")
+                    for k in range(n_distinct)])
+        host.append([t[:, k * chunk_ap:(k + 1) * chunk_ap].contiguous().pin_memory()
+                     for k in range(min(2, n_distinct))])
+        del v, t
+    subs = [dict(s.desc(), n_ap=chunk_ap) for s in specs]
+    per_sub = max(1, chunks_per_point // n_sub)
+    out = {"subarrays": [s["n_baselines"] for s in subs], "chunk_ap": chunk_ap,
+           "chunks_per_point": per_sub * n_sub,
+           "staging": f"first {n_distinct} chunks of each subarray's stream resident in HBM, replayed"}
+
+    def run(payloads, sched):
+        srv = FringeServer(subs, WS_C4, snr_threshold=4.5)
+        try:
+            run_schedule(srv, [(0.0, s, k) for s in range(n_sub) for k in range(2)], payloads)
+            st = run_schedule(srv, sched, payloads)
+        finally:
+            srv.close()
+        torch.cuda.synchronize()
+        return st.summary()
+
+    pd = [_Cycle(c) for c in dev]
+    sat = run(pd, [(0.0, s, k) for s in range(n_sub) for k in range(per_sub)])
+    r_star = sat["chunks_per_s"]
+    out["saturated"] = sat
+    out["r_star_chunks_per_s"] = r_star
+    out["points"] = []
+    for x in loads:
+        s = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)))
+        s["load"] = x
+        out["points"].append(s)
+        log(f"serving load {x}: p50 {s['p50_ms']:.3f} ms, p99 {s['p99_ms']:.3f} ms, "
+            f"{s['chunks_per_s']:.0f} chunks/s")
+    ph = [_Cycle(c) for c in host]
+    hs = run(ph, [(0.0, s, k) for s in range(n_sub) for k in range(per_sub)])
+    hp = run(ph, poisson_schedule(n_sub, per_sub, 0.5 * hs["chunks_per_s"] / n_sub, seed=7))
+    hp["load"] = 0.5
+    out["pinned_host"] = {"r_star_chunks_per_s": hs["chunks_per_s"], "point": hp}
+    return out
+
+
+WS_C4 = [1, 2, 4, 8, 16, 32]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +189,7 @@ def main():
     ap.add_argument("--n-ap", type=int, default=58600, help="(smaller values: quick check only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the search, copy a MIB-MiB device buffer once (a plain copy "
                          "kernel of known size for scaling hardware byte counters)")
@@ -238,6 +312,12 @@ def main():
         log("timing the one-window-per-launch path against the batched path")
         out["plain_vs_batched"] = plain_vs_batched(dev, spec, params)
         log("plain vs batched: " + json.dumps(out["plain_vs_batched"]))
+    if not args.no_serving:
+        log("serving: streamed subarrays, saturated rate and Poisson loads")
+        out["serving"] = serving_latency()
+        pts = out["serving"]["points"]
+        out["p50_ms"] = next(p["p50_ms"] for p in pts if p["load"] == 1.0)
+        out["p99_ms"] = next(p["p99_ms"] for p in pts if p["load"] == 1.0)
     if not args.no_cpu_baseline:
         log("timing the CPU reference on its sample")
         out["cpu_baseline"] = cpu_baseline(spec, params)

@@ -135,7 +135,10 @@ int fringe_search(fringe_plan_t plan, const fringe_cf32* const* d_vis, void* hip
  * (scan, baseline, window_ap, t_start), into host_out[0..capacity).
  * *n_total receives the number of candidates found.  If n_total exceeds
  * capacity or params->max_candidates, the first min(capacity,
- * max_candidates) in order are copied and FRINGE_E_CAPACITY is returned. */
+ * max_candidates) in order are copied and FRINGE_E_CAPACITY is returned.
+ * The search itself enqueues the copy of the count and of the first
+ * min(max_candidates, 2048) records to pinned host memory, so up to that
+ * many candidates come back with no further device transfer. */
 int candidates_get(fringe_plan_t plan, fringe_candidate* host_out,
                    int64_t capacity, int64_t* n_total);
 

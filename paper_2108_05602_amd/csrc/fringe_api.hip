@@ -55,6 +55,9 @@ int64_t ceil_to(int64_t v, int64_t m) { return -floor_to(-v, m); }
 
 constexpr uint64_t kDefaultScratchCap = 8ull << 30;  // work buffers when no budget is given
 constexpr uint64_t kMaxDumpBytes = 1ull << 30;
+// candidate records copied to pinned host memory at the end of every search,
+// so candidates_get needs no further device round trip when they suffice
+constexpr int64_t kCandPrefetch = 2048;
 
 // Windows of one scan in one search: their numbering and where their data is.
 struct CallScan {
@@ -360,6 +363,8 @@ struct fringe_plan_s {
   float2* grid = nullptr;
   float2* tw[13] = {};
   int64_t* h_total = nullptr;      // pinned
+  fringe_candidate* h_cands = nullptr;  // pinned, the first n_prefetch records
+  int64_t n_prefetch = 0;
   int64_t* d_ids = nullptr;        // windows_get staging
   fringe_candidate* d_recs = nullptr;
   int64_t staging_cap = 0;
@@ -406,6 +411,7 @@ void release(fringe_plan_t p) {
     if (p->arena_free[k]) (void)hipEventDestroy(p->arena_free[k]);
   }
   if (p->h_total) (void)hipHostFree(p->h_total);
+  if (p->h_cands) (void)hipHostFree(p->h_cands);
   for (auto ev : p->prof_ev) (void)hipEventDestroy(ev);
   if (p->done) (void)hipEventDestroy(p->done);
   delete p;
@@ -733,8 +739,13 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
       return hip_fail(he, "hipMemcpy(twiddles)");
     }
   }
+  p->n_prefetch = std::min(p->params.max_candidates, kCandPrefetch);
   if ((he = hipHostMalloc(reinterpret_cast<void**>(&p->h_total), sizeof(int64_t), hipHostMallocDefault)) !=
           hipSuccess ||
+      (p->n_prefetch > 0 &&
+       (he = hipHostMalloc(reinterpret_cast<void**>(&p->h_cands),
+                           size_t(p->n_prefetch) * sizeof(fringe_candidate), hipHostMallocDefault)) !=
+           hipSuccess) ||
       (he = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) {
     release(p);
     return hip_fail(he, "plan host resources");
@@ -906,6 +917,12 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   ca.lv = z.lv;
   FRINGE_TIMED(3, launch_compact(ca, st), "compaction launch");
 #undef FRINGE_TIMED
+  if ((he = hipMemcpyAsync(p->h_total, p->d_total, sizeof(int64_t), hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (p->n_prefetch > 0 &&
+       (he = hipMemcpyAsync(p->h_cands, p->cands, size_t(p->n_prefetch) * sizeof(fringe_candidate),
+                            hipMemcpyDeviceToHost, st)) != hipSuccess))
+    return hip_fail(he, "candidate prefetch");
   if ((he = hipEventRecord(p->done, st)) != hipSuccess ||
       (he = hipEventRecord(p->arena_free[k], st)) != hipSuccess)
     return hip_fail(he, "hipEventRecord");
@@ -920,15 +937,15 @@ int candidates_get(fringe_plan_t p, fringe_candidate* host_out, int64_t capacity
   if (!p->searched) return fail(FRINGE_E_STATE, "candidates_get before fringe_search");
   hipError_t he = hipEventSynchronize(p->done);
   if (he != hipSuccess) return hip_fail(he, "hipEventSynchronize");
-  if ((he = hipMemcpyAsync(p->h_total, p->d_total, sizeof(int64_t), hipMemcpyDeviceToHost,
-                           p->last_stream)) != hipSuccess ||
-      (he = hipStreamSynchronize(p->last_stream)) != hipSuccess)
-    return hip_fail(he, "reading the candidate count");
+  // the count and the first n_prefetch records reached pinned memory before
+  // the done event
   const int64_t total = *p->h_total;
   *n_total = total;
   const int64_t avail = std::min(total, p->params.max_candidates);
   const int64_t n = std::min(avail, capacity);
-  if (n > 0) {
+  if (n > 0 && n <= p->n_prefetch) {
+    std::memcpy(host_out, p->h_cands, size_t(n) * sizeof(fringe_candidate));
+  } else if (n > 0) {
     if ((he = hipMemcpyAsync(host_out, p->cands, size_t(n) * sizeof(fringe_candidate),
                              hipMemcpyDeviceToHost, p->last_stream)) != hipSuccess ||
         (he = hipStreamSynchronize(p->last_stream)) != hipSuccess)

@@ -1,4 +1,4 @@
-// Fused fringe search for window lengths up to 32 APs: delay transform,
+// Fused fringe search for window lengths up to 64 APs: delay transform,
 // rate transform and grid peak in one pass over the visibilities.
 //
 // Work item = (baseline b, time chunk, residue class c of the delay bins):
@@ -129,20 +129,25 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   for (int h = 0; h < HFMAX; ++h) wh[h] = ld_global(tw + (((cls * h) * 64) & (M - 1)));
 
   const float2* xb = a.vis + static_cast<int64_t>(b) * a.vis_stride;
-  // lane-dependent bounds by select, not by branch: out-of-range lanes read
-  // the AP's first sample and zero it
-  auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
+  // Loads are unconditional and in bounds (the AP clamped to T - 1, lanes
+  // past the band reading sample 0); what lies outside the data is zeroed
+  // where it is used, so no load has to complete before later work issues.
+  bool lane_in[HFMAX];
+  int lane_f[HFMAX];
 #pragma unroll
-    for (int h = 0; h < HFMAX; ++h) {
-      float2 v = make_float2(0.f, 0.f);
-      if (h < hf && t < T) {
-        const int f = fl + 64 * h;
-        const bool in = f < F;
-        const float2 x = ld_global(xb + static_cast<int64_t>(t) * F + (in ? f : 0));
-        v = make_float2(in ? x.x : 0.f, in ? x.y : 0.f);
-      }
-      dst[h] = v;
-    }
+  for (int h = 0; h < HFMAX; ++h) {
+    const int f = fl + 64 * h;
+    lane_in[h] = h < hf && f < F;
+    lane_f[h] = lane_in[h] ? f : 0;
+  }
+  auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
+    const float2* row = xb + static_cast<int64_t>(min(t, T - 1)) * F;
+#pragma unroll
+    for (int h = 0; h < HFMAX; ++h) dst[h] = ld_global(row + lane_f[h]);
+  };
+  auto sample = [&](float2 x, int h, bool t_in) {
+    const bool ok = t_in && lane_in[h];
+    return make_float2(ok ? x.x : 0.f, ok ? x.y : 0.f);
   };
 
   float2 pre[PD][HFMAX];
@@ -183,12 +188,14 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
       constexpr int fs = i % PD;
       const int t = p0 + i;
       // delay transform of AP t for this class: fold, then across the wave
-      float2 z = pre[fs][0];
-      float es = c_norm(pre[fs][0]);
+      const bool t_in = t < T;
+      float2 z = sample(pre[fs][0], 0, t_in);
+      float es = c_norm(z);
 #pragma unroll
       for (int h = 1; h < HFMAX; ++h) {
-        z = c_add(z, c_mul(pre[fs][h], wh[h]));
-        es += c_norm(pre[fs][h]);
+        const float2 x = sample(pre[fs][h], h, t_in);
+        z = c_add(z, c_mul(x, wh[h]));
+        es += c_norm(x);
       }
       load_ap(t + PD, pre[fs]);
       if (cls == 0) {
