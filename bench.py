@@ -32,6 +32,29 @@ if ROOT not in sys.path:
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector, published
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 
+# HBM bytes of one fused-kernel launch on the full EVN-like scan, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
+# the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99989,
+# WRITE_SIZE x 1.0).  Valid only for the kernel sources they were taken on:
+# `traffic` is reported as null when the hash of csrc/ differs.
+MEASURED_TRAFFIC = {
+    "csrc_sha256": "ebd365db9e048a643a0da5ca7aaa4c74c42d7062cf97b5d3a352d8ef8021b4f1",
+    "fetch_bytes": 8326204858,
+    "write_bytes": 1934643916,
+}
+
+
+def csrc_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2108_05602_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -268,6 +291,10 @@ def main():
     flops_per_launch = kernel_flops * args.steps / max(1, launches)
     achieved = flops_per_launch / avg_launch_s / 1e12
     cube_bytes = spec.nbytes()
+    info_kb = params["pad_freq"] * spec.n_freq // 64   # delay-bin classes of 64 bins
+    traffic = None
+    if fused and full and csrc_hash() == MEASURED_TRAFFIC["csrc_sha256"]:
+        traffic = MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]
     out = {
         "metric": "fringe-fit windows/s + HBM GB/s vs roofline; p50/p99 window latency",
         "value": n_win / (ms_per_step / 1e3),
@@ -297,8 +324,13 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "algorithmic_flops_per_launch": flops_per_launch,
+            # visibilities in, one 8-byte partial peak per window and delay-bin
+            # class out, one 4-byte energy per AP and baseline out
+            "algorithmic_bytes_per_launch": (cube_bytes + n_win * info_kb * 8 +
+                                             spec.n_baselines * spec.n_ap * 4) if fused else None,
             "avg_launch_ms": avg_launch_s * 1e3,
             "launches_per_step": launches / args.steps,
         },

@@ -317,6 +317,33 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   return FRINGE_OK;
 }
 
+// Time chunk of the fused kernel's work items.  A wave searches the windows
+// starting in its chunk and transforms the chunk plus W_max - 1 APs of halo,
+// so long chunks waste less on halos and short chunks give more, shorter
+// waves.  Take the longest chunk (a multiple of the kernel period, at least
+// 64 APs) that still gives every wave slot of the device kWaveRounds waves;
+// when even 64 does not, 64 (the latency-bound case of small grids).
+constexpr int kWavesPerSimd = 3;   // occupancy of the fused kernel
+constexpr int kWaveRounds = 16;
+void tune_chunks(Sizing* sz, int n_cu) {
+  if (!sz->fused) return;
+  const int period = fused_period(sz->w_max);
+  const int64_t target = int64_t(kWaveRounds) * n_cu * 4 * kWavesPerSimd;
+  int best = 64;
+  for (int c = 1024; c >= 64; c /= 2) {
+    if (c % period) continue;
+    int64_t waves = 0;
+    for (const auto& si : sz->scans) {
+      waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_kb;
+    }
+    if (waves >= target) {
+      best = c;
+      break;
+    }
+  }
+  for (auto& si : sz->scans) si.chunk = best;
+}
+
 ScanDev make_scan_dev(const ScanInfo& si, const CallScan& c) {
   ScanDev d{};
   d.win_off = c.win_off;
@@ -685,6 +712,13 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
     release(p);
     return hip_fail(he, "hipGetDevice");
   }
+  int n_cu = 0;
+  if ((he = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device)) !=
+      hipSuccess) {
+    release(p);
+    return hip_fail(he, "hipDeviceGetAttribute");
+  }
+  tune_chunks(&p->sz, std::max(1, n_cu));
   const Sizing& z = p->sz;
   const int ns = int(z.scans.size());
   if ((rc = dev_alloc(&p->X, z.scratch_x, "delay spectra")) ||

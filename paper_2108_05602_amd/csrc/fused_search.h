@@ -101,8 +101,9 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   }
   const FusedArgs& a = tab[lo];
   const int g = static_cast<int>(static_cast<int64_t>(blockIdx.x) - a.block_off);
-  const int cls = (g >> 3) % a.R;
-  const int q = ((g >> 3) / a.R) * 8 + (g & 7);
+  const int R = a.R;
+  const int cls = (g >> 3) % R;
+  const int q = ((g >> 3) / R) * 8 + (g & 7);
   if (q >= a.n_pairs) return;
   const int b = q / a.n_chunks;
   const int chunk = q - b * a.n_chunks;
@@ -178,7 +179,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
     if constexpr (DUMP) {
       if (lvl >= 0)
         gidx[L] = a.dump_base + static_cast<int64_t>(b) * a.grid_per_bl + a.lvl_goff[lvl] -
-                  static_cast<int64_t>(a.lvl_j0[lvl]) * (PT << L) * M + (cls + a.R * lane);
+                  static_cast<int64_t>(a.lvl_j0[lvl]) * (PT << L) * M + (cls + R * lane);
     }
   }
 
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
             if constexpr (DUMP) dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
             const uint32_t key = window_key<L, PT, DUMP>(
                 [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
-            const uint64_t pk = wave_peak(key, cls, a.R);
+            const uint64_t pk = wave_peak(key, cls, R);
             if (lane == 0) part[pidx[L] + j] = pk;
           }
         }
