@@ -135,34 +135,52 @@ __device__ __forceinline__ float dpp_f32(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
+// DPP move into the rows of ROW_MASK only; the other rows get 0, the
+// identity of an unsigned max (which lets the move fold into the max).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_rows_u32(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_rows_f32(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within 8
 constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within 16
 constexpr int kDppRor8 = 0x128;        // lane i <- (i + 8) mod 16 within 16
+constexpr int kDppRowBcast15 = 0x142;  // row r <- lane 15 of row r - 1
+constexpr int kDppRowBcast31 = 0x143;  // rows 2, 3 <- lane 31
 
-// Max of v over the 64 lanes (uniform result).
+// Max of v over the 64 lanes (uniform result): four DPP steps give every
+// lane of a 16-lane row the row's maximum; two row broadcasts (lane 15 into
+// rows 1 and 3, then lane 31 into rows 2 and 3) gather all four rows in
+// lane 63.
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   v = max(v, dpp_u32<kDppXor1>(v));
   v = max(v, dpp_u32<kDppXor2>(v));
   v = max(v, dpp_u32<kDppHalfMirror>(v));
   v = max(v, dpp_u32<kDppMirror>(v));
-  const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
-  const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
-  return max(max(r0, r1), max(r2, r3));
+  v = max(v, dpp_rows_u32<kDppRowBcast15, 0xA>(v));
+  v = max(v, dpp_rows_u32<kDppRowBcast31, 0xC>(v));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
-// Sum of v over the 64 lanes (uniform result).
+// Sum of v over the 64 lanes (uniform result), by the same steps as
+// wave_max_u32.
 __device__ __forceinline__ float wave_sum_dpp(float v) {
   v += dpp_f32<kDppXor1>(v);
   v += dpp_f32<kDppXor2>(v);
   v += dpp_f32<kDppHalfMirror>(v);
   v += dpp_f32<kDppMirror>(v);
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
+  v += dpp_rows_f32<kDppRowBcast15, 0xA>(v);
+  v += dpp_rows_f32<kDppRowBcast31, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Window key of a wave: the 64-lane max of the lanes' rate keys, and the
