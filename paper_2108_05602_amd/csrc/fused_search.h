@@ -44,8 +44,11 @@ __device__ __forceinline__ float xchg(float v) {
 // b lanes (for D <= 8), or new = a + s * b with the two halves a, b that a
 // permlane swap delivers (D = 16, 32).
 template <int D>
-__device__ __forceinline__ float2 dit_stage(float2 v, float2 w, float s) {
-  const float2 t = (D == 1) ? v : c_mul(v, w);
+__device__ __forceinline__ float2 dit_stage(float2 v, float2 w, float s, bool rot) {
+  // D = 2: the twiddle is 1 or -i (rot), applied by selects
+  const float2 t = (D == 1) ? v
+                 : (D == 2) ? make_float2(rot ? v.y : v.x, rot ? -v.x : v.y)
+                            : c_mul(v, w);
   if constexpr (D <= 8) {
     const float px = xchg<D>(t.x), py = xchg<D>(t.y);
     return make_float2(fmaf(s, t.x, px), fmaf(s, t.y, py));
@@ -68,16 +71,17 @@ __device__ __forceinline__ float2 dit_stage(float2 v, float2 w, float s) {
 struct LaneConsts {
   float2 w[6];   // stage twiddles (index log2 D)
   float s[6];    // stage signs
+  bool rot2;     // stage D = 2 twiddle is -i (b lane with bit 0 set)
   float2 wfold;  // w_M^{c f'} of this lane's f'
 };
 
 __device__ __forceinline__ float2 xlane_dit(float2 v, const LaneConsts& k) {
-  v = dit_stage<1>(v, k.w[0], k.s[0]);
-  v = dit_stage<2>(v, k.w[1], k.s[1]);
-  v = dit_stage<4>(v, k.w[2], k.s[2]);
-  v = dit_stage<8>(v, k.w[3], k.s[3]);
-  v = dit_stage<16>(v, k.w[4], k.s[4]);
-  v = dit_stage<32>(v, k.w[5], k.s[5]);
+  v = dit_stage<1>(v, k.w[0], k.s[0], false);
+  v = dit_stage<2>(v, k.w[1], k.s[1], k.rot2);
+  v = dit_stage<4>(v, k.w[2], k.s[2], false);
+  v = dit_stage<8>(v, k.w[3], k.s[3], false);
+  v = dit_stage<16>(v, k.w[4], k.s[4], false);
+  v = dit_stage<32>(v, k.w[5], k.s[5], false);
   return v;
 }
 
@@ -125,6 +129,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
     const float2 w = ld_global(tw + (lane & (d - 1)) * (M / (2 * d)));
     kc.w[st] = bl ? w : make_float2(1.f, 0.f);
   }
+  kc.rot2 = (lane & 2) != 0 && (lane & 1) != 0;
   float2 wh[HFMAX];  // fold twiddles w_R^{c h} (uniform)
 #pragma unroll
   for (int h = 0; h < HFMAX; ++h) wh[h] = ld_global(tw + (((cls * h) * 64) & (M - 1)));
@@ -146,6 +151,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
 #pragma unroll
     for (int h = 0; h < HFMAX; ++h) dst[h] = ld_global(row + lane_f[h]);
   };
+  const bool band_full = F == 64 * HFMAX;  // every lane in band for every fold
   auto sample = [&](float2 x, int h, bool t_in) {
     const bool ok = t_in && lane_in[h];
     return make_float2(ok ? x.x : 0.f, ok ? x.y : 0.f);
@@ -188,21 +194,26 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
       constexpr int i = decltype(ii)::value;
       constexpr int fs = i % PD;
       const int t = p0 + i;
-      // delay transform of AP t for this class: fold, then across the wave
-      const bool t_in = t < T;
-      float2 z = sample(pre[fs][0], 0, t_in);
-      float es = c_norm(z);
+      // delay transform of AP t for this class: fold, then across the wave.
+      // Samples outside the data (past the scan's end, lanes past a band
+      // narrower than the fold) are zeroed on a uniform branch, so APs with
+      // none spend nothing on it.
+      if (!(band_full && t < T)) {
+        const bool t_in = t < T;
 #pragma unroll
-      for (int h = 1; h < HFMAX; ++h) {
-        const float2 x = sample(pre[fs][h], h, t_in);
-        z = c_add(z, c_mul(x, wh[h]));
-        es += c_norm(x);
+        for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
       }
-      load_ap(t + PD, pre[fs]);
-      if (cls == 0) {
+      float2 z = pre[fs][0];
+#pragma unroll
+      for (int h = 1; h < HFMAX; ++h) z = c_add(z, c_mul(pre[fs][h], wh[h]));
+      if (cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
+        float es = 0.f;
+#pragma unroll
+        for (int h = 0; h < HFMAX; ++h) es += c_norm(pre[fs][h]);
         const float e = wave_sum_dpp(es);
         if (lane == 0 && t < own_hi) eb[t] = e;
       }
+      load_ap(t + PD, pre[fs]);
       hist[P + i] = fused::xlane_dit(c_mul(z, kc.wfold), kc);
 
       // every window that ends at AP t
