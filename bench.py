@@ -130,6 +130,34 @@ def plain_vs_batched(dev, spec, params, n_bl=3, n_ap=4096, reps=5):
     return out
 
 
+def graph_vs_eager(dev, spec, params, n_bl=15, n_ap=976, reps=200):
+    """Per-search latency (search + candidates on the host) of a small batch
+    plan, launched eagerly and replayed from its HIP graph (FRINGE_GRAPH):
+    baselines 0..n_bl-1 x APs 0..n_ap-1 of the resident scan (one 1 s chunk
+    of a 6-station subarray's worth of baselines)."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    sub = dev[:n_bl, :n_ap].contiguous()
+    desc = dict(spec.desc(), n_baselines=n_bl, n_ap=n_ap)
+    st = torch.cuda.current_stream()
+    kw = dict(pad_freq=params["pad_freq"], pad_time=params["pad_time"],
+              snr_threshold=params["snr_threshold"], max_candidates=1 << 16)
+    out = {"subset": f"baselines 0-{n_bl - 1} x APs 0-{n_ap - 1} of the same scan", "reps": reps}
+    for name, flags in (("eager", 0), ("graph", F.FRINGE_GRAPH)):
+        with F.Plan([desc], params["window_aps"], flags=flags, **kw) as plan:
+            for _ in range(3):
+                plan.search([sub.data_ptr()], st.cuda_stream)
+                plan.candidates()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.search([sub.data_ptr()], st.cuda_stream)
+                plan.candidates()
+            out[name + "_us"] = (time.perf_counter() - t0) / reps * 1e6
+    return out
+
+
 class _Cycle:
     """payloads[seq] for any seq: a subarray's distinct chunks, repeated."""
 
@@ -344,6 +372,9 @@ def main():
         log("timing the one-window-per-launch path against the batched path")
         out["plain_vs_batched"] = plain_vs_batched(dev, spec, params)
         log("plain vs batched: " + json.dumps(out["plain_vs_batched"]))
+    log("small batch plan: eager launches vs graph replay")
+    out["graph_vs_eager"] = graph_vs_eager(dev, spec, params)
+    log("graph vs eager: " + json.dumps(out["graph_vs_eager"]))
     if not args.no_serving:
         log("serving: streamed subarrays, saturated rate and Poisson loads")
         out["serving"] = serving_latency()

@@ -33,6 +33,7 @@ FRINGE_STREAMING = 0x1
 FRINGE_DUMP_GRID = 0x2
 FRINGE_PROFILE = 0x4
 FRINGE_PLAIN = 0x8
+FRINGE_GRAPH = 0x10
 
 ENTRY_POINTS = (
     "fringe_plan_check", "fringe_plan", "fringe_search", "candidates_get",

@@ -148,8 +148,10 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   if (!p->window_aps) return fail(FRINGE_E_INVALID, "window_aps is null");
   if (p->n_window_lengths < 1 || p->n_window_lengths > kMaxLevels)
     return fail(FRINGE_E_INVALID, "n_window_lengths must be in [1, %d]", kMaxLevels);
-  if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE | FRINGE_PLAIN))
+  if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE | FRINGE_PLAIN | FRINGE_GRAPH))
     return fail(FRINGE_E_INVALID, "unknown flag bits 0x%x", p->flags);
+  if ((p->flags & FRINGE_GRAPH) && (p->flags & (FRINGE_STREAMING | FRINGE_PROFILE | FRINGE_PLAIN)))
+    return fail(FRINGE_E_INVALID, "FRINGE_GRAPH is for batch plans without FRINGE_PROFILE or FRINGE_PLAIN");
   if ((p->flags & FRINGE_STREAMING) && (p->flags & FRINGE_DUMP_GRID))
     return fail(FRINGE_E_INVALID, "FRINGE_DUMP_GRID is for batch plans only");
   if ((p->flags & FRINGE_PLAIN) && (p->flags & (FRINGE_STREAMING | FRINGE_DUMP_GRID)))
@@ -408,6 +410,11 @@ struct fringe_plan_s {
   char* d_arena[2] = {nullptr, nullptr};
   hipEvent_t arena_free[2] = {nullptr, nullptr};
   int arena_last = -1;
+  // FRINGE_GRAPH: the device work of a search captured on a private stream,
+  // replayed while the descriptor tables (hence every pointer) are unchanged
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_arena = -1;
   // streaming
   std::vector<StreamState> streams;
   std::vector<CallScan> call;      // numbering of the last search
@@ -437,6 +444,8 @@ void release(fringe_plan_t p) {
     if (p->h_arena[k]) (void)hipHostFree(p->h_arena[k]);
     if (p->arena_free[k]) (void)hipEventDestroy(p->arena_free[k]);
   }
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
   if (p->h_total) (void)hipHostFree(p->h_total);
   if (p->h_cands) (void)hipHostFree(p->h_cands);
   for (auto ev : p->prof_ev) (void)hipEventDestroy(ev);
@@ -600,12 +609,14 @@ ArenaLayout arena_layout(const Sizing& z, size_t n_entries) {
 
 // Upload the host tables into a device arena (unless they equal the last
 // upload) and return its index.
-int upload_tables(fringe_plan_s* p, hipStream_t st, int* k_out) {
+int upload_tables(fringe_plan_s* p, hipStream_t st, int* k_out, bool* uploaded) {
   hipError_t he;
+  *uploaded = false;
   if (p->arena_last >= 0 && p->tables == p->last_upload) {
     *k_out = p->arena_last;
     return FRINGE_OK;
   }
+  *uploaded = true;
   const int k = p->arena_last < 0 ? 0 : (p->arena_last ^ 1);
   if ((he = hipEventSynchronize(p->arena_free[k])) != hipSuccess)
     return hip_fail(he, "descriptor staging");
@@ -780,7 +791,9 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
        (he = hipHostMalloc(reinterpret_cast<void**>(&p->h_cands),
                            size_t(p->n_prefetch) * sizeof(fringe_candidate), hipHostMallocDefault)) !=
            hipSuccess) ||
-      (he = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) {
+      (he = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess ||
+      ((params->flags & FRINGE_GRAPH) &&
+       (he = hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking)) != hipSuccess)) {
     release(p);
     return hip_fail(he, "plan host resources");
   }
@@ -863,15 +876,20 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     }
   }
   int k = 0;
+  bool uploaded = false;
   {
-    const int rc = upload_tables(p, st, &k);
+    const int rc = upload_tables(p, st, &k, &uploaded);
     if (rc != FRINGE_OK) return rc;
   }
   char* arena = p->d_arena[k];
   p->d_scans = reinterpret_cast<ScanDev*>(arena + L.scans);
   const FusedArgs* d_fus = reinterpret_cast<const FusedArgs*>(arena + L.fused);
   const FinalizeArgs* d_fin = reinterpret_cast<const FinalizeArgs*>(arena + L.fin);
+  const hipStream_t user_st = st;
 
+  // Every kernel and copy of the search, enqueued on stream st (the caller's,
+  // or the capture stream of FRINGE_GRAPH).
+  auto enqueue = [&](hipStream_t st) -> int {
   if (plain) {
     for (int64_t i = 0; i < p->call_windows; ++i) {
       const FusedArgs& h = reinterpret_cast<const FusedArgs*>(p->tables.data() + L.fused)[i];
@@ -950,13 +968,47 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   ca.n_scans = ns;
   ca.lv = z.lv;
   FRINGE_TIMED(3, launch_compact(ca, st), "compaction launch");
-#undef FRINGE_TIMED
   if ((he = hipMemcpyAsync(p->h_total, p->d_total, sizeof(int64_t), hipMemcpyDeviceToHost, st)) !=
           hipSuccess ||
       (p->n_prefetch > 0 &&
        (he = hipMemcpyAsync(p->h_cands, p->cands, size_t(p->n_prefetch) * sizeof(fringe_candidate),
                             hipMemcpyDeviceToHost, st)) != hipSuccess))
     return hip_fail(he, "candidate prefetch");
+  return FRINGE_OK;
+  };
+#undef FRINGE_TIMED
+
+  st = user_st;
+  if (p->params.flags & FRINGE_GRAPH) {
+    // new tables (other inputs or a first search): capture the work anew
+    if (uploaded || !p->gexec || p->g_arena != k) {
+      if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+      }
+      if ((he = hipStreamBeginCapture(p->cap_st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(he, "hipStreamBeginCapture");
+      const int rc = enqueue(p->cap_st);
+      hipGraph_t graph = nullptr;
+      const hipError_t he_end = hipStreamEndCapture(p->cap_st, &graph);
+      if (rc != FRINGE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (he_end != hipSuccess) return hip_fail(he_end, "hipStreamEndCapture");
+      he = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (he != hipSuccess) {
+        p->gexec = nullptr;
+        return hip_fail(he, "hipGraphInstantiate");
+      }
+      p->g_arena = k;
+    }
+    if ((he = hipGraphLaunch(p->gexec, st)) != hipSuccess) return hip_fail(he, "hipGraphLaunch");
+  } else {
+    const int rc = enqueue(st);
+    if (rc != FRINGE_OK) return rc;
+  }
   if ((he = hipEventRecord(p->done, st)) != hipSuccess ||
       (he = hipEventRecord(p->arena_free[k], st)) != hipSuccess)
     return hip_fail(he, "hipEventRecord");

@@ -117,6 +117,17 @@ def test_plain_flag_rules():
     assert _code(lambda: F.fringe_plan_check([c1], [4], flags=B.FRINGE_PLAIN | B.FRINGE_STREAMING)) == B.FRINGE_E_INVALID
 
 
+def test_graph_flag_rules():
+    """FRINGE_GRAPH is for batch plans: not with streaming, profiling or the
+    one-window-per-launch path."""
+    c1 = dict(n_baselines=1, n_ap=64, n_if=2, n_chan=16, ap_seconds=1.0, chan_width_hz=1 / 32)
+    assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_GRAPH)["n_windows"] == 31
+    assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_GRAPH | B.FRINGE_DUMP_GRID)["n_windows"] == 31
+    for other in (B.FRINGE_STREAMING, B.FRINGE_PROFILE, B.FRINGE_PLAIN):
+        assert _code(lambda: F.fringe_plan_check([c1], [4], flags=B.FRINGE_GRAPH | other)) == B.FRINGE_E_INVALID
+    assert _code(lambda: F.fringe_plan_check([c1], [4], flags=0x20)) == B.FRINGE_E_INVALID
+
+
 def test_streaming_sizing():
     # a 976-AP chunk of a 12-station subarray: windows ending in the chunk
     sub = dict(n_baselines=66, n_ap=976, n_if=8, n_chan=32, ap_seconds=1.024e-3, chan_width_hz=0.5e6)
