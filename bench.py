@@ -130,11 +130,12 @@ def plain_vs_batched(dev, spec, params, n_bl=3, n_ap=4096, reps=5):
     return out
 
 
-def graph_vs_eager(dev, spec, params, n_bl=15, n_ap=976, reps=200):
+def graph_vs_eager(dev, spec, params, n_bl=15, n_ap=976, rounds=6, reps=50):
     """Per-search latency (search + candidates on the host) of a small batch
-    plan, launched eagerly and replayed from its HIP graph (FRINGE_GRAPH):
-    baselines 0..n_bl-1 x APs 0..n_ap-1 of the resident scan (one 1 s chunk
-    of a 6-station subarray's worth of baselines)."""
+    plan launched eagerly and replayed from its HIP graph (FRINGE_GRAPH), on
+    baselines 0..n_bl-1 x APs 0..n_ap-1 of the resident scan (a 1 s chunk of
+    a 6-station array).  Both plans stay alive and are timed in alternating
+    rounds; the medians of the rounds are reported."""
     import torch
 
     import paper_2108_05602_amd as F
@@ -143,18 +144,29 @@ def graph_vs_eager(dev, spec, params, n_bl=15, n_ap=976, reps=200):
     st = torch.cuda.current_stream()
     kw = dict(pad_freq=params["pad_freq"], pad_time=params["pad_time"],
               snr_threshold=params["snr_threshold"], max_candidates=1 << 16)
-    out = {"subset": f"baselines 0-{n_bl - 1} x APs 0-{n_ap - 1} of the same scan", "reps": reps}
-    for name, flags in (("eager", 0), ("graph", F.FRINGE_GRAPH)):
-        with F.Plan([desc], params["window_aps"], flags=flags, **kw) as plan:
+    plans = {"eager": F.Plan([desc], params["window_aps"], **kw),
+             "graph": F.Plan([desc], params["window_aps"], flags=F.FRINGE_GRAPH, **kw)}
+    times = {k: [] for k in plans}
+    try:
+        for plan in plans.values():
             for _ in range(3):
                 plan.search([sub.data_ptr()], st.cuda_stream)
                 plan.candidates()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                plan.search([sub.data_ptr()], st.cuda_stream)
-                plan.candidates()
-            out[name + "_us"] = (time.perf_counter() - t0) / reps * 1e6
+        for _ in range(rounds):
+            for name, plan in plans.items():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    plan.search([sub.data_ptr()], st.cuda_stream)
+                    plan.candidates()
+                times[name].append((time.perf_counter() - t0) / reps * 1e6)
+    finally:
+        for plan in plans.values():
+            plan.close()
+    out = {"subset": f"baselines 0-{n_bl - 1} x APs 0-{n_ap - 1} of the same scan",
+           "rounds": rounds, "reps_per_round": reps}
+    for name, ts in times.items():
+        out[name + "_us"] = float(np.median(ts))
     return out
 
 

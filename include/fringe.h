@@ -59,12 +59,12 @@ extern "C" {
 #define FRINGE_PROFILE    0x4u   /* time every kernel launch with HIP events       */
 #define FRINGE_PLAIN      0x8u   /* one window per launch (a baseline for timing;  */
                                  /* batch plans with windows of at most 64 APs)    */
-#define FRINGE_GRAPH      0x10u  /* batch plans: capture a search's kernels and    */
-                                 /* copies in a HIP graph on a private stream and  */
-                                 /* replay it while the inputs (the d_vis pointers */
-                                 /* and so every descriptor) are those of the      */
-                                 /* captured search; new inputs are captured anew. */
-                                 /* Not with STREAMING, PROFILE or PLAIN.          */
+#define FRINGE_GRAPH      0x10u  /* batch plans: capture a search's kernels in a  */
+                                 /* HIP graph on a private stream, and replay it   */
+                                 /* while the inputs (the d_vis pointers, so every */
+                                 /* descriptor) are those of the captured search;  */
+                                 /* new inputs are captured anew.  Not with        */
+                                 /* STREAMING, PROFILE or PLAIN.                   */
 
 /* One complex64 sample, identical in layout to torch.complex64 / numpy.complex64. */
 typedef struct { float re, im; } fringe_cf32;

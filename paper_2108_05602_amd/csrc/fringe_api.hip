@@ -887,8 +887,8 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   const FinalizeArgs* d_fin = reinterpret_cast<const FinalizeArgs*>(arena + L.fin);
   const hipStream_t user_st = st;
 
-  // Every kernel and copy of the search, enqueued on stream st (the caller's,
-  // or the capture stream of FRINGE_GRAPH).
+  // Every kernel of the search, enqueued on stream st (the caller's, or the
+  // capture stream of FRINGE_GRAPH).
   auto enqueue = [&](hipStream_t st) -> int {
   if (plain) {
     for (int64_t i = 0; i < p->call_windows; ++i) {
@@ -968,12 +968,6 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   ca.n_scans = ns;
   ca.lv = z.lv;
   FRINGE_TIMED(3, launch_compact(ca, st), "compaction launch");
-  if ((he = hipMemcpyAsync(p->h_total, p->d_total, sizeof(int64_t), hipMemcpyDeviceToHost, st)) !=
-          hipSuccess ||
-      (p->n_prefetch > 0 &&
-       (he = hipMemcpyAsync(p->h_cands, p->cands, size_t(p->n_prefetch) * sizeof(fringe_candidate),
-                            hipMemcpyDeviceToHost, st)) != hipSuccess))
-    return hip_fail(he, "candidate prefetch");
   return FRINGE_OK;
   };
 #undef FRINGE_TIMED
@@ -1009,6 +1003,13 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     const int rc = enqueue(st);
     if (rc != FRINGE_OK) return rc;
   }
+  // the count and the first records to pinned host memory
+  if ((he = hipMemcpyAsync(p->h_total, p->d_total, sizeof(int64_t), hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (p->n_prefetch > 0 &&
+       (he = hipMemcpyAsync(p->h_cands, p->cands, size_t(p->n_prefetch) * sizeof(fringe_candidate),
+                            hipMemcpyDeviceToHost, st)) != hipSuccess))
+    return hip_fail(he, "candidate prefetch");
   if ((he = hipEventRecord(p->done, st)) != hipSuccess ||
       (he = hipEventRecord(p->arena_free[k], st)) != hipSuccess)
     return hip_fail(he, "hipEventRecord");
