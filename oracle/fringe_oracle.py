@@ -25,10 +25,16 @@ its phase model Eq. (1); section "Code optimization", steps 5 and 6; section
   exceeds the threshold.  Windows of length W start every max(1, W // 2) APs;
   a tail shorter than W is dropped.
 
-Readings of points the paper leaves open (all channels are summed, IF
-calibration terms are zero, the rate axis and its padding, the stride, the
-SNR normalisation, tie-breaking, the all-zero window) are the ones listed in
-the design notes; each function below names the passage it follows.
+The delay-only search (the paper's own scheme, without a rate axis) takes
+the same steps on the single row k_t = 0: the window's APs summed
+coherently, one zero-padded delay transform, the peak over the delay axis,
+E = the mean power over that axis (delay_only_row).
+
+Readings of points the paper leaves open: all channels are summed, IF
+calibration terms are zero, the rate axis has its own zero padding, windows
+overlap by half, SNR is the peak amplitude over the root of the mean grid
+power, ties go to the lowest flat index, an all-zero window has peak (0, 0)
+and SNR 0.  Each function below names the passage it follows.
 """
 
 from __future__ import annotations
@@ -49,6 +55,8 @@ __all__ = [
     "signed_bin",
     "WindowResult",
     "search_window",
+    "delay_only_row",
+    "search_window_delay_only",
     "search_baseline",
     "search_scan",
     "TABLE_DTYPE",
@@ -183,6 +191,34 @@ def search_window(x_b: np.ndarray, t0: int, window_ap: int,
     return grid_peak(g, duplicate_rate_rows=(window_ap == 1 and pad_time > 1))
 
 
+def delay_only_row(x_seg: np.ndarray, pad_freq: int) -> np.ndarray:
+    """The paper's own search function of one window, without a rate axis:
+
+        G_0[k_f] = sum_{f<F} (sum_{u<W} x[u, f]) exp(-2 pi i k_f f / M_f),
+
+    the window's APs summed coherently and transformed along frequency with
+    the zero padding of the delay transform.  Paper: section "Code
+    optimization", step 6 (the APs of a window summed, then the maximum
+    amplitude along the delay axis) with step 5 and the padding of section
+    "Fringe fitting".  x_seg has shape (W, F); the result has shape (1, M_f)
+    so that grid_peak applies unchanged (its mean power is then the mean
+    over the delay axis, = sum_f |sum_u x[u, f]|^2 by Parseval).
+    """
+    x_seg = np.asarray(x_seg, dtype=np.complex128)
+    n_freq = x_seg.shape[1]
+    s = x_seg.sum(axis=0)
+    return (s @ delay_dft_matrix(n_freq, pad_freq * n_freq))[None, :]
+
+
+def search_window_delay_only(x_b: np.ndarray, t0: int, window_ap: int,
+                             pad_freq: int) -> WindowResult:
+    """One window of the delay-only search (rate bin 0 only)."""
+    seg = np.asarray(x_b[t0:t0 + window_ap])
+    if seg.shape[0] != window_ap:
+        raise ValueError("window runs past the end of the data")
+    return grid_peak(delay_only_row(seg, pad_freq))
+
+
 TABLE_DTYPE = np.dtype([
     ("scan", np.int32), ("baseline", np.int32), ("window_ap", np.int32),
     ("t_start", np.int32), ("k_rate", np.int32), ("k_delay", np.int32),
@@ -194,17 +230,29 @@ TABLE_DTYPE = np.dtype([
 
 def search_baseline(x_b: np.ndarray, window_aps, pad_freq: int, pad_time: int,
                     ap_seconds: float, chan_width_hz: float,
-                    scan: int = 0, baseline: int = 0) -> np.ndarray:
+                    scan: int = 0, baseline: int = 0,
+                    delay_only: bool = False) -> np.ndarray:
     """Every window of one baseline, in (window length, start) order.
 
     The delay transform is done once per AP and shared by all windows
     (section "Code optimization": step 5 once, step 6 per window size).
+    With delay_only, every window is searched by delay_only_row (rate bin 0,
+    pad_time unused).
     """
     x_b = np.asarray(x_b)
     n_ap, n_freq = x_b.shape
     m_f = pad_freq * n_freq
-    y = delay_spectra(x_b, pad_freq)
     rows = []
+    if delay_only:
+        for w in sorted(int(v) for v in window_aps):
+            for t0 in window_starts(n_ap, w):
+                r = search_window_delay_only(x_b, int(t0), w, pad_freq)
+                rows.append((scan, baseline, w, int(t0), r.k_rate, r.k_delay,
+                             r.amp, r.snr, r.energy,
+                             signed_bin(r.k_delay, m_f) / (m_f * chan_width_hz), 0.0,
+                             r.margin))
+        return np.array(rows, dtype=TABLE_DTYPE)
+    y = delay_spectra(x_b, pad_freq)
     for w in sorted(int(v) for v in window_aps):
         m_t = pad_time * w
         a_t = rate_dft_matrix(w, m_t)
@@ -221,7 +269,7 @@ def search_baseline(x_b: np.ndarray, window_aps, pad_freq: int, pad_time: int,
 
 def search_scan(vis: np.ndarray, window_aps, pad_freq: int, pad_time: int,
                 snr_threshold: float, ap_seconds: float, chan_width_hz: float,
-                scan: int = 0, baselines=None):
+                scan: int = 0, baselines=None, delay_only: bool = False):
     """Full search of one scan.
 
     vis has shape (B, T, n_if, n_chan) (or (B, T, F)); the frequency index
@@ -236,7 +284,8 @@ def search_scan(vis: np.ndarray, window_aps, pad_freq: int, pad_time: int,
     if baselines is None:
         baselines = range(b_count)
     tables = [search_baseline(flat[b], window_aps, pad_freq, pad_time,
-                              ap_seconds, chan_width_hz, scan=scan, baseline=b)
+                              ap_seconds, chan_width_hz, scan=scan, baseline=b,
+                              delay_only=delay_only)
               for b in baselines]
     table = np.concatenate(tables) if tables else np.zeros(0, TABLE_DTYPE)
     cands = table[table["snr"] > snr_threshold]

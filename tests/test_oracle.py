@@ -127,8 +127,75 @@ def check_window_counts(mod):
     assert len(mod.window_starts(3, 4)) == 0
 
 
+def _c1_fringe_phasor_sum(t0, w):
+    """sum of exp(i pi (t - 20) / 4) over the fringe APs 20..23 inside the
+    window [t0, t0 + w): the 64-AP workload's fringe advances by half a rate
+    bin (of 4 APs) per AP, i.e. by pi/4."""
+    t = np.arange(max(t0, 20), min(t0 + w, 24))
+    return complex(np.sum(np.exp(1j * np.pi * (t - 20) / 4)))
+
+
+def check_delay_only_closed_form(mod):
+    """Delay-only search of the noise-free 64-AP workload, from the closed
+    form: the coherent sum of a window's fringe APs is 0.5 * C per channel
+    (C = sum of the APs' phasors), on delay bin 13 exactly, so
+    amp = F * 0.5 * |C|, E = F * 0.25 * |C|^2 and SNR = sqrt(F) = sqrt(32);
+    windows without fringe APs are all-zero.  (The workload is stored in
+    complex64, hence the 1e-6 tolerance.)"""
+    spec = synth.c1(noise=False)
+    v = spec.full()
+    table, cands = mod.search_scan(v, [4], 4, 2, 3.0, spec.ap_seconds, spec.chan_width_hz,
+                                   delay_only=True)
+    assert len(table) == 31
+    for row in table:
+        c = _c1_fringe_phasor_sum(int(row["t_start"]), 4)
+        assert row["k_rate"] == 0 and row["rate_hz"] == 0.0
+        if abs(c) == 0.0:
+            assert (row["k_delay"], row["amp"], row["snr"], row["energy"]) == (0, 0.0, 0.0, 0.0)
+            continue
+        assert row["k_delay"] == 13
+        assert row["amp"] == pytest.approx(32 * 0.5 * abs(c), rel=1e-6)
+        assert row["energy"] == pytest.approx(32 * 0.25 * abs(c) ** 2, rel=1e-6)
+        assert row["snr"] == pytest.approx(math.sqrt(32), rel=1e-6)
+    # windows 18, 20, 22 overlap the fringe; |C| = 2 cos(pi/8) for two APs,
+    # |sin(pi/2) / sin(pi/8)| for all four
+    assert [int(t) for t in cands["t_start"]] == [18, 20, 22]
+    assert cands["amp"][1] == pytest.approx(16 / math.sin(math.pi / 8), rel=1e-6)
+    assert cands["amp"][0] == pytest.approx(32 * math.cos(math.pi / 8), rel=1e-6)
+
+
+def check_delay_only_library(mod):
+    """The delay-only row equals numpy's FFT of the coherent AP sum, and the
+    rate-0 row of the full grid; its mean power is sum_f |sum_u x|^2."""
+    rng = np.random.default_rng(17)
+    for w, f, pf in [(1, 8, 4), (2, 16, 4), (4, 32, 2), (8, 8, 1), (3, 5, 4)]:
+        x = _rand_x(rng, w, f)
+        row = mod.delay_only_row(x, pf)
+        ref = np.fft.fft(x.sum(axis=0), n=pf * f)
+        assert row.shape == (1, pf * f)
+        assert np.allclose(row[0], ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+        r = mod.search_window_delay_only(x, 0, w, pf)
+        assert r.energy == pytest.approx(float(np.sum(np.abs(x.sum(axis=0)) ** 2)), rel=1e-12)
+        assert r.k_rate == 0 and r.k_delay == int(np.argmax(np.abs(ref) ** 2))
+
+
+def check_delay_only_on_grid(mod):
+    """A unit fringe on delay bin b with arbitrary per-AP phasors a_u peaks
+    at b with amp = F |sum a_u| and SNR = sqrt(F) exactly."""
+    rng = np.random.default_rng(23)
+    for w, f, pf, b in [(4, 32, 4, 50), (8, 16, 2, 7), (2, 64, 1, 33)]:
+        a = np.exp(2j * np.pi * rng.random(w)) * rng.uniform(0.5, 1.5, w)
+        ff = np.arange(f)[None, :]
+        x = a[:, None] * np.exp(2j * np.pi * b * ff / (pf * f))
+        r = mod.search_window_delay_only(x, 0, w, pf)
+        assert r.k_delay == b
+        assert r.amp == pytest.approx(f * abs(a.sum()), rel=1e-12)
+        assert r.snr == pytest.approx(math.sqrt(f), rel=1e-12)
+
+
 ALL_CHECKS = [check_c1_closed_form, check_library_fft, check_parseval_and_energy,
-              check_on_grid_fringe, check_ties_and_zero, check_window_counts]
+              check_on_grid_fringe, check_ties_and_zero, check_window_counts,
+              check_delay_only_closed_form, check_delay_only_library, check_delay_only_on_grid]
 
 
 @pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda c: c.__name__)
@@ -170,6 +237,26 @@ def test_noise_max_fisher_g():
         gs.append(r.snr ** 2 / m)
     p = stats.kstest(gs, lambda v: np.array([1.0 - _fisher_g_sf(t, m) if t > 0 else 0.0
                                              for t in np.atleast_1d(v)])).pvalue
+    assert p > 1e-3
+
+
+def test_delay_only_noise_laws():
+    """Noise only, delay-only search: at a fixed delay bin SNR^2 / F ~
+    Beta(1, F-1) for any padding and window length (the coherent sum of W
+    complex Gaussian APs is again one), and unpadded the maximum follows
+    Fisher's g for F ordinates.  KS over 2000 seeds each."""
+    w, f = 3, 8
+    bins, maxes = [], []
+    for s in range(2000):
+        x = _rand_x(np.random.default_rng([456, s]), w, f)
+        row = fo.delay_only_row(x, 4)[0]
+        e = float(np.mean(np.abs(row) ** 2))
+        bins.append(abs(row[5]) ** 2 / e / f)
+        r = fo.search_window_delay_only(x, 0, w, 1)
+        maxes.append(r.snr ** 2 / f)
+    assert stats.kstest(bins, stats.beta(1, f - 1).cdf).pvalue > 1e-3
+    p = stats.kstest(maxes, lambda v: np.array([1.0 - _fisher_g_sf(t, f) if t > 0 else 0.0
+                                                for t in np.atleast_1d(v)])).pvalue
     assert p > 1e-3
 
 
@@ -249,7 +336,8 @@ def _mutant(**overrides):
     m.__dict__.update(overrides)
     # rebind functions so their globals see the overrides
     for name in ("delay_spectra", "window_grid", "search_window", "search_baseline",
-                 "search_scan", "window_starts", "grid_peak"):
+                 "search_scan", "window_starts", "grid_peak", "delay_only_row",
+                 "search_window_delay_only"):
         f = getattr(fo, name)
         if name in overrides:
             continue
@@ -303,14 +391,33 @@ def _transposed_freq(x_b, pad_freq):
     return fo.delay_spectra(x_b.reshape(t, 2, f // 2).transpose(0, 2, 1).reshape(t, f), pad_freq)
 
 
+def _delay_only_incoherent(x_seg, pad_freq):
+    # per-AP power spectra summed (an incoherent search), not the coherent sum
+    x_seg = np.asarray(x_seg, complex)
+    spec = x_seg @ fo.delay_dft_matrix(x_seg.shape[1], pad_freq * x_seg.shape[1])
+    return np.sqrt(np.sum(np.abs(spec) ** 2, axis=0))[None, :].astype(complex)
+
+
+def _delay_only_grid_energy(x_b, t0, window_ap, pad_freq):
+    # E taken as the full grid's (sum of |x|^2) instead of the delay row's
+    r = fo.search_window_delay_only(x_b, t0, window_ap, pad_freq)
+    e = float(np.sum(np.abs(np.asarray(x_b[t0:t0 + window_ap])) ** 2))
+    r.energy = e
+    r.snr = r.amp / math.sqrt(e) if e > 0 else 0.0
+    return r
+
+
 @pytest.mark.parametrize("overrides", [
+    dict(delay_only_row=_delay_only_incoherent),
+    dict(search_window_delay_only=_delay_only_grid_energy),
     dict(delay_dft_matrix=_flip_sign_delay),
     dict(rate_dft_matrix=_rate_no_pad),
     dict(grid_peak=_peak_sum_energy),
     dict(grid_peak=_peak_last_tie),
     dict(window_starts=_starts_full_stride),
     dict(delay_spectra=_transposed_freq),
-], ids=["delay-sign", "rate-pad", "energy-sum", "tie-last", "stride", "freq-order"])
+], ids=["delay-only-incoherent", "delay-only-grid-energy", "delay-sign", "rate-pad",
+        "energy-sum", "tie-last", "stride", "freq-order"])
 def test_planted_mistake_is_caught(overrides):
     assert _fails(_mutant(**overrides))
 
