@@ -130,6 +130,42 @@ def plain_vs_batched(dev, spec, params, n_bl=3, n_ap=4096, reps=5):
     return out
 
 
+def delay_only_leg(dev, spec, params, steps=5):
+    """The paper's own delay-only search (FRINGE_DELAY_ONLY: rate bin 0, the
+    APs of each window summed, the peak over the delay axis) on the same
+    resident scan and windows: windows/s and its kernel's time."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    st = torch.cuda.current_stream()
+    with F.Plan([spec.desc()], params["window_aps"], pad_freq=params["pad_freq"],
+                pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],
+                max_candidates=1 << 20, flags=F.FRINGE_DELAY_ONLY | F.FRINGE_PROFILE) as plan:
+        n_win = plan.info()["n_windows"]
+        for _ in range(2):
+            plan.search([dev.data_ptr()], st.cuda_stream)
+            plan.candidates()
+        torch.cuda.synchronize()
+        kern = 0.0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.search([dev.data_ptr()], st.cuda_stream)
+            c = plan.candidates()
+            kern += plan.profile()["rate_ms"]
+        dt = (time.perf_counter() - t0) / steps
+    m_f = params["pad_freq"] * spec.n_freq
+    # algorithmic work: the delay FFT of every AP, W - 1 complex adds and the
+    # power, max and power sum of each window's M_f bins
+    flops = spec.n_baselines * spec.n_ap * 5.0 * m_f * math.log2(m_f)
+    for w, s_, n in window_levels(spec.n_ap, params["window_aps"]):
+        flops += spec.n_baselines * n * m_f * (2.0 * (w - 1) + 5.0)
+    k_ms = kern / steps
+    return {"windows_per_s": n_win / dt, "ms_per_step": dt * 1e3, "kernel_ms": k_ms,
+            "kernel_tflops_algorithmic": flops / (k_ms * 1e-3) / 1e12,
+            "kernel_hbm_gbs_algorithmic": spec.nbytes() / (k_ms * 1e-3) / 1e9,
+            "candidates": int(len(c))}
+
+
 def graph_vs_eager(dev, spec, params, n_bl=15, n_ap=976, rounds=6, reps=50):
     """Per-search latency (search + candidates on the host) of a small batch
     plan launched eagerly and replayed from its HIP graph (FRINGE_GRAPH), on
@@ -384,6 +420,9 @@ def main():
         log("timing the one-window-per-launch path against the batched path")
         out["plain_vs_batched"] = plain_vs_batched(dev, spec, params)
         log("plain vs batched: " + json.dumps(out["plain_vs_batched"]))
+    log("delay-only search of the same scan")
+    out["delay_only"] = delay_only_leg(dev, spec, params)
+    log("delay-only: " + json.dumps(out["delay_only"]))
     log("small batch plan: eager launches vs graph replay")
     out["graph_vs_eager"] = graph_vs_eager(dev, spec, params)
     log("graph vs eager: " + json.dumps(out["graph_vs_eager"]))

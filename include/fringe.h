@@ -65,6 +65,13 @@ extern "C" {
                                  /* descriptor) are those of the captured search;  */
                                  /* new inputs are captured anew.  Not with        */
                                  /* STREAMING, PROFILE or PLAIN.                   */
+#define FRINGE_DELAY_ONLY 0x20u  /* the paper's delay-only search (section "Code   */
+                                 /* optimization", step 6): per window the APs'    */
+                                 /* spectra summed coherently, the peak over the   */
+                                 /* M_f delay bins of rate bin 0 and E = the mean  */
+                                 /* power over those bins; k_rate = 0, rate_hz = 0 */
+                                 /* and pad_time unused.  Windows of at most 64    */
+                                 /* APs; not with DUMP_GRID.                       */
 
 /* One complex64 sample, identical in layout to torch.complex64 / numpy.complex64. */
 typedef struct { float re, im; } fringe_cf32;

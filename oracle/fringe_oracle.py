@@ -191,7 +191,7 @@ def search_window(x_b: np.ndarray, t0: int, window_ap: int,
     return grid_peak(g, duplicate_rate_rows=(window_ap == 1 and pad_time > 1))
 
 
-def delay_only_row(x_seg: np.ndarray, pad_freq: int) -> np.ndarray:
+def delay_only_row(x_seg: np.ndarray, pad_freq: int, a_f=None) -> np.ndarray:
     """The paper's own search function of one window, without a rate axis:
 
         G_0[k_f] = sum_{f<F} (sum_{u<W} x[u, f]) exp(-2 pi i k_f f / M_f),
@@ -202,21 +202,24 @@ def delay_only_row(x_seg: np.ndarray, pad_freq: int) -> np.ndarray:
     amplitude along the delay axis) with step 5 and the padding of section
     "Fringe fitting".  x_seg has shape (W, F); the result has shape (1, M_f)
     so that grid_peak applies unchanged (its mean power is then the mean
-    over the delay axis, = sum_f |sum_u x[u, f]|^2 by Parseval).
+    over the delay axis, = sum_f |sum_u x[u, f]|^2 by Parseval).  a_f, if
+    given, is delay_dft_matrix(F, M_f), built once by the caller.
     """
     x_seg = np.asarray(x_seg, dtype=np.complex128)
     n_freq = x_seg.shape[1]
+    if a_f is None:
+        a_f = delay_dft_matrix(n_freq, pad_freq * n_freq)
     s = x_seg.sum(axis=0)
-    return (s @ delay_dft_matrix(n_freq, pad_freq * n_freq))[None, :]
+    return (s @ a_f)[None, :]
 
 
 def search_window_delay_only(x_b: np.ndarray, t0: int, window_ap: int,
-                             pad_freq: int) -> WindowResult:
+                             pad_freq: int, a_f=None) -> WindowResult:
     """One window of the delay-only search (rate bin 0 only)."""
     seg = np.asarray(x_b[t0:t0 + window_ap])
     if seg.shape[0] != window_ap:
         raise ValueError("window runs past the end of the data")
-    return grid_peak(delay_only_row(seg, pad_freq))
+    return grid_peak(delay_only_row(seg, pad_freq, a_f))
 
 
 TABLE_DTYPE = np.dtype([
@@ -244,9 +247,10 @@ def search_baseline(x_b: np.ndarray, window_aps, pad_freq: int, pad_time: int,
     m_f = pad_freq * n_freq
     rows = []
     if delay_only:
+        a_f = delay_dft_matrix(n_freq, m_f)
         for w in sorted(int(v) for v in window_aps):
             for t0 in window_starts(n_ap, w):
-                r = search_window_delay_only(x_b, int(t0), w, pad_freq)
+                r = search_window_delay_only(x_b, int(t0), w, pad_freq, a_f)
                 rows.append((scan, baseline, w, int(t0), r.k_rate, r.k_delay,
                              r.amp, r.snr, r.energy,
                              signed_bin(r.k_delay, m_f) / (m_f * chan_width_hz), 0.0,

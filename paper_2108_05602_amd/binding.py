@@ -34,6 +34,7 @@ FRINGE_DUMP_GRID = 0x2
 FRINGE_PROFILE = 0x4
 FRINGE_PLAIN = 0x8
 FRINGE_GRAPH = 0x10
+FRINGE_DELAY_ONLY = 0x20
 
 ENTRY_POINTS = (
     "fringe_plan_check", "fringe_plan", "fringe_search", "candidates_get",

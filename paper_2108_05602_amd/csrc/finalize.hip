@@ -1,8 +1,8 @@
 // Window results and candidate list.
 //
 // finalize: per window, the max of the bin-block peak keys (window_key.h),
-//   the window
-//   energy E = sum of its APs' energies (= mean |G|^2 by Parseval),
+//   the window energy E = sum of its APs' energies (= mean |G|^2 by
+//   Parseval; delay-only: the classes' sums of |G_0|^2 over M_f),
 //   amp = sqrt(P_peak), SNR = amp / sqrt(E) (0 when E = 0).
 // compact: the windows with SNR > threshold (paper, section "Detection
 //   rate") in window-id order, i.e. sorted by (scan, baseline, window
@@ -38,12 +38,21 @@ __global__ void __launch_bounds__(256) finalize_kernel(const FinalizeArgs* __res
   while (li + 1 < a.lv.n && rem >= a.lvl_off[li + 1]) ++li;
   const int j = rem - a.lvl_off[li] + a.lvl_j0[li];
   const int t0 = j * a.lv.s[li];
-  const float* eb = a.e + static_cast<int64_t>(b) * a.T + t0;
   double energy = 0.0;
-  for (int u = 0; u < a.lv.W[li]; ++u) energy += eb[u];
-  // key = (rate key << 32) | (0xFFFFFFFF - k_f); rate key = power bits
-  // with the low log2(M_t) bits replaced by M_t - 1 - k_t
-  const uint32_t mask = static_cast<uint32_t>(a.pad_t * a.lv.W[li] - 1);
+  uint32_t mask = 0;
+  if (a.epart) {
+    // delay-only: mean over the M_f delay bins of |G_0|^2 from the classes'
+    // sums; the key is the power itself (rate bin 0)
+    for (int kb = 0; kb < a.n_kb; ++kb)
+      energy += a.epart[static_cast<int64_t>(kb) * a.slab_windows + w];
+    energy /= a.M;
+  } else {
+    const float* eb = a.e + static_cast<int64_t>(b) * a.T + t0;
+    for (int u = 0; u < a.lv.W[li]; ++u) energy += eb[u];
+    // key = (rate key << 32) | (0xFFFFFFFF - k_f); rate key = power bits
+    // with the low log2(M_t) bits replaced by M_t - 1 - k_t
+    mask = static_cast<uint32_t>(a.pad_t * a.lv.W[li] - 1);
+  }
   const uint32_t hi = static_cast<uint32_t>(key >> 32);
   const float p = __uint_as_float(hi & ~mask);
   const uint32_t k_t = mask - (hi & mask);

@@ -128,17 +128,22 @@ struct Sizing {
   int align = 1;                      // streaming: stage origins are multiples of this
   int64_t n_windows = 0;              // windows of one call, at most
   int64_t n_blocks = 0;
-  uint64_t scratch_x = 0, scratch_e = 0, scratch_part = 0, stage_bytes = 0;
+  bool delay_only = false;            // FRINGE_DELAY_ONLY: rate bin 0 only
+  uint64_t scratch_x = 0, scratch_e = 0, scratch_part = 0, scratch_epart = 0, stage_bytes = 0;
   uint64_t table_bytes = 0, blk_bytes = 0, cand_bytes = 0, grid_bytes = 0, fixed_bytes = 0;
   uint64_t total = 0;
 };
 
 int data_len(const ScanInfo& s, bool streaming) { return streaming ? s.stage_len : s.d.n_ap; }
 
-uint64_t per_baseline_scratch(const ScanInfo& s, bool fused, bool streaming) {
+// Bytes per window and delay-bin class: the peak key, and with the
+// delay-only search the class's power sum.
+size_t part_bytes(bool delay_only) { return sizeof(uint64_t) + (delay_only ? sizeof(float) : 0); }
+
+uint64_t per_baseline_scratch(const ScanInfo& s, bool fused, bool streaming, bool delay_only) {
   const uint64_t t = uint64_t(data_len(s, streaming));
   const uint64_t x = fused ? 0 : t * s.M * sizeof(float2);
-  return x + t * sizeof(float) + uint64_t(s.n_kb) * s.nwb_max * sizeof(uint64_t);
+  return x + t * sizeof(float) + uint64_t(s.n_kb) * s.nwb_max * part_bytes(delay_only);
 }
 
 int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* p,
@@ -148,8 +153,11 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   if (!p->window_aps) return fail(FRINGE_E_INVALID, "window_aps is null");
   if (p->n_window_lengths < 1 || p->n_window_lengths > kMaxLevels)
     return fail(FRINGE_E_INVALID, "n_window_lengths must be in [1, %d]", kMaxLevels);
-  if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE | FRINGE_PLAIN | FRINGE_GRAPH))
+  if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE | FRINGE_PLAIN | FRINGE_GRAPH |
+                   FRINGE_DELAY_ONLY))
     return fail(FRINGE_E_INVALID, "unknown flag bits 0x%x", p->flags);
+  if ((p->flags & FRINGE_DELAY_ONLY) && (p->flags & FRINGE_DUMP_GRID))
+    return fail(FRINGE_E_INVALID, "FRINGE_DELAY_ONLY has no grid to dump");
   if ((p->flags & FRINGE_GRAPH) && (p->flags & (FRINGE_STREAMING | FRINGE_PROFILE | FRINGE_PLAIN)))
     return fail(FRINGE_E_INVALID, "FRINGE_GRAPH is for batch plans without FRINGE_PROFILE or FRINGE_PLAIN");
   if ((p->flags & FRINGE_STREAMING) && (p->flags & FRINGE_DUMP_GRID))
@@ -182,6 +190,10 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   for (int i = sz.lv.n; i < kMaxLevels; ++i) sz.lv.W[i] = sz.lv.logW[i] = sz.lv.s[i] = 0;
   sz.w_max = sz.lv.W[sz.lv.n - 1];
   sz.fused = sz.w_max <= kFusedMaxWindow;
+  sz.delay_only = (p->flags & FRINGE_DELAY_ONLY) != 0;
+  if (sz.delay_only && !sz.fused)
+    return fail(FRINGE_E_UNSUPPORTED, "FRINGE_DELAY_ONLY needs windows of at most %d APs",
+                kFusedMaxWindow);
   if ((p->flags & FRINGE_PLAIN) && !sz.fused)
     return fail(FRINGE_E_UNSUPPORTED, "FRINGE_PLAIN needs windows of at most %d APs", kFusedMaxWindow);
   // the kernels count window strides (and the fused kernel its period) from
@@ -273,7 +285,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     cap = p->hbm_budget_bytes - sz.fixed_bytes;
   }
   for (auto& si : sz.scans) {
-    const uint64_t per = per_baseline_scratch(si, sz.fused, sz.streaming);
+    const uint64_t per = per_baseline_scratch(si, sz.fused, sz.streaming, sz.delay_only);
     int64_t nb = int64_t(cap / per);
     if (nb < 1) {
       if (p->hbm_budget_bytes > 0)
@@ -295,7 +307,8 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
       const uint64_t e_u = uint64_t(nb) * t;
       const uint64_t part_u = uint64_t(si.n_kb) * nb * si.nwb_max;
       const bool open = !sz.groups.empty() && sz.groups.back().u1 == int(sz.units.size());
-      if (!sz.fused || !open || (g_e + e_u) * sizeof(float) + (g_part + part_u) * sizeof(uint64_t) > cap) {
+      if (!sz.fused || !open ||
+          (g_e + e_u) * sizeof(float) + (g_part + part_u) * part_bytes(sz.delay_only) > cap) {
         sz.groups.push_back(Group{int(sz.units.size()), int(sz.units.size())});
         g_e = g_part = 0;
       }
@@ -311,10 +324,12 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   }
   sz.scratch_e = max_e * sizeof(float);
   sz.scratch_part = max_part * sizeof(uint64_t);
+  sz.scratch_epart = sz.delay_only ? max_part * sizeof(float) : 0;
   const size_t entries = (p->flags & FRINGE_PLAIN) ? size_t(sz.n_windows) : sz.units.size();
   sz.arena_bytes = align_up(size_t(n_scans) * sizeof(ScanDev)) +
                    align_up(entries * sizeof(FusedArgs)) + align_up(entries * sizeof(FinalizeArgs));
-  sz.total = sz.fixed_bytes + sz.scratch_x + sz.scratch_e + sz.scratch_part + 2 * sz.arena_bytes;
+  sz.total = sz.fixed_bytes + sz.scratch_x + sz.scratch_e + sz.scratch_part + sz.scratch_epart +
+             2 * sz.arena_bytes;
   *out = std::move(sz);
   return FRINGE_OK;
 }
@@ -383,6 +398,7 @@ struct fringe_plan_s {
   float2* X = nullptr;
   float* e = nullptr;
   uint64_t* part = nullptr;
+  float* epart = nullptr;          // delay-only: per-class power sums
   WindowRec* table = nullptr;
   int32_t* blk_counts = nullptr;
   int64_t* blk_offsets = nullptr;
@@ -431,7 +447,7 @@ namespace {
 void release(fringe_plan_t p) {
   if (!p) return;
   if (p->searched && p->done) (void)hipEventSynchronize(p->done);
-  void* bufs[] = {p->X, p->e, p->part, p->table, p->blk_counts, p->blk_offsets, p->cands,
+  void* bufs[] = {p->X, p->e, p->part, p->epart, p->table, p->blk_counts, p->blk_offsets, p->cands,
                   p->d_total, p->grid, p->d_ids, p->d_recs, p->d_arena[0], p->d_arena[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -550,6 +566,7 @@ FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan
   fu.vis = data ? data + int64_t(u.b0) * vis_stride : nullptr;
   fu.vis_stride = vis_stride;
   fu.part = p->part + u.part_off;
+  fu.epart = p->epart ? p->epart + u.part_off : nullptr;
   fu.e = p->e + u.e_off;
   fu.dump = p->grid;
   fu.tw = p->tw[si.log_m];
@@ -579,6 +596,7 @@ FinalizeArgs finalize_entry(const fringe_plan_s* p, const ScanInfo& si, const Ca
                             const Unit& u) {
   FinalizeArgs fa{};
   fa.part = p->part + u.part_off;
+  fa.epart = p->epart ? p->epart + u.part_off : nullptr;
   fa.e = p->e + u.e_off;
   fa.table = p->table + c.win_off + int64_t(u.b0) * c.nwb;
   fa.slab_windows = int64_t(u.nb) * c.nwb;
@@ -698,7 +716,7 @@ int fringe_plan_check(const fringe_scan_desc* scans, int32_t n_scans, const frin
   if (rc != FRINGE_OK) return rc;
   out->n_windows = sz.n_windows;
   out->device_bytes = int64_t(sz.total);
-  out->scratch_bytes = int64_t(sz.scratch_x + sz.scratch_e + sz.scratch_part);
+  out->scratch_bytes = int64_t(sz.scratch_x + sz.scratch_e + sz.scratch_part + sz.scratch_epart);
   out->max_window_ap = sz.w_max;
   int mn = 1 << 30;
   for (auto& si : sz.scans) mn = std::min(mn, si.slab_nb);
@@ -735,6 +753,7 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
   if ((rc = dev_alloc(&p->X, z.scratch_x, "delay spectra")) ||
       (rc = dev_alloc(&p->e, z.scratch_e, "AP energies")) ||
       (rc = dev_alloc(&p->part, z.scratch_part, "bin-block peaks")) ||
+      (rc = dev_alloc(&p->epart, z.scratch_epart, "bin-block power sums")) ||
       (rc = dev_alloc(&p->table, z.table_bytes, "window table")) ||
       (rc = dev_alloc(&p->blk_counts, uint64_t(z.n_blocks) * sizeof(int32_t), "block counts")) ||
       (rc = dev_alloc(&p->blk_offsets, uint64_t(z.n_blocks) * sizeof(int64_t), "block offsets")) ||
@@ -886,6 +905,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   const FusedArgs* d_fus = reinterpret_cast<const FusedArgs*>(arena + L.fused);
   const FinalizeArgs* d_fin = reinterpret_cast<const FinalizeArgs*>(arena + L.fin);
   const hipStream_t user_st = st;
+  const int kernel_pad_t = z.delay_only ? 0 : z.scans[0].pad_t;  // 0: the delay-only kernels
 
   // Every kernel of the search, enqueued on stream st (the caller's, or the
   // capture stream of FRINGE_GRAPH).
@@ -893,7 +913,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   if (plain) {
     for (int64_t i = 0; i < p->call_windows; ++i) {
       const FusedArgs& h = reinterpret_cast<const FusedArgs*>(p->tables.data() + L.fused)[i];
-      FRINGE_TIMED(1, launch_fused(d_fus + i, 1, fused_blocks(h), z.scans[0].pad_t, z.w_max, h.hf,
+      FRINGE_TIMED(1, launch_fused(d_fus + i, 1, fused_blocks(h), kernel_pad_t, z.w_max, h.hf,
                                    false, st), "plain fused launch");
       FRINGE_TIMED(2, launch_finalize(d_fin + i, 1, 1, st), "plain finalize launch");
     }
@@ -901,7 +921,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     for (size_t g = 0; g < z.groups.size(); ++g) {
       const int u0 = z.groups[g].u0, n = z.groups[g].u1 - z.groups[g].u0;
       if (grp_windows[g] == 0) continue;
-      FRINGE_TIMED(1, launch_fused(d_fus + u0, n, grp_blocks[g], z.scans[0].pad_t, z.w_max, hf_max,
+      FRINGE_TIMED(1, launch_fused(d_fus + u0, n, grp_blocks[g], kernel_pad_t, z.w_max, hf_max,
                                    p->grid != nullptr, st), "fused search launch");
       FRINGE_TIMED(2, launch_finalize(d_fin + u0, n, grp_windows[g], st), "finalize launch");
     }
@@ -1159,7 +1179,8 @@ int fringe_plan_info(fringe_plan_t p, fringe_plan_summary* out) {
   if (!p || !out) return fail(FRINGE_E_INVALID, "null argument");
   out->n_windows = p->sz.streaming ? p->call_windows : p->sz.n_windows;
   out->device_bytes = int64_t(p->sz.total);
-  out->scratch_bytes = int64_t(p->sz.scratch_x + p->sz.scratch_e + p->sz.scratch_part);
+  out->scratch_bytes = int64_t(p->sz.scratch_x + p->sz.scratch_e + p->sz.scratch_part +
+                               p->sz.scratch_epart);
   out->max_window_ap = p->sz.w_max;
   int mn = 1 << 30;
   for (auto& si : p->sz.scans) mn = std::min(mn, si.slab_nb);

@@ -1,0 +1,13 @@
+// Instantiations of the fused search kernel: delay-only search (rate bin 0),
+// windows up to 64 APs.
+#include "fused_search.h"
+
+namespace fringe {
+
+hipError_t launch_fused_d_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                             hipStream_t st) {
+  if (hf_max <= 4) return launch_fused_t<0, 6, 4, false>(tab, n, blocks, st);
+  return launch_fused_t<0, 6, 16, false>(tab, n, blocks, st);
+}
+
+}  // namespace fringe

@@ -15,6 +15,12 @@ hipError_t launch_fused_p1_w6(const FusedArgs* tab, int n, int64_t blocks, int h
                               hipStream_t st);
 hipError_t launch_fused_p2_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
                               hipStream_t st);
+hipError_t launch_fused_d_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                             hipStream_t st);
+hipError_t launch_fused_d_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                             hipStream_t st);
+hipError_t launch_fused_d_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                             hipStream_t st);
 
 // APs per unrolled period of the kernel that serves w_max.
 int fused_period(int w_max) { return w_max <= 8 ? 4 : (w_max <= 32 ? 16 : 32); }
@@ -29,6 +35,12 @@ int64_t fused_blocks(const FusedArgs& a) {
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
                         int w_max, int hf_max, bool dump, hipStream_t st) {
   if (hf_max > 16 || w_max > kFusedMaxWindow) return hipErrorInvalidValue;
+  if (pad_t == 0) {
+    if (dump) return hipErrorInvalidValue;
+    if (w_max <= 8) return launch_fused_d_w3(d_tab, n_tab, n_blocks, hf_max, st);
+    if (w_max <= 32) return launch_fused_d_w5(d_tab, n_tab, n_blocks, hf_max, st);
+    return launch_fused_d_w6(d_tab, n_tab, n_blocks, hf_max, st);
+  }
   if (pad_t == 1) {
     if (w_max <= 8) return launch_fused_p1_w3(d_tab, n_tab, n_blocks, hf_max, dump, st);
     if (w_max <= 32) return launch_fused_p1_w5(d_tab, n_tab, n_blocks, hf_max, dump, st);

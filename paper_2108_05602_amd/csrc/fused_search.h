@@ -15,6 +15,9 @@
 // ends at the AP is searched at once (window_key: rate transform + peak
 // key) and reduced over the 64 bins with DPP (wave_peak); one lane stores
 // the class's partial peak.  Waves of class 0 also store the AP energies.
+// PT = 0 is the delay-only search of the paper's step 6: the window's APs
+// are summed, the power of the sum is the key, and each class also stores
+// its sum of that power over its 64 bins (for the mean over the delay axis).
 //
 // Block g runs on XCD g mod 8; the R classes of one (baseline, chunk) are
 // given the same XCD and consecutive slots, so the chunk's visibilities are
@@ -172,6 +175,9 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   // loop, so they live in scalar registers)
   const auto part = gptr(a.part + static_cast<int64_t>(cls) * a.slab_windows +
                          static_cast<int64_t>(b) * a.nwb);
+  float* const epart = PT == 0 ? a.epart + static_cast<int64_t>(cls) * a.slab_windows +
+                                     static_cast<int64_t>(b) * a.nwb
+                               : nullptr;
   const int t_emit = a.t_emit;
   int pidx[LOGWMAX + 1];
   bool on[LOGWMAX + 1];
@@ -206,7 +212,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
       float2 z = pre[fs][0];
 #pragma unroll
       for (int h = 1; h < HFMAX; ++h) z = c_add(z, c_mul(pre[fs][h], wh[h]));
-      if (cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
+      if (PT > 0 && cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
         float es = 0.f;
 #pragma unroll
         for (int h = 0; h < HFMAX; ++h) es += c_norm(pre[fs][h]);
@@ -225,13 +231,28 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
         if constexpr (base >= 0 && ((i + 1 - W) % s + s) % s == 0) {
           const int start = t + 1 - W;
           if (on[L] && start >= own_lo && start < own_hi && t < T && t >= t_emit) {
-            float2* dump = nullptr;
             const int j = start / s;
-            if constexpr (DUMP) dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
-            const uint32_t key = window_key<L, PT, DUMP>(
-                [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
-            const uint64_t pk = wave_peak(key, cls, R);
-            if (lane == 0) part[pidx[L] + j] = pk;
+            if constexpr (PT == 0) {
+              // delay-only: the window's APs summed coherently; its power in
+              // this lane's bin is the key, and the class's power sum goes
+              // to the mean power over the delay axis
+              float2 sum = hist[base];
+              static_for<1, W>([&](auto ui) { sum = c_add(sum, hist[base + decltype(ui)::value]); });
+              const float pw = c_norm(sum);
+              const uint64_t pk = wave_peak(__float_as_uint(pw), cls, R);
+              const float es = wave_sum_dpp(pw);
+              if (lane == 0) {
+                part[pidx[L] + j] = pk;
+                epart[pidx[L] + j] = es;
+              }
+            } else {
+              float2* dump = nullptr;
+              if constexpr (DUMP) dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
+              const uint32_t key = window_key<L, PT, DUMP>(
+                  [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
+              const uint64_t pk = wave_peak(key, cls, R);
+              if (lane == 0) part[pidx[L] + j] = pk;
+            }
           }
         }
       });

@@ -71,6 +71,7 @@ struct FusedArgs {
   const float2* vis;   // [nb][T][F] visibilities of the slab
   int64_t vis_stride;  // elements between baselines of vis (>= T * F)
   uint64_t* part;      // [R][slab_windows] per residue-class peak keys (out)
+  float* epart;        // [R][slab_windows] per residue-class sum of |G_0|^2 (delay-only, out)
   float* e;            // [nb][T] per-AP energies (out)
   float2* dump;        // full grids (FRINGE_DUMP_GRID) or nullptr
   const float2* tw;    // [M] exp(-2 pi i k / M)
@@ -90,6 +91,7 @@ struct FusedArgs {
 struct FinalizeArgs {
   int64_t win_begin;
   const uint64_t* part;
+  const float* epart;  // delay-only: per-class power sums; nullptr otherwise
   const float* e;
   WindowRec* table;    // records of this slab's windows (already offset)
   int64_t slab_windows;
@@ -123,7 +125,8 @@ constexpr int kFusedMaxWindow = 64;
 int fused_period(int w_max);
 // Blocks that entry `a` occupies in a fused launch.
 int64_t fused_blocks(const FusedArgs& a);
-// d_tab: n_tab entries in device memory; hf_max: the largest entry hf.
+// d_tab: n_tab entries in device memory; hf_max: the largest entry hf;
+// pad_t = 0 selects the delay-only search (rate bin 0 only).
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
                         int w_max, int hf_max, bool dump, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs* d_tab, int n_tab, int64_t n_windows,

@@ -111,11 +111,11 @@ def compare_candidates(gpu_c, ref_table, threshold, label=""):
     assert diff <= near, f"{label}: candidate lists differ at {sorted(diff - near)[:10]}"
 
 
-def oracle_table(scans_vis, scans, window_aps, pad_freq, pad_time, threshold):
+def oracle_table(scans_vis, scans, window_aps, pad_freq, pad_time, threshold, delay_only=False):
     """Reference table for several scans, in window-id order, with `scan` set."""
     tabs = []
     for s, (v, d) in enumerate(zip(scans_vis, scans)):
         t, _ = fo.search_scan(v, window_aps, pad_freq, pad_time, threshold, d["ap_seconds"],
-                              d["chan_width_hz"], scan=s)
+                              d["chan_width_hz"], scan=s, delay_only=delay_only)
         tabs.append(t)
     return np.concatenate(tabs)

@@ -125,7 +125,25 @@ def test_graph_flag_rules():
     assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_GRAPH | B.FRINGE_DUMP_GRID)["n_windows"] == 31
     for other in (B.FRINGE_STREAMING, B.FRINGE_PROFILE, B.FRINGE_PLAIN):
         assert _code(lambda: F.fringe_plan_check([c1], [4], flags=B.FRINGE_GRAPH | other)) == B.FRINGE_E_INVALID
-    assert _code(lambda: F.fringe_plan_check([c1], [4], flags=0x20)) == B.FRINGE_E_INVALID
+    assert _code(lambda: F.fringe_plan_check([c1], [4], flags=0x40)) == B.FRINGE_E_INVALID
+
+
+def test_delay_only_flag_rules():
+    """FRINGE_DELAY_ONLY: same windows, windows of at most 64 APs, no grid
+    dump; its work buffers hold a power sum per window and class besides
+    the peak key."""
+    c1 = dict(n_baselines=1, n_ap=64, n_if=2, n_chan=16, ap_seconds=1.0, chan_width_hz=1 / 32)
+    assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_DELAY_ONLY)["n_windows"] == 31
+    for flags in (B.FRINGE_DELAY_ONLY | B.FRINGE_STREAMING, B.FRINGE_DELAY_ONLY | B.FRINGE_PLAIN,
+                  B.FRINGE_DELAY_ONLY | B.FRINGE_GRAPH):
+        assert F.fringe_plan_check([c1], [1, 2, 4], flags=flags)["n_windows"] > 0
+    assert _code(lambda: F.fringe_plan_check([dict(c1, n_ap=256)], [128],
+                                             flags=B.FRINGE_DELAY_ONLY)) == B.FRINGE_E_UNSUPPORTED
+    assert _code(lambda: F.fringe_plan_check([c1], [4], flags=B.FRINGE_DELAY_ONLY | B.FRINGE_DUMP_GRID)) == B.FRINGE_E_INVALID
+    full = F.fringe_plan_check([C2], C2_W)
+    do = F.fringe_plan_check([C2], C2_W, flags=B.FRINGE_DELAY_ONLY)
+    assert do["n_windows"] == full["n_windows"]
+    assert do["scratch_bytes"] > full["scratch_bytes"]
 
 
 def test_streaming_sizing():

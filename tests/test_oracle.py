@@ -391,16 +391,16 @@ def _transposed_freq(x_b, pad_freq):
     return fo.delay_spectra(x_b.reshape(t, 2, f // 2).transpose(0, 2, 1).reshape(t, f), pad_freq)
 
 
-def _delay_only_incoherent(x_seg, pad_freq):
+def _delay_only_incoherent(x_seg, pad_freq, a_f=None):
     # per-AP power spectra summed (an incoherent search), not the coherent sum
     x_seg = np.asarray(x_seg, complex)
     spec = x_seg @ fo.delay_dft_matrix(x_seg.shape[1], pad_freq * x_seg.shape[1])
     return np.sqrt(np.sum(np.abs(spec) ** 2, axis=0))[None, :].astype(complex)
 
 
-def _delay_only_grid_energy(x_b, t0, window_ap, pad_freq):
+def _delay_only_grid_energy(x_b, t0, window_ap, pad_freq, a_f=None):
     # E taken as the full grid's (sum of |x|^2) instead of the delay row's
-    r = fo.search_window_delay_only(x_b, t0, window_ap, pad_freq)
+    r = fo.search_window_delay_only(x_b, t0, window_ap, pad_freq, a_f)
     e = float(np.sum(np.abs(np.asarray(x_b[t0:t0 + window_ap])) ** 2))
     r.energy = e
     r.snr = r.amp / math.sqrt(e) if e > 0 else 0.0
