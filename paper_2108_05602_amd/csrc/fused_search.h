@@ -6,7 +6,8 @@
 // R m + c.  Per AP t (paper, section "Code optimization", step 5):
 //   z[f'] = w_M^{c f'} sum_h x_t[f' + 64 h] w_R^{c h}      (f' < 64)
 //   X_t[R m + c] = sum_{f'} z[f'] w_64^{m f'}
-// lane l folds f' = bitrev6(l), then six radix-2 decimation-in-time stages
+// lane l loads and folds f = l (contiguous loads), one LDS permute moves the
+// fold to lane bitrev6(f), then six radix-2 decimation-in-time stages
 // across the wave (DPP, ds_swizzle and permlane swaps, no LDS) leave X_t of
 // lane m's bin in lane m.  Each lane keeps the last W_max APs of its bin's
 // spectrum in registers: the APs come in periods of P = W_max / 2 that are
@@ -88,6 +89,30 @@ __device__ __forceinline__ float2 xlane_dit(float2 v, const LaneConsts& k) {
   return v;
 }
 
+// Windows ending at position i of a period of P APs: the length 2^L has
+// one there when its first AP is still held (base >= 0) and its start is on
+// the length's stride.
+template <int P>
+constexpr bool window_site(int i, int L) {
+  const int w = 1 << L, s = w > 1 ? w / 2 : 1, base = P + i + 1 - w;
+  return base >= 0 && ((i + 1 - w) % s + s) % s == 0;
+}
+
+template <int P, int LOGWMAX>
+constexpr int window_sites(int i) {
+  int n = 0;
+  for (int L = 0; L <= LOGWMAX; ++L) n += window_site<P>(i, L) ? 1 : 0;
+  return n;
+}
+
+// The length (log2) of the k-th window ending at position i.
+template <int P, int LOGWMAX>
+constexpr int site_level(int i, int k) {
+  for (int L = 0; L <= LOGWMAX; ++L)
+    if (window_site<P>(i, L) && k-- == 0) return L;
+  return -1;
+}
+
 }  // namespace fused
 
 template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
@@ -96,7 +121,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   constexpr int WMAX = 1 << LOGWMAX;
   constexpr int P = WMAX / 2;          // APs per unrolled period
   constexpr int HS = 2 * P;            // history registers (complex)
-  constexpr int PD = HFMAX <= 4 ? 4 : 1;  // prefetch depth in APs
+  constexpr int PD = HFMAX > 4 ? 1 : (PT == 0 ? 2 : 4);  // prefetch depth in APs
   static_assert(P % PD == 0 && P >= 4, "period");
 
   const int lane = threadIdx.x;
@@ -121,6 +146,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
 
   // lane constants
   const int fl = static_cast<int>(__builtin_bitreverse32(static_cast<uint32_t>(lane)) >> 26);
+  const int rev_addr = fl * 4;  // ds_bpermute source lane bitrev6(lane), in bytes
   fused::LaneConsts kc;
   const float2* tw = a.tw;
   kc.wfold = ld_global(tw + ((cls * fl) & (M - 1)));
@@ -145,7 +171,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   int lane_f[HFMAX];
 #pragma unroll
   for (int h = 0; h < HFMAX; ++h) {
-    const int f = fl + 64 * h;
+    const int f = lane + 64 * h;  // natural order: each load is one contiguous segment
     lane_in[h] = h < hf && f < F;
     lane_f[h] = lane_in[h] ? f : 0;
   }
@@ -220,32 +246,58 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
         if (lane == 0 && t < own_hi) eb[t] = e;
       }
       load_ap(t + PD, pre[fs]);
+      // lane l folded f = l; the transform wants f' = bitrev6(l) in lane l
+      z = make_float2(
+          __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z.x))),
+          __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z.y))));
       hist[P + i] = fused::xlane_dit(c_mul(z, kc.wfold), kc);
 
       // every window that ends at AP t
-      static_for<0, LOGWMAX + 1>([&](auto li) {
-        constexpr int L = decltype(li)::value;
-        constexpr int W = 1 << L;
-        constexpr int s = W > 1 ? W / 2 : 1;
-        constexpr int base = P + i + 1 - W;  // register of the window's first AP
-        if constexpr (base >= 0 && ((i + 1 - W) % s + s) % s == 0) {
+      if constexpr (PT == 0) {
+        // delay-only: each window's APs summed coherently; the power of the
+        // sum in this lane's bin is its key, and the class's power sum goes
+        // to the mean over the delay axis.  The windows ending here are
+        // reduced together (independent DPP chains interleaved).
+        constexpr int NS = fused::window_sites<P, LOGWMAX>(i);
+        uint32_t key[NS], mx[NS];
+        float ps[NS];
+        static_for<0, NS>([&](auto ki) {
+          constexpr int k = decltype(ki)::value;
+          constexpr int W = 1 << fused::site_level<P, LOGWMAX>(i, k);
+          constexpr int base = P + i + 1 - W;
+          float2 sum = hist[base];
+          static_for<1, W>([&](auto ui) { sum = c_add(sum, hist[base + decltype(ui)::value]); });
+          ps[k] = c_norm(sum);
+          key[k] = __float_as_uint(ps[k]);
+          mx[k] = key[k];
+        });
+        wave_max_u32_n(mx);
+        wave_sum_f32_n(ps);
+        static_for<0, NS>([&](auto ki) {
+          constexpr int k = decltype(ki)::value;
+          constexpr int L = fused::site_level<P, LOGWMAX>(i, k);
+          constexpr int W = 1 << L;
+          constexpr int s = W > 1 ? W / 2 : 1;
           const int start = t + 1 - W;
           if (on[L] && start >= own_lo && start < own_hi && t < T && t >= t_emit) {
             const int j = start / s;
-            if constexpr (PT == 0) {
-              // delay-only: the window's APs summed coherently; its power in
-              // this lane's bin is the key, and the class's power sum goes
-              // to the mean power over the delay axis
-              float2 sum = hist[base];
-              static_for<1, W>([&](auto ui) { sum = c_add(sum, hist[base + decltype(ui)::value]); });
-              const float pw = c_norm(sum);
-              const uint64_t pk = wave_peak(__float_as_uint(pw), cls, R);
-              const float es = wave_sum_dpp(pw);
-              if (lane == 0) {
-                part[pidx[L] + j] = pk;
-                epart[pidx[L] + j] = es;
-              }
-            } else {
+            const uint64_t pk = peak_partial(key[k], mx[k], cls, R);
+            if (lane == 0) {
+              part[pidx[L] + j] = pk;
+              epart[pidx[L] + j] = ps[k];
+            }
+          }
+        });
+      } else {
+        static_for<0, LOGWMAX + 1>([&](auto li) {
+          constexpr int L = decltype(li)::value;
+          constexpr int W = 1 << L;
+          constexpr int s = W > 1 ? W / 2 : 1;
+          constexpr int base = P + i + 1 - W;  // register of the window's first AP
+          if constexpr (fused::window_site<P>(i, L)) {
+            const int start = t + 1 - W;
+            if (on[L] && start >= own_lo && start < own_hi && t < T && t >= t_emit) {
+              const int j = start / s;
               float2* dump = nullptr;
               if constexpr (DUMP) dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
               const uint32_t key = window_key<L, PT, DUMP>(
@@ -254,8 +306,8 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
               if (lane == 0) part[pidx[L] + j] = pk;
             }
           }
-        }
-      });
+        });
+      }
     });
 #pragma unroll
     for (int k = 0; k < P; ++k) hist[k] = hist[P + k];

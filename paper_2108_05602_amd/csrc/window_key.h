@@ -183,17 +183,49 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Maxima and sums over the 64 lanes of N independent values (uniform
+// results), by the steps of wave_max_u32 / wave_sum_dpp with the N
+// reductions interleaved so that their dependent DPP chains overlap.
+template <int N>
+__device__ __forceinline__ void wave_max_u32_n(uint32_t (&v)[N]) {
+  static_for<0, N>([&](auto k) { v[k] = max(v[k], dpp_u32<kDppXor1>(v[k])); });
+  static_for<0, N>([&](auto k) { v[k] = max(v[k], dpp_u32<kDppXor2>(v[k])); });
+  static_for<0, N>([&](auto k) { v[k] = max(v[k], dpp_u32<kDppHalfMirror>(v[k])); });
+  static_for<0, N>([&](auto k) { v[k] = max(v[k], dpp_u32<kDppMirror>(v[k])); });
+  static_for<0, N>([&](auto k) { v[k] = max(v[k], dpp_rows_u32<kDppRowBcast15, 0xA>(v[k])); });
+  static_for<0, N>([&](auto k) { v[k] = max(v[k], dpp_rows_u32<kDppRowBcast31, 0xC>(v[k])); });
+  static_for<0, N>([&](auto k) { v[k] = __builtin_amdgcn_readlane(v[k], 63); });
+}
+
+template <int N>
+__device__ __forceinline__ void wave_sum_f32_n(float (&v)[N]) {
+  static_for<0, N>([&](auto k) { v[k] += dpp_f32<kDppXor1>(v[k]); });
+  static_for<0, N>([&](auto k) { v[k] += dpp_f32<kDppXor2>(v[k]); });
+  static_for<0, N>([&](auto k) { v[k] += dpp_f32<kDppHalfMirror>(v[k]); });
+  static_for<0, N>([&](auto k) { v[k] += dpp_f32<kDppMirror>(v[k]); });
+  static_for<0, N>([&](auto k) { v[k] += dpp_rows_f32<kDppRowBcast15, 0xA>(v[k]); });
+  static_for<0, N>([&](auto k) { v[k] += dpp_rows_f32<kDppRowBcast31, 0xC>(v[k]); });
+  static_for<0, N>([&](auto k) {
+    v[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[k]), 63));
+  });
+}
+
+// The bin-block partial of a window whose 64-lane key maximum m is known:
+//   (m << 32) | (0xFFFFFFFF - k_f),  k_f of the lowest lane holding m.
+__device__ __forceinline__ uint64_t peak_partial(uint32_t key, uint32_t m, int kf_base, int kf_step) {
+  const uint64_t holders = __ballot(key == m);
+  const int lane = __builtin_ctzll(holders);
+  const uint32_t kf = static_cast<uint32_t>(kf_base + kf_step * lane);
+  return (static_cast<uint64_t>(m) << 32) | (0xFFFFFFFFu - kf);
+}
+
 // Window key of a wave: the 64-lane max of the lanes' rate keys, and the
 // lowest lane holding it.  Returned as the bin-block partial
 //   (key << 32) | (0xFFFFFFFF - k_f)   with k_f = kf_base + kf_step * lane,
 // whose unsigned max over blocks is the window's peak (lowest flat index
 // among ties).
 __device__ __forceinline__ uint64_t wave_peak(uint32_t key, int kf_base, int kf_step) {
-  const uint32_t m = wave_max_u32(key);
-  const uint64_t holders = __ballot(key == m);
-  const int lane = __builtin_ctzll(holders);
-  const uint32_t kf = static_cast<uint32_t>(kf_base + kf_step * lane);
-  return (static_cast<uint64_t>(m) << 32) | (0xFFFFFFFFu - kf);
+  return peak_partial(key, wave_max_u32(key), kf_base, kf_step);
 }
 
 }  // namespace fringe
