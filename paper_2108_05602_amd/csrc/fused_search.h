@@ -89,6 +89,8 @@ __device__ __forceinline__ float2 xlane_dit(float2 v, const LaneConsts& k) {
   return v;
 }
 
+constexpr int ilog2c(int v) { return v > 1 ? 1 + ilog2c(v / 2) : 0; }
+
 // Windows ending at position i of a period of P APs: the length 2^L has
 // one there when its first AP is still held (base >= 0) and its start is on
 // the length's stride.
@@ -201,10 +203,11 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   // loop, so they live in scalar registers)
   const auto part = gptr(a.part + static_cast<int64_t>(cls) * a.slab_windows +
                          static_cast<int64_t>(b) * a.nwb);
-  float* const epart = PT == 0 ? a.epart + static_cast<int64_t>(cls) * a.slab_windows +
-                                     static_cast<int64_t>(b) * a.nwb
-                               : nullptr;
+  const auto epart = gptr(PT == 0 ? a.epart + static_cast<int64_t>(cls) * a.slab_windows +
+                                        static_cast<int64_t>(b) * a.nwb
+                                  : a.epart);
   const int t_emit = a.t_emit;
+  const uint32_t own_n = static_cast<uint32_t>(own_hi - own_lo);
   int pidx[LOGWMAX + 1];
   bool on[LOGWMAX + 1];
   int64_t gidx[LOGWMAX + 1];
@@ -252,7 +255,9 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
           __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z.y))));
       hist[P + i] = fused::xlane_dit(c_mul(z, kc.wfold), kc);
 
-      // every window that ends at AP t
+      // every window that ends at AP t (and is reported: within the data,
+      // at or after the first AP the call reports, starting in this chunk)
+      const bool t_ok = t < T && t >= t_emit;
       if constexpr (PT == 0) {
         // delay-only: each window's APs summed coherently; the power of the
         // sum in this lane's bin is its key, and the class's power sum goes
@@ -279,12 +284,13 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
           constexpr int W = 1 << L;
           constexpr int s = W > 1 ? W / 2 : 1;
           const int start = t + 1 - W;
-          if (on[L] && start >= own_lo && start < own_hi && t < T && t >= t_emit) {
-            const int j = start / s;
+          if (on[L] && t_ok && static_cast<uint32_t>(start - own_lo) < own_n) {
+            const uint32_t idx = static_cast<uint32_t>(pidx[L]) +
+                                 (static_cast<uint32_t>(start) >> fused::ilog2c(s));
             const uint64_t pk = peak_partial(key[k], mx[k], cls, R);
             if (lane == 0) {
-              part[pidx[L] + j] = pk;
-              epart[pidx[L] + j] = ps[k];
+              part[idx] = pk;
+              epart[idx] = ps[k];
             }
           }
         });
@@ -296,14 +302,14 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
           constexpr int base = P + i + 1 - W;  // register of the window's first AP
           if constexpr (fused::window_site<P>(i, L)) {
             const int start = t + 1 - W;
-            if (on[L] && start >= own_lo && start < own_hi && t < T && t >= t_emit) {
-              const int j = start / s;
+            if (on[L] && t_ok && static_cast<uint32_t>(start - own_lo) < own_n) {
+              const uint32_t j = static_cast<uint32_t>(start) >> fused::ilog2c(s);
               float2* dump = nullptr;
               if constexpr (DUMP) dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
               const uint32_t key = window_key<L, PT, DUMP>(
                   [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
               const uint64_t pk = wave_peak(key, cls, R);
-              if (lane == 0) part[pidx[L] + j] = pk;
+              if (lane == 0) part[static_cast<uint32_t>(pidx[L]) + j] = pk;
             }
           }
         });
