@@ -208,6 +208,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
                                   : a.epart);
   const int t_emit = a.t_emit;
   const uint32_t own_n = static_cast<uint32_t>(own_hi - own_lo);
+  const uint32_t kf_top = 0xFFFFFFFFu - static_cast<uint32_t>(cls);  // peak_partial's k_f base
   int pidx[LOGWMAX + 1];
   bool on[LOGWMAX + 1];
   int64_t gidx[LOGWMAX + 1];
@@ -225,6 +226,21 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   }
 
   for (int p0 = own_lo; p0 < t_end; p0 += P) {
+    // this period's store bases per length: a window with start p0 + d
+    // (d a multiple of its stride s) has index pidx + p0 / s + d / s, so its
+    // slot is pb[L][d / s], a constant offset from a base set once here
+    // (p0 is a multiple of every stride).  The base index is signed: with a
+    // streaming plan pidx < 0, and a period's base may lie before the
+    // buffer while the windows it reports (d > 0) lie inside it.
+    std::remove_const_t<decltype(part)> pb[LOGWMAX + 1];
+    std::remove_const_t<decltype(epart)> epb[LOGWMAX + 1];
+    static_for<0, LOGWMAX + 1>([&](auto li) {
+      constexpr int L = decltype(li)::value;
+      constexpr int LS = L > 0 ? L - 1 : 0;
+      const int64_t o = static_cast<int64_t>(pidx[L]) + (p0 >> LS);
+      pb[L] = part + o;
+      if constexpr (PT == 0) epb[L] = epart + o;
+    });
     static_for<0, P>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
       constexpr int fs = i % PD;
@@ -283,14 +299,13 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
           constexpr int L = fused::site_level<P, LOGWMAX>(i, k);
           constexpr int W = 1 << L;
           constexpr int s = W > 1 ? W / 2 : 1;
+          constexpr int d = (i + 1 - W) / s;  // start - p0, in strides
           const int start = t + 1 - W;
           if (on[L] && t_ok && static_cast<uint32_t>(start - own_lo) < own_n) {
-            const uint32_t idx = static_cast<uint32_t>(pidx[L]) +
-                                 (static_cast<uint32_t>(start) >> fused::ilog2c(s));
-            const uint64_t pk = peak_partial(key[k], mx[k], cls, R);
+            const uint64_t pk = peak_partial(key[k], mx[k], kf_top, R);
             if (lane == 0) {
-              part[idx] = pk;
-              epart[idx] = ps[k];
+              pb[L][d] = pk;
+              epb[L][d] = ps[k];
             }
           }
         });
@@ -301,15 +316,18 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
           constexpr int s = W > 1 ? W / 2 : 1;
           constexpr int base = P + i + 1 - W;  // register of the window's first AP
           if constexpr (fused::window_site<P>(i, L)) {
+            constexpr int d = (i + 1 - W) / s;  // start - p0, in strides
             const int start = t + 1 - W;
             if (on[L] && t_ok && static_cast<uint32_t>(start - own_lo) < own_n) {
-              const uint32_t j = static_cast<uint32_t>(start) >> fused::ilog2c(s);
               float2* dump = nullptr;
-              if constexpr (DUMP) dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
+              if constexpr (DUMP) {
+                const uint32_t j = static_cast<uint32_t>(start) >> fused::ilog2c(s);
+                dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
+              }
               const uint32_t key = window_key<L, PT, DUMP>(
                   [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
-              const uint64_t pk = wave_peak(key, cls, R);
-              if (lane == 0) part[static_cast<uint32_t>(pidx[L]) + j] = pk;
+              const uint64_t pk = peak_partial(key, wave_max_u32(key), kf_top, R);
+              if (lane == 0) pb[L][d] = pk;
             }
           }
         });

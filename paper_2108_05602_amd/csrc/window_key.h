@@ -211,12 +211,13 @@ __device__ __forceinline__ void wave_sum_f32_n(float (&v)[N]) {
 }
 
 // The bin-block partial of a window whose 64-lane key maximum m is known:
-//   (m << 32) | (0xFFFFFFFF - k_f),  k_f of the lowest lane holding m.
-__device__ __forceinline__ uint64_t peak_partial(uint32_t key, uint32_t m, int kf_base, int kf_step) {
+//   (m << 32) | (0xFFFFFFFF - k_f),  k_f = kf_base + kf_step * (lowest lane
+// holding m); kf_top = 0xFFFFFFFF - kf_base.
+__device__ __forceinline__ uint64_t peak_partial(uint32_t key, uint32_t m, uint32_t kf_top,
+                                                 int kf_step) {
   const uint64_t holders = __ballot(key == m);
   const int lane = __builtin_ctzll(holders);
-  const uint32_t kf = static_cast<uint32_t>(kf_base + kf_step * lane);
-  return (static_cast<uint64_t>(m) << 32) | (0xFFFFFFFFu - kf);
+  return (static_cast<uint64_t>(m) << 32) | (kf_top - static_cast<uint32_t>(kf_step * lane));
 }
 
 // Window key of a wave: the 64-lane max of the lanes' rate keys, and the
@@ -225,7 +226,8 @@ __device__ __forceinline__ uint64_t peak_partial(uint32_t key, uint32_t m, int k
 // whose unsigned max over blocks is the window's peak (lowest flat index
 // among ties).
 __device__ __forceinline__ uint64_t wave_peak(uint32_t key, int kf_base, int kf_step) {
-  return peak_partial(key, wave_max_u32(key), kf_base, kf_step);
+  return peak_partial(key, wave_max_u32(key), 0xFFFFFFFFu - static_cast<uint32_t>(kf_base),
+                      kf_step);
 }
 
 }  // namespace fringe
