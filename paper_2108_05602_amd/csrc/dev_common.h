@@ -37,6 +37,42 @@ __device__ __forceinline__ float2 ld_global(const float2* p) {
   return make_float2(v.x, v.y);
 }
 
+// The same load at a byte offset (< 4 GiB) from a wave-uniform base, so the
+// address is a scalar base plus a 32-bit vector offset (no 64-bit vector
+// address arithmetic per load).
+__device__ __forceinline__ float2 ld_global_off(const float2* base, uint32_t byte_off) {
+  const auto* b = (const __attribute__((address_space(1))) char*)(base);
+  const f32x2_t v = *(const __attribute__((address_space(1))) f32x2_t*)(b + byte_off);
+  return make_float2(v.x, v.y);
+}
+
+// Raw buffer access to a wave-uniform region: a load is a per-lane 32-bit
+// offset plus a scalar offset (both in bytes), with no vector address
+// arithmetic.  Word 3 of the resource is the gfx9-family setting for
+// untyped 32-bit-element access; the record limit is left at its maximum
+// (callers keep offsets inside their data).
+constexpr int kBufferWord3 = 0x00020000;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0), -1,
+                                           kBufferWord3);
+}
+
+__device__ __forceinline__ float2 ld_buffer(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(voff),
+                                                         static_cast<int>(soff), 0);
+  return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+
+// v held in a vector register: values the compiler would keep in scalar
+// registers (wave-uniform) cost a slower issue when they are VALU operands.
+__device__ __forceinline__ float in_vgpr(float v) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
 // ---------------------------------------------------------------- complex --
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -244,6 +244,9 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     if (si.nwb_max > (int64_t(1) << 30) || nw > (int64_t(1) << 40) ||
         int64_t(data_len(si, sz.streaming)) > (int64_t(1) << 30))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: too many windows", s);
+    // the fused kernel addresses one baseline's samples with 32-bit offsets
+    if (sz.fused && int64_t(data_len(si, sz.streaming)) * F * int64_t(sizeof(float2)) >= (int64_t(1) << 32))
+      return fail(FRINGE_E_UNSUPPORTED, "scan %d: a baseline holds 4 GiB or more of samples", s);
     si.full.win_off = win_off;
     si.grid_off = grid_off;
     win_off += nw;

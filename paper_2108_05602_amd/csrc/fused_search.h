@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
   constexpr int WMAX = 1 << LOGWMAX;
   constexpr int P = WMAX / 2;          // APs per unrolled period
   constexpr int HS = 2 * P;            // history registers (complex)
-  constexpr int PD = HFMAX > 4 ? 1 : (PT == 0 ? 2 : 4);  // prefetch depth in APs
+  constexpr int PD = HFMAX > 4 ? 1 : 2;  // prefetch depth in APs
   static_assert(P % PD == 0 && P >= 4, "period");
 
   const int lane = threadIdx.x;
@@ -161,26 +161,32 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
     kc.w[st] = bl ? w : make_float2(1.f, 0.f);
   }
   kc.rot2 = (lane & 2) != 0 && (lane & 1) != 0;
-  float2 wh[HFMAX];  // fold twiddles w_R^{c h} (uniform)
+  float2 wh[HFMAX];  // fold twiddles w_R^{c h} (uniform, kept in vector registers)
 #pragma unroll
-  for (int h = 0; h < HFMAX; ++h) wh[h] = ld_global(tw + (((cls * h) * 64) & (M - 1)));
+  for (int h = 0; h < HFMAX; ++h) {
+    const float2 w = ld_global(tw + (((cls * h) * 64) & (M - 1)));
+    wh[h] = make_float2(in_vgpr(w.x), in_vgpr(w.y));
+  }
 
   const float2* xb = a.vis + static_cast<int64_t>(b) * a.vis_stride;
   // Loads are unconditional and in bounds (the AP clamped to T - 1, lanes
   // past the band reading sample 0); what lies outside the data is zeroed
   // where it is used, so no load has to complete before later work issues.
   bool lane_in[HFMAX];
-  int lane_f[HFMAX];
+  uint32_t lane_off[HFMAX];  // byte offset of the lane's sample in an AP row
 #pragma unroll
   for (int h = 0; h < HFMAX; ++h) {
     const int f = lane + 64 * h;  // natural order: each load is one contiguous segment
     lane_in[h] = h < hf && f < F;
-    lane_f[h] = lane_in[h] ? f : 0;
+    lane_off[h] = lane_in[h] ? static_cast<uint32_t>(f) * sizeof(float2) : 0u;
   }
+  // (a baseline's data is < 4 GiB, checked at plan time)
+  const auto vrs = buffer_of(xb);
+  const uint32_t row_bytes = static_cast<uint32_t>(F) * sizeof(float2);
   auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
-    const float2* row = xb + static_cast<int64_t>(min(t, T - 1)) * F;
+    const uint32_t row_off = static_cast<uint32_t>(min(t, T - 1)) * row_bytes;
 #pragma unroll
-    for (int h = 0; h < HFMAX; ++h) dst[h] = ld_global(row + lane_f[h]);
+    for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h], row_off);
   };
   const bool band_full = F == 64 * HFMAX;  // every lane in band for every fold
   auto sample = [&](float2 x, int h, bool t_in) {
