@@ -35,11 +35,9 @@ namespace fused {
 // Partner exchange across lanes lane ^ D (D <= 8) on one float.
 template <int D>
 __device__ __forceinline__ float xchg(float v) {
-  if constexpr (D == 1) return dpp_f32<kDppXor1>(v);
-  else if constexpr (D == 2) return dpp_f32<kDppXor2>(v);
-  else if constexpr (D == 4)
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
-  else return dpp_f32<kDppRor8>(v);
+  // ds_swizzle in bit mode (lane ^ D within 32 lanes): it runs on the LDS
+  // crossbar, so the exchange takes no VALU issue slot (a DPP move does)
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (D << 10) | 0x1F));
 }
 
 // One DIT stage of half-span D.  Lanes with bit D set ("b" lanes) first
