@@ -8,8 +8,8 @@
 //   X_t[R m + c] = sum_{f'} z[f'] w_64^{m f'}
 // lane l loads and folds f = l (contiguous loads), one LDS permute moves the
 // fold to lane bitrev6(f), then six radix-2 decimation-in-time stages
-// across the wave (DPP, ds_swizzle and permlane swaps, no LDS) leave X_t of
-// lane m's bin in lane m.  Each lane keeps the last W_max APs of its bin's
+// across the wave (partners exchanged on the LDS crossbar: ds_swizzle and
+// ds_bpermute, no LDS memory) leave X_t of lane m's bin in lane m.  Each lane keeps the last W_max APs of its bin's
 // spectrum in registers: the APs come in periods of P = W_max / 2 that are
 // unrolled, so every window that ends in a period has compile-time register
 // positions; after the period the newer half moves down.  Every window that
@@ -32,58 +32,47 @@ namespace fringe {
 
 namespace fused {
 
-// Partner exchange across lanes lane ^ D (D <= 8) on one float.
+// Partner exchange across lanes lane ^ D on one float, on the LDS crossbar
+// (it takes no VALU issue slot, a DPP move or permlane swap does):
+// ds_swizzle in bit mode within 32 lanes for D <= 16, ds_bpermute from the
+// precomputed byte address 4 * (lane ^ 32) for D = 32.
 template <int D>
-__device__ __forceinline__ float xchg(float v) {
-  // ds_swizzle in bit mode (lane ^ D within 32 lanes): it runs on the LDS
-  // crossbar, so the exchange takes no VALU issue slot (a DPP move does)
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (D << 10) | 0x1F));
+__device__ __forceinline__ float xchg(float v, int addr32) {
+  if constexpr (D <= 16)
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (D << 10) | 0x1F));
+  else
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr32, __float_as_int(v)));
 }
 
 // One DIT stage of half-span D.  Lanes with bit D set ("b" lanes) first
 // multiply their value by w (w = 1 on "a" lanes); then a' = a + w b and
 // b' = a - w b, i.e. new = s * own + partner with s = +1 on a lanes, -1 on
-// b lanes (for D <= 8), or new = a + s * b with the two halves a, b that a
-// permlane swap delivers (D = 16, 32).
+// b lanes.
 template <int D>
-__device__ __forceinline__ float2 dit_stage(float2 v, float2 w, float s, bool rot) {
+__device__ __forceinline__ float2 dit_stage(float2 v, float2 w, float s, bool rot, int addr32) {
   // D = 2: the twiddle is 1 or -i (rot), applied by selects
   const float2 t = (D == 1) ? v
                  : (D == 2) ? make_float2(rot ? v.y : v.x, rot ? -v.x : v.y)
                             : c_mul(v, w);
-  if constexpr (D <= 8) {
-    const float px = xchg<D>(t.x), py = xchg<D>(t.y);
-    return make_float2(fmaf(s, t.x, px), fmaf(s, t.y, py));
-  } else {
-    int ax, bx, ay, by;
-    if constexpr (D == 16) {
-      const auto rx = __builtin_amdgcn_permlane16_swap(__float_as_int(t.x), __float_as_int(t.x), false, false);
-      const auto ry = __builtin_amdgcn_permlane16_swap(__float_as_int(t.y), __float_as_int(t.y), false, false);
-      ax = rx[0]; bx = rx[1]; ay = ry[0]; by = ry[1];
-    } else {
-      const auto rx = __builtin_amdgcn_permlane32_swap(__float_as_int(t.x), __float_as_int(t.x), false, false);
-      const auto ry = __builtin_amdgcn_permlane32_swap(__float_as_int(t.y), __float_as_int(t.y), false, false);
-      ax = rx[0]; bx = rx[1]; ay = ry[0]; by = ry[1];
-    }
-    return make_float2(fmaf(s, __int_as_float(bx), __int_as_float(ax)),
-                       fmaf(s, __int_as_float(by), __int_as_float(ay)));
-  }
+  const float px = xchg<D>(t.x, addr32), py = xchg<D>(t.y, addr32);
+  return make_float2(fmaf(s, t.x, px), fmaf(s, t.y, py));
 }
 
 struct LaneConsts {
   float2 w[6];   // stage twiddles (index log2 D)
   float s[6];    // stage signs
   bool rot2;     // stage D = 2 twiddle is -i (b lane with bit 0 set)
+  int addr32;    // 4 * (lane ^ 32), the D = 32 exchange's source
   float2 wfold;  // w_M^{c f'} of this lane's f'
 };
 
 __device__ __forceinline__ float2 xlane_dit(float2 v, const LaneConsts& k) {
-  v = dit_stage<1>(v, k.w[0], k.s[0], false);
-  v = dit_stage<2>(v, k.w[1], k.s[1], k.rot2);
-  v = dit_stage<4>(v, k.w[2], k.s[2], false);
-  v = dit_stage<8>(v, k.w[3], k.s[3], false);
-  v = dit_stage<16>(v, k.w[4], k.s[4], false);
-  v = dit_stage<32>(v, k.w[5], k.s[5], false);
+  v = dit_stage<1>(v, k.w[0], k.s[0], false, k.addr32);
+  v = dit_stage<2>(v, k.w[1], k.s[1], k.rot2, k.addr32);
+  v = dit_stage<4>(v, k.w[2], k.s[2], false, k.addr32);
+  v = dit_stage<8>(v, k.w[3], k.s[3], false, k.addr32);
+  v = dit_stage<16>(v, k.w[4], k.s[4], false, k.addr32);
+  v = dit_stage<32>(v, k.w[5], k.s[5], false, k.addr32);
   return v;
 }
 
@@ -159,6 +148,7 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
     kc.w[st] = bl ? w : make_float2(1.f, 0.f);
   }
   kc.rot2 = (lane & 2) != 0 && (lane & 1) != 0;
+  kc.addr32 = (lane ^ 32) * 4;
   float2 wh[HFMAX];  // fold twiddles w_R^{c h} (uniform, kept in vector registers)
 #pragma unroll
   for (int h = 0; h < HFMAX; ++h) {
