@@ -7,7 +7,8 @@ chunk boundaries are searched exactly once) and a HIP stream of default
 priority.  Requests are admitted in arrival order as soon as
 
   * a device input slot is free (slots are what the HBM budget leaves after
-    the plans' own memory, one chunk each), and
+    the plans' own memory, one chunk each; a chunk already in HBM is searched
+    in place and its slot only bounds how many are in flight), and
   * the subarray's plan is idle (chunks of one subarray are searched in order),
 
 so chunks of different subarrays that arrive while others are on the GPU run
@@ -155,10 +156,19 @@ class FringeServer:
         torch = self.torch
         st = self.streams[req.sub]
         n = self.chunk_elems[req.sub]
-        dst = self.slots[slot][:n].view(req.payload.shape)
-        with torch.cuda.stream(st):
-            dst.copy_(req.payload, non_blocking=True)
-        self.plans[req.sub].search([dst.data_ptr()], st.cuda_stream)
+        pay = req.payload
+        if pay.device == self.device and pay.is_contiguous():
+            # already in HBM: the plan stages it straight from the request
+            # (which the server holds until the chunk is done); the slot only
+            # counts against the admission budget
+            src = pay
+            if torch.cuda.current_stream() != st:
+                st.wait_stream(torch.cuda.current_stream())
+        else:
+            src = self.slots[slot][:n].view(pay.shape)
+            with torch.cuda.stream(st):
+                src.copy_(pay, non_blocking=True)
+        self.plans[req.sub].search([src.data_ptr()], st.cuda_stream)
         ev = torch.cuda.Event()
         ev.record(st)
         self.busy[req.sub] = (req, slot, ev)
