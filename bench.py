@@ -34,13 +34,13 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 
 # HBM bytes of one fused-kernel launch on the full EVN-like scan, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
-# the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99989,
+# the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99990,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources they were taken on:
 # `traffic` is reported as null when the hash of csrc/ differs.
 MEASURED_TRAFFIC = {
-    "csrc_sha256": "ebd365db9e048a643a0da5ca7aaa4c74c42d7062cf97b5d3a352d8ef8021b4f1",
-    "fetch_bytes": 8326204858,
-    "write_bytes": 1934643916,
+    "csrc_sha256": "b74e9547f50fbddcb0cc48ab64e6aff7a639d178e33b95933872eff1afb6ca93",
+    "fetch_bytes": 6598477490,
+    "write_bytes": 1840910112,
 }
 
 
