@@ -59,6 +59,7 @@ __all__ = [
     "search_window_delay_only",
     "search_baseline",
     "search_scan",
+    "calibrate",
     "TABLE_DTYPE",
 ]
 
@@ -271,20 +272,38 @@ def search_baseline(x_b: np.ndarray, window_aps, pad_freq: int, pad_time: int,
     return np.array(rows, dtype=TABLE_DTYPE)
 
 
+def calibrate(vis: np.ndarray, gains) -> np.ndarray:
+    """x'[b, t, f] = g[b, f] x[b, t, f]: per-baseline, per-channel complex gains
+    applied to every AP before the search.  Paper: Eq. (1) and section
+    "Fringe fitting" (the per-IF instrumental delay and phase offsets enter the
+    phase model; removing them multiplies each channel by
+    exp(-i (2 pi f dtau + dphi))), section "Code optimization" step 3 (the
+    calibration applied ahead of the search); a gain of 0 flags a channel.
+    vis has shape (B, T, F), gains (B, F)."""
+    vis = np.asarray(vis, dtype=np.complex128)
+    g = np.asarray(gains, dtype=np.complex128)
+    if g.shape != (vis.shape[0], vis.shape[2]):
+        raise ValueError("gains must have shape (baselines, channels)")
+    return vis * g[:, None, :]
+
+
 def search_scan(vis: np.ndarray, window_aps, pad_freq: int, pad_time: int,
                 snr_threshold: float, ap_seconds: float, chan_width_hz: float,
-                scan: int = 0, baselines=None, delay_only: bool = False):
+                scan: int = 0, baselines=None, delay_only: bool = False, gains=None):
     """Full search of one scan.
 
     vis has shape (B, T, n_if, n_chan) (or (B, T, F)); the frequency index
     is f = n * n_chan + c, so all IFs form one band (section "Fringe
-    fitting": one delay across all IFs).  Returns (table, candidates): the
+    fitting": one delay across all IFs).  With gains (shape (B, F)), the
+    visibilities are calibrated first (calibrate).  Returns (table, candidates): the
     per-window table in key order (baseline, window length, start) and the
     windows whose SNR exceeds the threshold (strictly), same order.
     """
     vis = np.asarray(vis)
     b_count, n_ap = vis.shape[0], vis.shape[1]
     flat = vis.reshape(b_count, n_ap, -1)
+    if gains is not None:
+        flat = calibrate(flat, gains)
     if baselines is None:
         baselines = range(b_count)
     tables = [search_baseline(flat[b], window_aps, pad_freq, pad_time,

@@ -193,9 +193,41 @@ def check_delay_only_on_grid(mod):
         assert r.snr == pytest.approx(math.sqrt(f), rel=1e-12)
 
 
+def check_calibration(mod):
+    """Gains that remove a per-channel instrumental delay put the fringe back
+    on its true delay bin with amp = W*F and SNR = sqrt(W*F) (while the
+    uncalibrated search peaks at the sum of both delays); flagged channels
+    (gain 0) drop out of E (Parseval on the calibrated data); unit gains
+    change nothing."""
+    w, f, pf, pt, b_true, b_inst, a_rate = 4, 32, 4, 2, 21, 9, 3
+    mt, mf = pt * w, pf * f
+    u = np.arange(w)[:, None]
+    ff = np.arange(f)[None, :]
+    x = np.exp(2j * np.pi * (a_rate * u / mt + (b_true + b_inst) * ff / mf))
+    vis = x[None]                                  # one baseline
+    g = np.exp(-2j * np.pi * b_inst * np.arange(f) / mf)[None, :]
+    t_raw, _ = mod.search_scan(vis, [w], pf, pt, 1.0, 1.0, 1.0)
+    t_cal, _ = mod.search_scan(vis, [w], pf, pt, 1.0, 1.0, 1.0, gains=g)
+    assert (t_raw["k_rate"][0], t_raw["k_delay"][0]) == (a_rate, b_true + b_inst)
+    assert (t_cal["k_rate"][0], t_cal["k_delay"][0]) == (a_rate, b_true)
+    assert t_cal["amp"][0] == pytest.approx(w * f, rel=1e-12)
+    assert t_cal["snr"][0] == pytest.approx(math.sqrt(w * f), rel=1e-12)
+    rng = np.random.default_rng(29)
+    xr = _rand_x(rng, 6, f)[None]
+    mask = np.ones((1, f))
+    mask[0, 5:17] = 0.0
+    t_m, _ = mod.search_scan(xr, [2], pf, pt, 1.0, 1.0, 1.0, gains=mask)
+    e_want = [float(np.sum(np.abs(xr[0, t0:t0 + 2, mask[0] > 0]) ** 2)) for t0 in range(5)]
+    assert np.allclose(t_m["energy"], e_want, rtol=1e-12)
+    t_1, _ = mod.search_scan(xr, [2], pf, pt, 1.0, 1.0, 1.0, gains=np.ones((1, f)))
+    t_0, _ = mod.search_scan(xr, [2], pf, pt, 1.0, 1.0, 1.0)
+    assert np.array_equal(t_1, t_0)
+
+
 ALL_CHECKS = [check_c1_closed_form, check_library_fft, check_parseval_and_energy,
               check_on_grid_fringe, check_ties_and_zero, check_window_counts,
-              check_delay_only_closed_form, check_delay_only_library, check_delay_only_on_grid]
+              check_delay_only_closed_form, check_delay_only_library, check_delay_only_on_grid,
+              check_calibration]
 
 
 @pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda c: c.__name__)
@@ -337,7 +369,7 @@ def _mutant(**overrides):
     # rebind functions so their globals see the overrides
     for name in ("delay_spectra", "window_grid", "search_window", "search_baseline",
                  "search_scan", "window_starts", "grid_peak", "delay_only_row",
-                 "search_window_delay_only"):
+                 "search_window_delay_only", "calibrate"):
         f = getattr(fo, name)
         if name in overrides:
             continue
@@ -407,7 +439,13 @@ def _delay_only_grid_energy(x_b, t0, window_ap, pad_freq, a_f=None):
     return r
 
 
+def _calibrate_conjugate(vis, gains):
+    # the conjugate gains: adds the instrumental delay instead of removing it
+    return fo.calibrate(vis, np.conj(np.asarray(gains)))
+
+
 @pytest.mark.parametrize("overrides", [
+    dict(calibrate=_calibrate_conjugate),
     dict(delay_only_row=_delay_only_incoherent),
     dict(search_window_delay_only=_delay_only_grid_energy),
     dict(delay_dft_matrix=_flip_sign_delay),
@@ -416,7 +454,7 @@ def _delay_only_grid_energy(x_b, t0, window_ap, pad_freq, a_f=None):
     dict(grid_peak=_peak_last_tie),
     dict(window_starts=_starts_full_stride),
     dict(delay_spectra=_transposed_freq),
-], ids=["delay-only-incoherent", "delay-only-grid-energy", "delay-sign", "rate-pad",
+], ids=["calibration-conjugate", "delay-only-incoherent", "delay-only-grid-energy", "delay-sign", "rate-pad",
         "energy-sum", "tie-last", "stride", "freq-order"])
 def test_planted_mistake_is_caught(overrides):
     assert _fails(_mutant(**overrides))
