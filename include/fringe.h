@@ -172,6 +172,19 @@ int fringe_window_id(fringe_plan_t plan, int32_t scan, int32_t baseline,
 int fringe_grid_get(fringe_plan_t plan, int64_t window_id, fringe_cf32* host_out,
                     int64_t capacity);
 
+/* Calibration and channel flags of scan s (a subarray, with FRINGE_STREAMING)
+ * for the searches that follow (paper: Eq. (1), whose per-IF delay and phase
+ * offsets are removed by multiplying each channel by
+ * exp(-i (2 pi f dtau + dphi)); section "Code optimization", step 3).
+ * d_gains: device address of n_baselines x F complex gains, [b][f] with
+ * f = n * n_chan + c; every sample of baseline b, channel f is multiplied by
+ * g[b][f] before the delay transform (0 flags a channel; a real factor
+ * scales it).  E and SNR are those of the calibrated data.  The caller owns
+ * the gains and keeps them valid and unchanged while searches that use them
+ * may run; NULL returns to unit gains.  Errors: FRINGE_E_INVALID for a null
+ * plan or a scan index out of range. */
+int fringe_set_gains(fringe_plan_t plan, int32_t scan, const fringe_cf32* d_gains);
+
 /* Kernel times of the last search of a plan made with FRINGE_PROFILE,
  * measured with HIP events recorded on the search's stream around each
  * launch (waits for the search).  Times in milliseconds, summed over the

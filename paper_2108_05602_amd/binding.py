@@ -39,7 +39,7 @@ FRINGE_DELAY_ONLY = 0x20
 ENTRY_POINTS = (
     "fringe_plan_check", "fringe_plan", "fringe_search", "candidates_get",
     "fringe_windows_get", "fringe_window_id", "fringe_grid_get", "fringe_profile_get",
-    "fringe_plan_info",
+    "fringe_plan_info", "fringe_set_gains",
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
 )
 
@@ -265,6 +265,13 @@ def fringe_plan_info(plan: int) -> dict:
     return {k: getattr(out, k) for k, _ in fringe_plan_summary._fields_}
 
 
+def fringe_set_gains(plan: int, scan: int, d_gains) -> None:
+    """d_gains: device address (int) of [n_baselines][F] complex64 gains, or None."""
+    lib = load()
+    _check(lib.fringe_set_gains(c_void_p(plan), c_int32(int(scan)), c_void_p(d_gains or None)),
+           "fringe_set_gains")
+
+
 def fringe_plan_destroy(plan: int) -> None:
     if plan:
         load().fringe_plan_destroy(c_void_p(plan))
@@ -296,6 +303,9 @@ class Plan:
 
     def info(self):
         return fringe_plan_info(self.handle)
+
+    def set_gains(self, scan, d_gains):
+        fringe_set_gains(self.handle, scan, d_gains)
 
     def profile(self):
         return fringe_profile_get(self.handle)

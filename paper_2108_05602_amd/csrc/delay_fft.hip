@@ -2,7 +2,8 @@
 // over the concatenated IF x channel axis (paper, section "Code
 // optimization", step 5; padding factor of section "Fringe fitting"):
 //   X_t[k] = sum_{f<F} x_t[f] exp(-2 pi i k f / M),  M = pad_f * F,
-// plus the AP energy e_t = sum_f |x_t[f]|^2 that the window SNR divides by.
+// plus the AP energy e_t = sum_f |x_t[f]|^2 that the window SNR divides by
+// (x multiplied first by the slab's calibration gains when it has them).
 //
 // One wavefront per work group.  A wave transforms NAP = max(1, 1024 / M)
 // APs at a time with a self-sorting (Stockham) FFT: radix-16 passes, then
@@ -58,7 +59,8 @@ template <int M, int NAP, int R, int NS, int PF, bool FIRST, bool LAST>
 __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ xin,
                                               float2* __restrict__ xout,
                                               const float2* __restrict__ tw, int lane,
-                                              int n_valid_ap, int F, float* esum) {
+                                              int n_valid_ap, int F, float* esum,
+                                              const float2* __restrict__ gains = nullptr) {
   constexpr int NBF = NAP * M / R;   // butterflies in this pass
   constexpr int BPL = NBF / 64;      // per lane
   static_assert(BPL >= 1 && NBF % 64 == 0, "pass does not fill the wave");
@@ -77,7 +79,10 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
         if (r < NZ) {
           const int idx = j + r * SPAN;
           float2 x = make_float2(0.f, 0.f);
-          if (ok && idx < F) x = xin[static_cast<int64_t>(a) * F + idx];
+          if (ok && idx < F) {
+            x = xin[static_cast<int64_t>(a) * F + idx];
+            if (gains) x = c_mul(x, gains[idx]);  // calibration
+          }
           v[i][r] = x;
           *esum += c_norm(x);
         } else {
@@ -149,8 +154,9 @@ __global__ void __launch_bounds__(64) delay_fft_kernel(DelayArgs a) {
     float2* xout = a.X + ap0 * M;
     float es = 0.f;
     constexpr bool ONE_PASS = (R0 == M);
+    const float2* gains = a.gains ? a.gains + static_cast<int64_t>(b) * F : nullptr;
     stockham_pass<M, NAP, R0, 1, PF, true, ONE_PASS>(lds, xin, xout, a.tw, lane, n_valid, F,
-                                                     &es);
+                                                     &es, gains);
     // AP energies: lanes of one AP form an aligned group of GROUP lanes.
 #pragma unroll
     for (int off = GROUP / 2; off >= 1; off >>= 1) es += __shfl_xor(es, off, 64);

@@ -434,6 +434,7 @@ struct fringe_plan_s {
   hipStream_t cap_st = nullptr;
   hipGraphExec_t gexec = nullptr;
   int g_arena = -1;
+  std::vector<const float2*> gains;  // per scan: [n_baselines][F] device gains or nullptr
   // streaming
   std::vector<StreamState> streams;
   std::vector<CallScan> call;      // numbering of the last search
@@ -567,6 +568,8 @@ FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan
   const Sizing& z = p->sz;
   FusedArgs fu{};
   fu.vis = data ? data + int64_t(u.b0) * vis_stride : nullptr;
+  const float2* g = p->gains.empty() ? nullptr : p->gains[u.scan];
+  fu.gains = g ? g + int64_t(u.b0) * si.F : nullptr;
   fu.vis_stride = vis_stride;
   fu.part = p->part + u.part_off;
   fu.epart = p->epart ? p->epart + u.part_off : nullptr;
@@ -677,6 +680,7 @@ int plain_tables(fringe_plan_s* p, const std::vector<const float2*>& data) {
           Unit u{int(s), 0, 1, 0, 0};
           const float2* base = data[s] + (int64_t(b) * si.d.n_ap + j * stride) * si.F;
           fus[i] = fused_entry(p, si, one, u, base, int64_t(si.d.n_ap) * si.F);
+          fus[i].gains = p->gains[s] ? p->gains[s] + int64_t(b) * si.F : nullptr;
           fus[i].block_off = 0;
           // only this length: the shorter windows inside these W APs are
           // other entries' work
@@ -737,6 +741,7 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
   auto* p = new fringe_plan_s();
   p->sz = std::move(sz);
   p->params = *params;
+  p->gains.assign(size_t(n_scans), nullptr);
   p->window_aps.assign(params->window_aps, params->window_aps + params->n_window_lengths);
   p->params.window_aps = p->window_aps.data();
   hipError_t he = hipGetDevice(&p->device);
@@ -938,6 +943,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       if (grp_windows[g] == 0) continue;
       DelayArgs da{};
       da.vis = hfus[ui].vis;
+      da.gains = hfus[ui].gains;
       da.vis_stride = hfus[ui].vis_stride;
       da.X = p->X;
       da.e = p->e + u.e_off;
@@ -1149,6 +1155,14 @@ int fringe_grid_get(fringe_plan_t p, int64_t id, fringe_cf32* host_out, int64_t 
   if (he == hipSuccess)
     he = hipMemcpy(host_out, p->grid + off, size_t(n) * sizeof(float2), hipMemcpyDeviceToHost);
   if (he != hipSuccess) return hip_fail(he, "copying grid");
+  return FRINGE_OK;
+}
+
+int fringe_set_gains(fringe_plan_t p, int32_t scan, const fringe_cf32* d_gains) {
+  if (!p) return fail(FRINGE_E_INVALID, "null plan");
+  if (scan < 0 || scan >= int32_t(p->gains.size()))
+    return fail(FRINGE_E_INVALID, "scan %d out of range [0, %d)", scan, int(p->gains.size()));
+  p->gains[size_t(scan)] = reinterpret_cast<const float2*>(d_gains);
   return FRINGE_OK;
 }
 

@@ -177,6 +177,10 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
     for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h], row_off);
   };
   const bool band_full = F == 64 * HFMAX;  // every lane in band for every fold
+  // calibration: the baseline's gains, read where they are applied (cache
+  // hits after the first AP; held in registers they would cost occupancy)
+  const bool has_g = a.gains != nullptr;
+  const auto grs = buffer_of(has_g ? a.gains + static_cast<int64_t>(b) * F : a.tw);
   auto sample = [&](float2 x, int h, bool t_in) {
     const bool ok = t_in && lane_in[h];
     return make_float2(ok ? x.x : 0.f, ok ? x.y : 0.f);
@@ -247,6 +251,10 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
         const bool t_in = t < T;
 #pragma unroll
         for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
+      }
+      if (has_g) {
+#pragma unroll
+        for (int h = 0; h < HFMAX; ++h) pre[fs][h] = c_mul(pre[fs][h], ld_buffer(grs, lane_off[h], 0));
       }
       float2 z = pre[fs][0];
 #pragma unroll

@@ -29,14 +29,25 @@ def to_device(vis: np.ndarray):
 
 
 def run_gpu(scans, vis_list, window_aps, pad_freq, pad_time, snr_threshold,
-            max_candidates=1 << 16, flags=0, all_windows=True):
-    """Plan + search on cuda:0; returns (plan, table or None, candidates)."""
+            max_candidates=1 << 16, flags=0, all_windows=True, gains=None):
+    """Plan + search on cuda:0; returns (plan, table or None, candidates).
+    gains: None, or per scan None / a (B, F) complex array."""
     import torch
 
     import paper_2108_05602_amd as F
     tensors = [to_device(v) for v in vis_list]
     plan = F.Plan(scans, window_aps, pad_freq=pad_freq, pad_time=pad_time,
                   snr_threshold=snr_threshold, max_candidates=max_candidates, flags=flags)
+    g_dev = []
+    if gains is not None:
+        for s, g in enumerate(gains):
+            if g is None:
+                continue
+            d = scans[s]
+            g = np.ascontiguousarray(np.asarray(g, dtype=np.complex64))
+            assert g.shape == (d["n_baselines"], d["n_if"] * d["n_chan"])
+            g_dev.append(to_device(g))
+            plan.set_gains(s, g_dev[-1].data_ptr())
     plan.search([t.data_ptr() for t in tensors], torch.cuda.current_stream().cuda_stream)
     cands = plan.candidates()
     table = None
@@ -45,6 +56,7 @@ def run_gpu(scans, vis_list, window_aps, pad_freq, pad_time, snr_threshold,
         table = plan.windows(np.arange(n, dtype=np.int64)) if n else np.zeros(0, cands.dtype)
     torch.cuda.synchronize()
     del tensors
+    del g_dev
     return plan, table, cands
 
 
@@ -111,11 +123,14 @@ def compare_candidates(gpu_c, ref_table, threshold, label=""):
     assert diff <= near, f"{label}: candidate lists differ at {sorted(diff - near)[:10]}"
 
 
-def oracle_table(scans_vis, scans, window_aps, pad_freq, pad_time, threshold, delay_only=False):
-    """Reference table for several scans, in window-id order, with `scan` set."""
+def oracle_table(scans_vis, scans, window_aps, pad_freq, pad_time, threshold, delay_only=False,
+                 gains=None):
+    """Reference table for several scans, in window-id order, with `scan` set.
+    gains: None, or per scan None / a (B, F) array of calibration gains."""
     tabs = []
     for s, (v, d) in enumerate(zip(scans_vis, scans)):
+        g = None if gains is None else gains[s]
         t, _ = fo.search_scan(v, window_aps, pad_freq, pad_time, threshold, d["ap_seconds"],
-                              d["chan_width_hz"], scan=s, delay_only=delay_only)
+                              d["chan_width_hz"], scan=s, delay_only=delay_only, gains=g)
         tabs.append(t)
     return np.concatenate(tabs)
