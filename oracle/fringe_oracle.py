@@ -60,6 +60,7 @@ __all__ = [
     "search_baseline",
     "search_scan",
     "calibrate",
+    "dedisperse",
     "TABLE_DTYPE",
 ]
 
@@ -287,15 +288,36 @@ def calibrate(vis: np.ndarray, gains) -> np.ndarray:
     return vis * g[:, None, :]
 
 
+def dedisperse(vis: np.ndarray, shifts) -> np.ndarray:
+    """x'[b, t, f] = x[b, t + d_f, f], and 0 where t + d_f runs past the data:
+    each channel moved earlier by its dispersion delay d_f >= 0 (in APs)
+    relative to the reference (highest) frequency.  Paper: section "Code
+    optimization", step 4 (dedispersion of the buffer for one DM value: a
+    time shift per frequency point).  vis has shape (B, T, F), shifts (F,)."""
+    vis = np.asarray(vis, dtype=np.complex128)
+    d = np.asarray(shifts, dtype=np.int64)
+    b_count, n_ap, n_freq = vis.shape
+    if d.shape != (n_freq,) or np.any(d < 0):
+        raise ValueError("shifts must be F non-negative AP counts")
+    out = np.zeros_like(vis)
+    for f in range(n_freq):
+        k = int(d[f])
+        if k < n_ap:
+            out[:, :n_ap - k, f] = vis[:, k:, f]
+    return out
+
+
 def search_scan(vis: np.ndarray, window_aps, pad_freq: int, pad_time: int,
                 snr_threshold: float, ap_seconds: float, chan_width_hz: float,
-                scan: int = 0, baselines=None, delay_only: bool = False, gains=None):
+                scan: int = 0, baselines=None, delay_only: bool = False, gains=None,
+                shifts=None):
     """Full search of one scan.
 
     vis has shape (B, T, n_if, n_chan) (or (B, T, F)); the frequency index
     is f = n * n_chan + c, so all IFs form one band (section "Fringe
     fitting": one delay across all IFs).  With gains (shape (B, F)), the
-    visibilities are calibrated first (calibrate).  Returns (table, candidates): the
+    visibilities are calibrated first (calibrate), with shifts (shape (F,))
+    dedispersed (dedisperse; the two commute).  Returns (table, candidates): the
     per-window table in key order (baseline, window length, start) and the
     windows whose SNR exceeds the threshold (strictly), same order.
     """
@@ -304,6 +326,8 @@ def search_scan(vis: np.ndarray, window_aps, pad_freq: int, pad_time: int,
     flat = vis.reshape(b_count, n_ap, -1)
     if gains is not None:
         flat = calibrate(flat, gains)
+    if shifts is not None:
+        flat = dedisperse(flat, shifts)
     if baselines is None:
         baselines = range(b_count)
     tables = [search_baseline(flat[b], window_aps, pad_freq, pad_time,

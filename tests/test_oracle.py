@@ -224,10 +224,35 @@ def check_calibration(mod):
     assert np.array_equal(t_1, t_0)
 
 
+def check_dedispersion(mod):
+    """A unit pulse that reaches channel f at AP t0 + d_f (dispersed) is
+    restored by the shifts d_f: the one-AP window at t0 then holds every
+    channel, amp = F and SNR = sqrt(F) at delay bin 0, and the APs after it
+    are empty; with zero shifts the search is unchanged."""
+    f, t, t0 = 32, 40, 5
+    d = (np.arange(f)[::-1] * 3) // 4          # 0 .. 23 APs, larger at low f
+    vis = np.zeros((1, t, f), complex)
+    vis[0, t0 + d, np.arange(f)] = 1.0
+    tab, _ = mod.search_scan(vis, [1], 4, 2, 1.0, 1.0, 1.0, shifts=d)
+    r = tab[tab["t_start"] == t0][0]
+    assert (r["k_rate"], r["k_delay"]) == (0, 0)
+    assert r["amp"] == pytest.approx(f, rel=1e-12)
+    assert r["snr"] == pytest.approx(math.sqrt(f), rel=1e-12)
+    assert np.all(tab[tab["t_start"] != t0]["amp"] == 0.0)
+    raw, _ = mod.search_scan(vis, [1], 4, 2, 1.0, 1.0, 1.0)
+    # undispersed, the window at t0 holds only the channels with no delay
+    assert raw[raw["t_start"] == t0]["amp"][0] == pytest.approx(float(np.sum(d == 0)), rel=1e-12)
+    rng = np.random.default_rng(31)
+    xr = _rand_x(rng, 9, 16)[None]
+    z, _ = mod.search_scan(xr, [1, 4], 4, 2, 1.0, 1.0, 1.0, shifts=np.zeros(16, int))
+    n, _ = mod.search_scan(xr, [1, 4], 4, 2, 1.0, 1.0, 1.0)
+    assert np.array_equal(z, n)
+
+
 ALL_CHECKS = [check_c1_closed_form, check_library_fft, check_parseval_and_energy,
               check_on_grid_fringe, check_ties_and_zero, check_window_counts,
               check_delay_only_closed_form, check_delay_only_library, check_delay_only_on_grid,
-              check_calibration]
+              check_calibration, check_dedispersion]
 
 
 @pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda c: c.__name__)
@@ -369,7 +394,7 @@ def _mutant(**overrides):
     # rebind functions so their globals see the overrides
     for name in ("delay_spectra", "window_grid", "search_window", "search_baseline",
                  "search_scan", "window_starts", "grid_peak", "delay_only_row",
-                 "search_window_delay_only", "calibrate"):
+                 "search_window_delay_only", "calibrate", "dedisperse"):
         f = getattr(fo, name)
         if name in overrides:
             continue
@@ -439,6 +464,16 @@ def _delay_only_grid_energy(x_b, t0, window_ap, pad_freq, a_f=None):
     return r
 
 
+def _dedisperse_backwards(vis, shifts):
+    # channels moved later instead of earlier
+    vis = np.asarray(vis, complex)
+    out = np.zeros_like(vis)
+    for f, k in enumerate(np.asarray(shifts, int)):
+        if k < vis.shape[1]:
+            out[:, k:, f] = vis[:, :vis.shape[1] - k, f]
+    return out
+
+
 def _calibrate_conjugate(vis, gains):
     # the conjugate gains: adds the instrumental delay instead of removing it
     return fo.calibrate(vis, np.conj(np.asarray(gains)))
@@ -446,6 +481,7 @@ def _calibrate_conjugate(vis, gains):
 
 @pytest.mark.parametrize("overrides", [
     dict(calibrate=_calibrate_conjugate),
+    dict(dedisperse=_dedisperse_backwards),
     dict(delay_only_row=_delay_only_incoherent),
     dict(search_window_delay_only=_delay_only_grid_energy),
     dict(delay_dft_matrix=_flip_sign_delay),
@@ -454,7 +490,7 @@ def _calibrate_conjugate(vis, gains):
     dict(grid_peak=_peak_last_tie),
     dict(window_starts=_starts_full_stride),
     dict(delay_spectra=_transposed_freq),
-], ids=["calibration-conjugate", "delay-only-incoherent", "delay-only-grid-energy", "delay-sign", "rate-pad",
+], ids=["calibration-conjugate", "dedispersion-backwards", "delay-only-incoherent", "delay-only-grid-energy", "delay-sign", "rate-pad",
         "energy-sum", "tie-last", "stride", "freq-order"])
 def test_planted_mistake_is_caught(overrides):
     assert _fails(_mutant(**overrides))
