@@ -185,6 +185,20 @@ int fringe_grid_get(fringe_plan_t plan, int64_t window_id, fringe_cf32* host_out
  * plan or a scan index out of range. */
 int fringe_set_gains(fringe_plan_t plan, int32_t scan, const fringe_cf32* d_gains);
 
+/* Dedispersion of scan s for the searches that follow (paper: section
+ * "Code optimization", step 4: a time shift per frequency point for one DM
+ * value).  d_shifts: device address of F int32 AP counts d_f >= 0; the
+ * search sees x'[b][t][f] = x[b][t + d_f][f], and 0 where t + d_f runs past
+ * the scan (values are clamped to [0, n_ap]).  Several DM trials of one cube
+ * are several scans of one plan with the same visibility pointer and their
+ * own shifts: one search call, one launch.  The caller owns the shifts and
+ * keeps them valid and unchanged while searches that use them may run; NULL
+ * removes them.  Errors: FRINGE_E_INVALID for a null plan or a scan out of
+ * range; FRINGE_E_UNSUPPORTED for streaming or FRINGE_PLAIN plans (a
+ * shifted window reads APs past its own) and for baselines of 1 GiB or more
+ * of samples. */
+int fringe_set_shifts(fringe_plan_t plan, int32_t scan, const int32_t* d_shifts);
+
 /* Kernel times of the last search of a plan made with FRINGE_PROFILE,
  * measured with HIP events recorded on the search's stream around each
  * launch (waits for the search).  Times in milliseconds, summed over the

@@ -39,7 +39,7 @@ FRINGE_DELAY_ONLY = 0x20
 ENTRY_POINTS = (
     "fringe_plan_check", "fringe_plan", "fringe_search", "candidates_get",
     "fringe_windows_get", "fringe_window_id", "fringe_grid_get", "fringe_profile_get",
-    "fringe_plan_info", "fringe_set_gains",
+    "fringe_plan_info", "fringe_set_gains", "fringe_set_shifts",
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
 )
 
@@ -272,6 +272,13 @@ def fringe_set_gains(plan: int, scan: int, d_gains) -> None:
            "fringe_set_gains")
 
 
+def fringe_set_shifts(plan: int, scan: int, d_shifts) -> None:
+    """d_shifts: device address (int) of F int32 AP shifts, or None."""
+    lib = load()
+    _check(lib.fringe_set_shifts(c_void_p(plan), c_int32(int(scan)), c_void_p(d_shifts or None)),
+           "fringe_set_shifts")
+
+
 def fringe_plan_destroy(plan: int) -> None:
     if plan:
         load().fringe_plan_destroy(c_void_p(plan))
@@ -306,6 +313,9 @@ class Plan:
 
     def set_gains(self, scan, d_gains):
         fringe_set_gains(self.handle, scan, d_gains)
+
+    def set_shifts(self, scan, d_shifts):
+        fringe_set_shifts(self.handle, scan, d_shifts)
 
     def profile(self):
         return fringe_profile_get(self.handle)

@@ -60,7 +60,10 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
                                               float2* __restrict__ xout,
                                               const float2* __restrict__ tw, int lane,
                                               int n_valid_ap, int F, float* esum,
-                                              const float2* __restrict__ gains = nullptr) {
+                                              const float2* __restrict__ gains = nullptr,
+                                              const int32_t* __restrict__ shifts = nullptr,
+                                              const float2* __restrict__ xbl = nullptr,
+                                              int t_first = 0, int T = 0) {
   constexpr int NBF = NAP * M / R;   // butterflies in this pass
   constexpr int BPL = NBF / 64;      // per lane
   static_assert(BPL >= 1 && NBF % 64 == 0, "pass does not fill the wave");
@@ -80,7 +83,12 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
           const int idx = j + r * SPAN;
           float2 x = make_float2(0.f, 0.f);
           if (ok && idx < F) {
-            x = xin[static_cast<int64_t>(a) * F + idx];
+            if (shifts) {  // dedispersion: channel idx from AP t + d, 0 past the data
+              const int row = t_first + a + min(max(shifts[idx], 0), T);
+              if (row < T) x = xbl[static_cast<int64_t>(row) * F + idx];
+            } else {
+              x = xin[static_cast<int64_t>(a) * F + idx];
+            }
             if (gains) x = c_mul(x, gains[idx]);  // calibration
           }
           v[i][r] = x;
@@ -155,8 +163,9 @@ __global__ void __launch_bounds__(64) delay_fft_kernel(DelayArgs a) {
     float es = 0.f;
     constexpr bool ONE_PASS = (R0 == M);
     const float2* gains = a.gains ? a.gains + static_cast<int64_t>(b) * F : nullptr;
+    const float2* xbl = a.vis + static_cast<int64_t>(b) * a.vis_stride;
     stockham_pass<M, NAP, R0, 1, PF, true, ONE_PASS>(lds, xin, xout, a.tw, lane, n_valid, F,
-                                                     &es, gains);
+                                                     &es, gains, a.shifts, xbl, t0, a.T);
     // AP energies: lanes of one AP form an aligned group of GROUP lanes.
 #pragma unroll
     for (int off = GROUP / 2; off >= 1; off >>= 1) es += __shfl_xor(es, off, 64);

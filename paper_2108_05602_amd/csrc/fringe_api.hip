@@ -245,7 +245,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
         int64_t(data_len(si, sz.streaming)) > (int64_t(1) << 30))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: too many windows", s);
     // the fused kernel addresses one baseline's samples with 32-bit offsets
-    if (sz.fused && int64_t(data_len(si, sz.streaming)) * F * int64_t(sizeof(float2)) >= (int64_t(1) << 32))
+    if (sz.fused && (int64_t(data_len(si, sz.streaming)) + 1) * F * int64_t(sizeof(float2)) >= (int64_t(1) << 32))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: a baseline holds 4 GiB or more of samples", s);
     si.full.win_off = win_off;
     si.grid_off = grid_off;
@@ -435,6 +435,7 @@ struct fringe_plan_s {
   hipGraphExec_t gexec = nullptr;
   int g_arena = -1;
   std::vector<const float2*> gains;  // per scan: [n_baselines][F] device gains or nullptr
+  std::vector<const int32_t*> shifts;  // per scan: [F] dedispersion shifts or nullptr
   // streaming
   std::vector<StreamState> streams;
   std::vector<CallScan> call;      // numbering of the last search
@@ -570,6 +571,7 @@ FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan
   fu.vis = data ? data + int64_t(u.b0) * vis_stride : nullptr;
   const float2* g = p->gains.empty() ? nullptr : p->gains[u.scan];
   fu.gains = g ? g + int64_t(u.b0) * si.F : nullptr;
+  fu.shifts = p->shifts.empty() ? nullptr : p->shifts[u.scan];
   fu.vis_stride = vis_stride;
   fu.part = p->part + u.part_off;
   fu.epart = p->epart ? p->epart + u.part_off : nullptr;
@@ -742,6 +744,7 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
   p->sz = std::move(sz);
   p->params = *params;
   p->gains.assign(size_t(n_scans), nullptr);
+  p->shifts.assign(size_t(n_scans), nullptr);
   p->window_aps.assign(params->window_aps, params->window_aps + params->n_window_lengths);
   p->params.window_aps = p->window_aps.data();
   hipError_t he = hipGetDevice(&p->device);
@@ -944,6 +947,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       DelayArgs da{};
       da.vis = hfus[ui].vis;
       da.gains = hfus[ui].gains;
+      da.shifts = hfus[ui].shifts;
       da.vis_stride = hfus[ui].vis_stride;
       da.X = p->X;
       da.e = p->e + u.e_off;
@@ -1163,6 +1167,22 @@ int fringe_set_gains(fringe_plan_t p, int32_t scan, const fringe_cf32* d_gains) 
   if (scan < 0 || scan >= int32_t(p->gains.size()))
     return fail(FRINGE_E_INVALID, "scan %d out of range [0, %d)", scan, int(p->gains.size()));
   p->gains[size_t(scan)] = reinterpret_cast<const float2*>(d_gains);
+  return FRINGE_OK;
+}
+
+int fringe_set_shifts(fringe_plan_t p, int32_t scan, const int32_t* d_shifts) {
+  if (!p) return fail(FRINGE_E_INVALID, "null plan");
+  if (scan < 0 || scan >= int32_t(p->shifts.size()))
+    return fail(FRINGE_E_INVALID, "scan %d out of range [0, %d)", scan, int(p->shifts.size()));
+  if (d_shifts) {
+    if (p->params.flags & (FRINGE_STREAMING | FRINGE_PLAIN))
+      return fail(FRINGE_E_UNSUPPORTED,
+                  "dedispersion needs the whole scan: not with FRINGE_STREAMING or FRINGE_PLAIN");
+    const ScanInfo& si = p->sz.scans[size_t(scan)];
+    if (int64_t(si.d.n_ap) * si.F * int64_t(sizeof(float2)) >= (int64_t(1) << 30))
+      return fail(FRINGE_E_UNSUPPORTED, "scan %d: dedispersion needs baselines under 1 GiB", scan);
+  }
+  p->shifts[size_t(scan)] = d_shifts;
   return FRINGE_OK;
 }
 

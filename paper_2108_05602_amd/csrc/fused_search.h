@@ -169,18 +169,37 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
     lane_off[h] = lane_in[h] ? static_cast<uint32_t>(f) * sizeof(float2) : 0u;
   }
   // (a baseline's data is < 4 GiB, checked at plan time)
-  const auto vrs = buffer_of(xb);
   const uint32_t row_bytes = static_cast<uint32_t>(F) * sizeof(float2);
-  auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
-    const uint32_t row_off = static_cast<uint32_t>(min(t, T - 1)) * row_bytes;
+  // dedispersion: channel f of AP t is read from AP t + d_f.  The shift is
+  // folded into the lane's offset, the AP is added to it (not given as the
+  // scalar offset), and the buffer's record limit, the baseline's T rows,
+  // turns the reads past the data into zeros (with shifts a baseline is
+  // < 1 GiB, so no offset wraps).  Without shifts every read is in range.
+  const bool has_s = a.shifts != nullptr;
+  if (has_s) {
 #pragma unroll
-    for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h], row_off);
+    for (int h = 0; h < HFMAX; ++h)
+      if (lane_in[h])
+        lane_off[h] += static_cast<uint32_t>(min(max(a.shifts[lane + 64 * h], 0), T)) * row_bytes;
+  }
+  const auto vrs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2*>(xb), static_cast<short>(0),
+      static_cast<int>(static_cast<uint32_t>(T) * row_bytes), kBufferWord3);
+  auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
+    const uint32_t toff = static_cast<uint32_t>(min(t, T - 1)) * row_bytes;
+#pragma unroll
+    for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h] + toff, 0);
   };
   const bool band_full = F == 64 * HFMAX;  // every lane in band for every fold
   // calibration: the baseline's gains, read where they are applied (cache
-  // hits after the first AP; held in registers they would cost occupancy)
+  // hits after the first AP; held in registers they would cost occupancy).
+  // Their buffer holds exactly the baseline's F gains, so lanes past the
+  // band read zeros.
   const bool has_g = a.gains != nullptr;
-  const auto grs = buffer_of(has_g ? a.gains + static_cast<int64_t>(b) * F : a.tw);
+  const auto grs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2*>(has_g ? a.gains + static_cast<int64_t>(b) * F : a.tw), static_cast<short>(0),
+      static_cast<int>(static_cast<uint32_t>(F) * sizeof(float2)), kBufferWord3);
+  const uint32_t lane8 = static_cast<uint32_t>(lane) * sizeof(float2);
   auto sample = [&](float2 x, int h, bool t_in) {
     const bool ok = t_in && lane_in[h];
     return make_float2(ok ? x.x : 0.f, ok ? x.y : 0.f);
@@ -254,7 +273,8 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
       }
       if (has_g) {
 #pragma unroll
-        for (int h = 0; h < HFMAX; ++h) pre[fs][h] = c_mul(pre[fs][h], ld_buffer(grs, lane_off[h], 0));
+        for (int h = 0; h < HFMAX; ++h)
+          pre[fs][h] = c_mul(pre[fs][h], ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0));
       }
       float2 z = pre[fs][0];
 #pragma unroll

@@ -42,6 +42,7 @@ struct ScanDev {
 struct DelayArgs {
   const float2* vis;   // [nb][T][F] visibilities of the slab
   const float2* gains; // [nb][F] calibration gains of the slab, or nullptr
+  const int32_t* shifts;  // [F] dedispersion shifts in APs, or nullptr
   int64_t vis_stride;  // elements between baselines of vis (>= T * F)
   float2* X;           // [nb][T][M] delay spectra (out)
   float* e;            // [nb][T] per-AP energy sum |x|^2 (out)
@@ -71,6 +72,7 @@ struct FusedArgs {
   int64_t block_off;   // first block of this entry in the launch (a multiple of 8)
   const float2* vis;   // [nb][T][F] visibilities of the slab
   const float2* gains; // [nb][F] calibration gains of the slab, or nullptr
+  const int32_t* shifts;  // [F] dedispersion shifts in APs, or nullptr
   int64_t vis_stride;  // elements between baselines of vis (>= T * F)
   uint64_t* part;      // [R][slab_windows] per residue-class peak keys (out)
   float* epart;        // [R][slab_windows] per residue-class sum of |G_0|^2 (delay-only, out)

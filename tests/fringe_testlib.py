@@ -124,13 +124,16 @@ def compare_candidates(gpu_c, ref_table, threshold, label=""):
 
 
 def oracle_table(scans_vis, scans, window_aps, pad_freq, pad_time, threshold, delay_only=False,
-                 gains=None):
+                 gains=None, shifts=None):
     """Reference table for several scans, in window-id order, with `scan` set.
-    gains: None, or per scan None / a (B, F) array of calibration gains."""
+    gains: None, or per scan None / a (B, F) array of calibration gains;
+    shifts: None, or per scan None / an (F,) array of dedispersion shifts."""
     tabs = []
     for s, (v, d) in enumerate(zip(scans_vis, scans)):
         g = None if gains is None else gains[s]
+        sh = None if shifts is None else shifts[s]
         t, _ = fo.search_scan(v, window_aps, pad_freq, pad_time, threshold, d["ap_seconds"],
-                              d["chan_width_hz"], scan=s, delay_only=delay_only, gains=g)
+                              d["chan_width_hz"], scan=s, delay_only=delay_only, gains=g,
+                              shifts=sh)
         tabs.append(t)
     return np.concatenate(tabs)

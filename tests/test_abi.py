@@ -6,6 +6,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 import paper_2108_05602_amd as F
@@ -158,3 +160,17 @@ def test_streaming_sizing():
 
 def test_dump_grid_only_for_small_plans():
     assert _code(lambda: F.fringe_plan_check([C2], C2_W, flags=B.FRINGE_DUMP_GRID)) == B.FRINGE_E_INVALID
+
+
+def test_dm_shifts():
+    """Dispersion shifts: the cold-plasma law at two frequencies, rounding to
+    APs, the highest channel as the zero reference."""
+    from paper_2108_05602_amd.dedisp import channel_freqs_hz, dm_shifts
+    f = channel_freqs_hz(1.6e9, 8, 32, 0.5e6)
+    assert f.shape == (256,) and f[0] == 1.6e9 and f[32] == 1.616e9 and f[-1] == 1.6e9 + 127.5e6
+    d = dm_shifts(100.0, f, 1.024e-3)
+    # 100 pc cm^-3 between 1600 and 1727.5 MHz: 4148.808 * 100 * (1600^-2 - 1727.5^-2) s
+    want = 4148.808 * 100 * (1600.0 ** -2 - 1727.5 ** -2) / 1.024e-3
+    assert d[0] == int(round(want)) and d[-1] == 0
+    assert np.all(np.diff(d) <= 0) and d.dtype == np.int32
+    assert np.all(dm_shifts(0.0, f, 1e-3) == 0)

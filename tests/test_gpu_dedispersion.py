@@ -1,0 +1,174 @@
+"""Dedispersion shifts (fringe_set_shifts) on cuda:0 against the CPU
+reference, which moves channel f of every AP t to t - d_f (0 past the data)
+before the search.
+
+Covered: the fused path (windows to 32 and to 64 APs), the two-pass path
+(W = 128), the delay-only search, shifts with calibration gains, a
+dispersed pulse restored exactly, and a batch of DM trials searched as
+scans of one plan over one cube (one launch) equal to separate plans.  The
+cubes are followed in device memory by NaN samples, so a read past a
+baseline's data that was not turned into zeros would show in the results.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from fringe_testlib import compare_candidates, compare_windows, oracle_table, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _padded(v):
+    """The cube on the device followed by NaN samples, T + 64 APs of them (more
+    than any read past the last baseline could reach: shifts are clamped to
+    T); returns (tensor, ptr)."""
+    import torch
+    v = np.ascontiguousarray(v)
+    t, nf = v.shape[1], int(np.prod(v.shape[2:]))
+    flat = torch.from_numpy(v.reshape(-1))
+    buf = torch.full((flat.numel() + (t + 64) * nf,), complex(float("nan"), float("nan")),
+                     dtype=torch.complex64, device="cuda")
+    buf[:flat.numel()].copy_(flat.cuda())
+    return buf, buf.data_ptr()
+
+
+def _run(descs, ptrs, ws, pf, pt, thr, flags=0, shifts=None, gains=None):
+    import torch
+
+    import paper_2108_05602_amd as F
+    keep = []
+    plan = F.Plan(descs, ws, pad_freq=pf, pad_time=pt, snr_threshold=thr, flags=flags,
+                  max_candidates=1 << 16)
+    for s in range(len(descs)):
+        if shifts is not None and shifts[s] is not None:
+            keep.append(to_device(np.asarray(shifts[s], dtype=np.int32)))
+            plan.set_shifts(s, keep[-1].data_ptr())
+        if gains is not None and gains[s] is not None:
+            keep.append(to_device(np.asarray(gains[s], dtype=np.complex64)))
+            plan.set_gains(s, keep[-1].data_ptr())
+    plan.search(ptrs, torch.cuda.current_stream().cuda_stream)
+    table = plan.windows(np.arange(plan.info()["n_windows"]))
+    cands = plan.candidates()
+    torch.cuda.synchronize()
+    return plan, table, cands
+
+
+def _shifted(v, d):
+    out = np.zeros_like(v)
+    for f, k in enumerate(d):
+        if k < v.shape[1]:
+            out[:, :v.shape[1] - k, f] = v[:, k:, f]
+    return out
+
+
+@pytest.mark.parametrize("case", [
+    # (n_bl, T, n_if, n_chan, windows, pad_f, pad_t, kind, max shift)
+    (3, 400, 8, 32, [1, 2, 4, 8, 16, 32], 4, 2, "full", 40),
+    (2, 300, 4, 16, [1, 4, 16, 64], 4, 2, "full", 90),
+    (2, 300, 8, 8, [1, 128], 4, 2, "full", 35),          # two-pass path
+    (2, 500, 4, 16, [1, 2, 4, 8, 16, 32], 2, 2, "delay-only", 60),
+    (2, 260, 8, 32, [2, 8, 32], 4, 1, "gains", 300),      # shifts past the data too
+], ids=["fused32", "fused64", "two-pass", "delay-only", "with-gains"])
+def test_shift_parity(case):
+    import paper_2108_05602_amd as F
+    nb, t, n_if, n_chan, ws, pf, pt, kind, dmax = case
+    print(f"case: shifts {case}", flush=True)
+    rng = np.random.default_rng([66, nb, t, n_if, n_chan])
+    nf = n_if * n_chan
+    v = (rng.standard_normal((nb, t, n_if, n_chan)) +
+         1j * rng.standard_normal((nb, t, n_if, n_chan))).astype(np.complex64)
+    d = np.sort(rng.integers(0, dmax + 1, nf))[::-1].astype(np.int32)
+    fv = v.reshape(nb, t, nf)
+    # a dispersed fringe that the shifts bring back together
+    f = np.arange(nf)
+    for k in range(5):
+        rows = t // 3 + k + d
+        ok = rows < t
+        fv[0, rows[ok], f[ok]] += (0.9 * np.exp(2j * np.pi * 0.19 * f[ok])).astype(np.complex64)
+    g = None
+    if kind == "gains":
+        g = (rng.uniform(0.5, 1.5, (nb, nf)) * np.exp(2j * np.pi * rng.random((nb, nf)))).astype(np.complex64)
+    desc = dict(n_baselines=nb, n_ap=t, n_if=n_if, n_chan=n_chan, ap_seconds=1e-3, chan_width_hz=1e6)
+    buf, ptr = _padded(v)
+    flags = F.FRINGE_DELAY_ONLY if kind == "delay-only" else 0
+    plan, table, cands = _run([desc], [ptr], ws, pf, pt, 4.0, flags=flags, shifts=[d],
+                              gains=[g] if g is not None else None)
+    ref = oracle_table([v], [desc], ws, pf, pt, 4.0, delay_only=(kind == "delay-only"),
+                       gains=[g] if g is not None else None, shifts=[d])
+    xs = _shifted(fv * (g[:, None, :] if g is not None else 1), d)
+    n_amb = compare_windows(table, ref, lambda s, b: xs[b], pf, pt, str(case))
+    compare_candidates(cands, ref, 4.0, str(case))
+    assert n_amb <= max(2, len(ref) // 1000)
+    assert np.all(np.isfinite(table["amp"]))
+    plan.close()
+    del buf
+
+
+def test_dispersed_pulse_restored():
+    """A unit pulse reaching channel f at AP t0 + d_f: with the shifts the
+    one-AP window at t0 has amp = F and SNR = sqrt(F) at delay bin 0."""
+    print("case: dispersed pulse", flush=True)
+    nf, t, t0 = 256, 200, 17
+    d = (np.arange(nf)[::-1] * 150) // nf
+    v = np.zeros((1, t, nf), np.complex64)
+    v[0, t0 + d, np.arange(nf)] = 1.0
+    desc = dict(n_baselines=1, n_ap=t, n_if=8, n_chan=32, ap_seconds=1.0, chan_width_hz=1.0)
+    buf, ptr = _padded(v)
+    _, table, _ = _run([desc], [ptr], [1], 4, 2, 3.0, shifts=[d.astype(np.int32)])
+    r = table[table["t_start"] == t0][0]
+    assert (int(r["k_rate"]), int(r["k_delay"])) == (0, 0)
+    assert r["amp"] == pytest.approx(nf, rel=1e-6)
+    assert r["snr"] == pytest.approx(math.sqrt(nf), rel=1e-6)
+    assert np.all(table[table["t_start"] != t0]["amp"] == 0)
+
+
+def test_dm_trials_one_launch():
+    """Four DM trials of one EVN-like slice as four scans of one plan over the
+    same device cube: one fused launch, each scan equal to its own plan."""
+    import paper_2108_05602_amd as F
+    from paper_2108_05602_amd.dedisp import channel_freqs_hz, dm_shifts
+    print("case: DM trials", flush=True)
+    spec = synth.evn_scan(5201, 3, 1200, 8, 32, 1.024e-3, 16e6, 2, width_max=16, n_tones=1)
+    v = spec.full()
+    desc = spec.desc()
+    freqs = channel_freqs_hz(1.6e9, 8, 32, desc["chan_width_hz"])
+    trials = [dm_shifts(dm, freqs, desc["ap_seconds"]) for dm in (0.0, 40.0, 120.0, 300.0)]
+    assert trials[-1].max() > 50
+    ws = [1, 2, 4, 8, 16, 32]
+    buf, ptr = _padded(v)
+    plan, table, cands = _run([desc] * 4, [ptr] * 4, ws, 4, 2, 4.5, flags=F.FRINGE_PROFILE,
+                              shifts=trials)
+    prof = plan.profile()
+    assert prof["rate_launches"] == 1, prof
+    for s, d in enumerate(trials):
+        _, t1, _ = _run([desc], [ptr], ws, 4, 2, 4.5, shifts=[d])
+        sub = table[table["scan"] == s]
+        for k in ("baseline", "window_ap", "t_start", "k_rate", "k_delay", "amp", "snr", "energy"):
+            assert np.array_equal(sub[k], t1[k]), (s, k)
+    # DM 0 is the unshifted search
+    _, t0, _ = _run([desc], [ptr], ws, 4, 2, 4.5)
+    for k in ("k_delay", "amp", "snr"):
+        assert np.array_equal(table[table["scan"] == 0][k], t0[k]), k
+    plan.close()
+    del buf
+
+
+def test_shift_errors():
+    import torch
+
+    import paper_2108_05602_amd as F
+    print("case: shift errors", flush=True)
+    desc = dict(n_baselines=1, n_ap=100, n_if=2, n_chan=32, ap_seconds=1e-3, chan_width_hz=1e6)
+    d = torch.zeros(64, dtype=torch.int32, device="cuda")
+    with F.Plan([desc], [4], flags=F.FRINGE_STREAMING) as p:
+        with pytest.raises(F.FringeError) as e:
+            p.set_shifts(0, d.data_ptr())
+        assert e.value.code == -2
+        p.set_shifts(0, None)
+    with F.Plan([desc], [4]) as p:
+        with pytest.raises(F.FringeError) as e:
+            p.set_shifts(1, d.data_ptr())
+        assert e.value.code == -1
