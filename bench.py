@@ -166,6 +166,43 @@ def delay_only_leg(dev, spec, params, steps=5):
             "candidates": int(len(c))}
 
 
+def dm_search_leg(dev, spec, params, n_dm=20, dm_max=500.0, steps=2):
+    """A DM search of the same resident scan: n_dm trials (DM 0..dm_max,
+    channels from 1.6 GHz up) as n_dm scans of one plan over the one cube,
+    each with its dedispersion shifts; windows/s over all trials."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    from paper_2108_05602_amd.dedisp import channel_freqs_hz, dm_shifts
+    d = spec.desc()
+    freqs = channel_freqs_hz(1.6e9, d["n_if"], d["n_chan"], d["chan_width_hz"])
+    dms = np.linspace(0.0, dm_max, n_dm)
+    shifts = [torch.from_numpy(dm_shifts(dm, freqs, d["ap_seconds"])).cuda() for dm in dms]
+    st = torch.cuda.current_stream()
+    with F.Plan([d] * n_dm, params["window_aps"], pad_freq=params["pad_freq"],
+                pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],
+                max_candidates=1 << 22, flags=F.FRINGE_PROFILE) as plan:
+        for s_, sh in enumerate(shifts):
+            plan.set_shifts(s_, sh.data_ptr())
+        n_win = plan.info()["n_windows"]
+        ptrs = [dev.data_ptr()] * n_dm
+        plan.search(ptrs, st.cuda_stream)
+        plan.candidates()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kern = 0.0
+        for _ in range(steps):
+            plan.search(ptrs, st.cuda_stream)
+            c = plan.candidates(capacity=1 << 22)
+            kern += plan.profile()["rate_ms"]
+        dt = (time.perf_counter() - t0) / steps
+        launches = plan.profile()["rate_launches"]
+    return {"dm_trials": n_dm, "dm_max": dm_max, "max_shift_aps": int(shifts[-1].max()),
+            "windows": n_win, "windows_per_s": n_win / dt, "ms_per_step": dt * 1e3,
+            "ms_per_dm_trial": dt * 1e3 / n_dm, "fused_kernel_ms": kern / steps,
+            "fused_launches": launches, "candidates": int(len(c))}
+
+
 def graph_vs_eager(dev, spec, params, n_bl=15, n_ap=976, rounds=6, reps=50):
     """Per-search latency (search + candidates on the host) of a small batch
     plan launched eagerly and replayed from its HIP graph (FRINGE_GRAPH), on
@@ -423,6 +460,9 @@ def main():
     log("delay-only search of the same scan")
     out["delay_only"] = delay_only_leg(dev, spec, params)
     log("delay-only: " + json.dumps(out["delay_only"]))
+    log("DM search: 20 dedispersed trials of the same scan in one plan")
+    out["dm_search"] = dm_search_leg(dev, spec, params)
+    log("DM search: " + json.dumps(out["dm_search"]))
     log("small batch plan: eager launches vs graph replay")
     out["graph_vs_eager"] = graph_vs_eager(dev, spec, params)
     log("graph vs eager: " + json.dumps(out["graph_vs_eager"]))
