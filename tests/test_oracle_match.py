@@ -1,0 +1,183 @@
+"""Pins of the reference single-pulse matching and localization: hand-built
+candidate lists whose pulses follow from the criteria by inspection, and
+localization recovering a known offset exactly and singling out a corrupted
+baseline.  Planted mistakes in the reference must fail one of the checks."""
+
+import types
+
+import numpy as np
+import pytest
+
+import oracle.pulse_match_oracle as pm
+from oracle.fringe_oracle import TABLE_DTYPE
+
+
+def _c(rows):
+    out = np.zeros(len(rows), TABLE_DTYPE)
+    for i, (scan, b, w, t, snr) in enumerate(rows):
+        out[i]["scan"], out[i]["baseline"], out[i]["window_ap"], out[i]["t_start"] = scan, b, w, t
+        # amp falls as SNR rises, so a representative chosen by amp is caught
+        out[i]["snr"], out[i]["amp"] = snr, 100.0 - snr
+        out[i]["k_delay"], out[i]["delay_s"] = b + 1, 1e-9 * (b + 1)
+    return out
+
+
+def check_baseline_pulses(mod):
+    rows = [
+        (0, 0, 2, 10, 5.0), (0, 0, 4, 9, 6.0),                      # two lengths overlap: pulse
+        (0, 0, 2, 40, 7.0), (0, 0, 2, 41, 8.0),                     # one length only: none
+        (0, 0, 2, 60, 5.0), (0, 0, 8, 61, 5.0), (0, 0, 2, 68, 9.0), # chain 60-62 ~ 61-69 ~ 68-70
+        (0, 1, 2, 10, 5.0), (0, 1, 4, 12, 5.0),                     # touching, no shared AP: none
+    ]
+    ps = mod.baseline_pulses(_c(rows), min_windows=2)
+    got = [(p["baseline"], p["t_lo"], p["t_hi"], p["n_windows"], p["n_lengths"],
+            int(p["rep"]["t_start"])) for p in ps]
+    assert got == [(0, 9, 13, 2, 2, 9), (0, 60, 70, 3, 2, 68)]
+    # SNR ties: the shorter window, then the earlier start
+    ps = mod.baseline_pulses(_c([(0, 3, 4, 20, 5.0), (0, 3, 2, 21, 5.0), (0, 3, 2, 23, 5.0)]))
+    assert [(int(p["rep"]["window_ap"]), int(p["rep"]["t_start"])) for p in ps] == [(2, 21)]
+
+
+def check_single_pulses(mod):
+    # baseline pulses on 6 baselines around AP 100; baseline 5's is apart (AP 300)
+    rows = []
+    for b in range(6):
+        t = 100 + b if b < 5 else 300
+        rows += [(0, b, 2, t, 5.0 + b), (0, b, 4, t - 1, 4.0)]
+    sp = mod.single_pulses(_c(rows), min_windows=2, min_baselines=5)
+    assert [r["baseline"] for r in sp] == [0, 1, 2, 3, 4]
+    assert {r["pulse"] for r in sp} == {0}
+    assert all(r["window_ap"] == 2 and r["t_start"] == 100 + r["baseline"] for r in sp)
+    assert [(r["t_lo"], r["t_hi"]) for r in sp] == [(99 + b, 103 + b) for b in range(5)]
+    assert mod.single_pulses(_c(rows), min_windows=2, min_baselines=6) == []
+    # a second scan is matched on its own, and numbered after the first
+    rows2 = rows + [(1, b, 2, 100, 5.0) for b in range(5)] + [(1, b, 8, 98, 5.0) for b in range(5)]
+    sp2 = mod.single_pulses(_c(rows2), min_windows=2, min_baselines=5)
+    assert [(r["scan"], r["pulse"]) for r in sp2] == [(0, 0)] * 5 + [(1, 1)] * 5
+    # four baselines, one of them with two pulses in the group: four distinct
+    # baselines, so no single pulse at five; at four, baseline 0 is represented
+    # by its higher-SNR pulse
+    rows3 = [(0, 0, 2, 50, 6.0), (0, 0, 4, 49, 1.0), (0, 0, 2, 55, 9.0), (0, 0, 4, 54, 1.0)]
+    for b in (1, 2, 3):
+        rows3 += [(0, b, 8, 48, 5.0), (0, b, 4, 52, 5.0)]
+    assert mod.single_pulses(_c(rows3), min_windows=2, min_baselines=5) == []
+    sp3 = mod.single_pulses(_c(rows3), min_windows=2, min_baselines=4)
+    assert [r["baseline"] for r in sp3] == [0, 1, 2, 3]
+    assert (sp3[0]["t_start"], sp3[0]["snr"]) == (55, 9.0)
+
+
+def check_localize(mod):
+    rng = np.random.default_rng(3)
+    n = 7
+    a = rng.normal(0, 1e-4, n)     # s/rad partials
+    d = rng.normal(0, 1e-4, n)
+    truth = np.array([2.5e-6, -1.2e-6])
+    tau = a * truth[0] + d * truth[1]
+    sol, rms, loo, loo_rms = mod.localize(tau, a, d)
+    assert np.allclose(sol, truth, rtol=1e-9, atol=0) and rms < 1e-20
+    assert loo.shape == (n, 2) and np.allclose(loo, truth, rtol=1e-9, atol=0)
+    assert np.all(loo_rms < 1e-20)
+    # a corrupted baseline: only the fit without it is exact again
+    bad = tau.copy()
+    bad[4] += 3e-10
+    sol, rms, loo, loo_rms = mod.localize(bad, a, d)
+    assert int(np.argmin(loo_rms)) == 4 and loo_rms[4] < 1e-20
+    assert np.all(np.delete(loo_rms, 4) > 1e-12) and rms > 1e-12
+    assert np.allclose(loo[4], truth, rtol=1e-9, atol=0)
+    assert not np.allclose(sol, truth, rtol=1e-3, atol=0)
+    # two baselines: a 2x2 solve, no leave-one-out
+    sol, rms, loo, loo_rms = mod.localize(tau[:2], a[:2], d[:2])
+    assert np.allclose(sol, truth, rtol=1e-9, atol=0) and loo.shape == (0, 2) and len(loo_rms) == 0
+
+
+ALL_CHECKS = [check_baseline_pulses, check_single_pulses, check_localize]
+
+
+@pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda c: c.__name__)
+def test_reference_matching(check):
+    check(pm)
+
+
+# ------------------------------------------------------ planted mistakes ---
+
+def _mutant(**overrides):
+    m = types.ModuleType("mutant_match")
+    m.__dict__.update({k: getattr(pm, k) for k in dir(pm) if not k.startswith("__")})
+    m.__dict__.update(overrides)
+    for name in ("baseline_pulses", "single_pulses", "localize", "_components", "_best"):
+        if name in overrides:
+            continue
+        f = getattr(pm, name)
+        setattr(m, name, types.FunctionType(f.__code__, m.__dict__, name, f.__defaults__,
+                                            f.__closure__))
+    return m
+
+
+def _fails(mod):
+    for c in ALL_CHECKS:
+        try:
+            c(mod)
+        except AssertionError:
+            return True
+    return False
+
+
+def _touching_links(s1, e1, s2, e2):
+    return s1 <= e2 and s2 <= e1
+
+
+def _best_by_amp(rows, idx):
+    return max(idx, key=lambda k: (float(rows[k]["amp"]), -int(rows[k]["window_ap"]),
+                                   -int(rows[k]["t_start"])))
+
+
+def _best_latest(rows, idx):
+    return max(idx, key=lambda k: (float(rows[k]["snr"]), int(rows[k]["window_ap"]),
+                                   int(rows[k]["t_start"])))
+
+
+def _count_windows(cands, min_windows=2):
+    # windows counted instead of distinct window lengths
+    out = pm.baseline_pulses(cands, 1)
+    return [p for p in out if p["n_windows"] >= min_windows]
+
+
+def _count_pulses(cands, min_windows=2, min_baselines=5):
+    # baseline pulses counted instead of distinct baselines
+    bps = pm.baseline_pulses(cands, min_windows)
+    rows = pm.single_pulses(cands, min_windows, 1)
+    keep = []
+    for pid in sorted({r["pulse"] for r in rows}):
+        grp = [r for r in rows if r["pulse"] == pid]
+        n = sum(1 for p in bps if p["scan"] == grp[0]["scan"] and
+                any(p["t_lo"] < r["t_hi"] and r["t_lo"] < p["t_hi"] for r in grp))
+        if n >= min_baselines:
+            keep += grp
+    return keep
+
+
+def _loo_keeps_all(tau, dtau_dra, dtau_ddec):
+    sol, rms, loo, loo_rms = pm.localize(tau, dtau_dra, dtau_ddec)
+    return sol, rms, np.tile(sol, (len(loo), 1)), np.full(len(loo_rms), rms)
+
+
+def _localize_swapped(tau, dtau_dra, dtau_ddec):
+    return pm.localize(tau, dtau_ddec, dtau_dra)
+
+
+@pytest.mark.parametrize("overrides", [
+    dict(_spans_share_ap=_touching_links),
+    dict(_best=_best_by_amp),
+    dict(_best=_best_latest),
+    dict(baseline_pulses=_count_windows),
+    dict(single_pulses=_count_pulses),
+    dict(localize=_loo_keeps_all),
+    dict(localize=_localize_swapped),
+], ids=["touching-spans", "rep-by-amp", "rep-tie-latest", "count-windows", "count-pulses",
+        "loo-keeps-all", "partials-swapped"])
+def test_planted_mistake_is_caught(overrides):
+    assert _fails(_mutant(**overrides))
+
+
+def test_unmutated_reference_passes_all_checks():
+    assert not _fails(pm)
