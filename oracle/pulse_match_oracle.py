@@ -102,7 +102,7 @@ def single_pulses(cands, min_windows=2, min_baselines=5):
         by_b = {}
         for p in members:
             q = by_b.get(p["baseline"])
-            if q is None or float(p["rep"]["snr"]) > float(q["rep"]["snr"]):
+            if q is None or (float(p["rep"]["snr"]), -p["t_lo"]) > (float(q["rep"]["snr"]), -q["t_lo"]):
                 by_b[p["baseline"]] = p
         for b in sorted(by_b):
             p = by_b[b]
@@ -138,3 +138,18 @@ def localize(tau, dtau_dra, dtau_ddec):
             loo.append(x)
             loo_rms.append(r)
     return sol, rms, np.array(loo).reshape(-1, 2), np.array(loo_rms)
+
+
+C_LIGHT = 299792458.0
+
+
+def delay_partials(b_xyz, gast, ra, dec):
+    """(dtau/dra, dtau/ddec) in s/rad for each Earth-fixed baseline vector
+    b_xyz[i] = r_2 - r_1 (metres).  The source direction in the Earth-fixed
+    frame is s = (cos dec cos h, -cos dec sin h, sin dec) with h = gast - ra,
+    and tau_g = -(b . s) / c; the partials differentiate s."""
+    b = np.asarray(b_xyz, float).reshape(-1, 3)
+    h = gast - ra
+    ds_dra = np.array([np.cos(dec) * np.sin(h), np.cos(dec) * np.cos(h), 0.0])
+    ds_ddec = np.array([-np.sin(dec) * np.cos(h), np.sin(dec) * np.sin(h), np.cos(dec)])
+    return -(b @ ds_dra) / C_LIGHT, -(b @ ds_ddec) / C_LIGHT

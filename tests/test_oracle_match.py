@@ -64,6 +64,11 @@ def check_single_pulses(mod):
     sp3 = mod.single_pulses(_c(rows3), min_windows=2, min_baselines=4)
     assert [r["baseline"] for r in sp3] == [0, 1, 2, 3]
     assert (sp3[0]["t_start"], sp3[0]["snr"]) == (55, 9.0)
+    # equal SNR: the earlier of the two pulses (its span starts first)
+    rows4 = [(0, 0, 2, 55, 6.0)] + rows3[1:2] + [(0, 0, 2, 50, 6.0)] + rows3[3:]
+    rows4 = rows4[2:] + rows4[:2]          # input order must not matter
+    sp4 = mod.single_pulses(_c(rows4), min_windows=2, min_baselines=4)
+    assert (sp4[0]["t_start"], sp4[0]["t_lo"]) == (50, 49)
 
 
 def check_localize(mod):
@@ -90,7 +95,56 @@ def check_localize(mod):
     assert np.allclose(sol, truth, rtol=1e-9, atol=0) and loo.shape == (0, 2) and len(loo_rms) == 0
 
 
-ALL_CHECKS = [check_baseline_pulses, check_single_pulses, check_localize]
+
+
+# ------------------------------------------------------ delay partials ---
+
+def _tau_by_rotation(b, gast, ra, dec):
+    # the source's celestial unit vector turned into the Earth-fixed frame by
+    # a rotation of -gast about the pole; tau_g = -(b . s) / c
+    s_cel = np.array([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)])
+    c, s = np.cos(gast), np.sin(gast)
+    rot = np.array([[c, s, 0.0], [-s, c, 0.0], [0.0, 0.0, 1.0]])
+    return -(np.asarray(b, float) @ (rot @ s_cel)) / pm.C_LIGHT
+
+
+def check_delay_partials(mod):
+    rng = np.random.default_rng(11)
+    b = rng.normal(0, 3e6, (9, 3))
+    for gast, ra, dec in [(1.1, 0.9, 0.3), (4.0, 5.5, -1.2), (0.2, 3.0, 1.5)]:
+        da, dd = mod.delay_partials(b, gast, ra, dec)
+        h = 1e-6
+        fa = (_tau_by_rotation(b, gast, ra + h, dec) - _tau_by_rotation(b, gast, ra - h, dec)) / (2 * h)
+        fd = (_tau_by_rotation(b, gast, ra, dec + h) - _tau_by_rotation(b, gast, ra, dec - h)) / (2 * h)
+        scale = np.linalg.norm(b, axis=1) / pm.C_LIGHT
+        assert np.all(np.abs(da - fa) < 1e-7 * scale) and np.all(np.abs(dd - fd) < 1e-7 * scale)
+    # at the pole the delay does not depend on ra; a polar baseline sees no ra term
+    da, dd = mod.delay_partials(b, 0.7, 1.3, np.pi / 2)
+    assert np.all(np.abs(da) < 1e-16 * np.linalg.norm(b, axis=1))
+    da, _ = mod.delay_partials([[0.0, 0.0, 6e6]], 0.7, 1.3, 0.4)
+    assert da[0] == 0.0
+    # reversing a baseline reverses its partials
+    da1, dd1 = mod.delay_partials(b, 2.0, 1.0, 0.5)
+    da2, dd2 = mod.delay_partials(-b, 2.0, 1.0, 0.5)
+    assert np.array_equal(da1, -da2) and np.array_equal(dd1, -dd2)
+
+
+def check_localize_geometric(mod):
+    # an offset source: the delay residuals against the a priori position,
+    # fitted with the partials, recover the offset to first order
+    rng = np.random.default_rng(5)
+    st = rng.normal(0, 3e6, (6, 3))
+    b = np.array([st[j] - st[i] for i in range(6) for j in range(i + 1, 6)])
+    gast, ra0, dec0 = 1.7, 0.8, 0.6
+    off = np.array([2e-7, -3e-7])          # rad (~0.04", -0.06")
+    tau = _tau_by_rotation(b, gast, ra0 + off[0], dec0 + off[1]) - _tau_by_rotation(b, gast, ra0, dec0)
+    da, dd = mod.delay_partials(b, gast, ra0, dec0)
+    sol, rms, _, _ = mod.localize(tau, da, dd)
+    assert np.allclose(sol, off, rtol=1e-5, atol=0)
+
+
+ALL_CHECKS = [check_baseline_pulses, check_single_pulses, check_localize, check_delay_partials,
+              check_localize_geometric]
 
 
 @pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda c: c.__name__)
@@ -104,7 +158,8 @@ def _mutant(**overrides):
     m = types.ModuleType("mutant_match")
     m.__dict__.update({k: getattr(pm, k) for k in dir(pm) if not k.startswith("__")})
     m.__dict__.update(overrides)
-    for name in ("baseline_pulses", "single_pulses", "localize", "_components", "_best"):
+    for name in ("baseline_pulses", "single_pulses", "localize", "_components", "_best",
+                 "delay_partials"):
         if name in overrides:
             continue
         f = getattr(pm, name)
@@ -181,3 +236,22 @@ def test_planted_mistake_is_caught(overrides):
 
 def test_unmutated_reference_passes_all_checks():
     assert not _fails(pm)
+
+
+
+
+def _partials_hour_angle_flipped(b_xyz, gast, ra, dec):
+    return pm.delay_partials(b_xyz, -gast, -ra, dec)
+
+
+def _partials_no_sign(b_xyz, gast, ra, dec):
+    da, dd = pm.delay_partials(b_xyz, gast, ra, dec)
+    return -da, -dd
+
+
+@pytest.mark.parametrize("overrides", [
+    dict(delay_partials=_partials_hour_angle_flipped),
+    dict(delay_partials=_partials_no_sign),
+], ids=["hour-angle-flipped", "partials-sign"])
+def test_planted_partials_mistake_is_caught(overrides):
+    assert _fails(_mutant(**overrides))
