@@ -5,27 +5,37 @@ the test suite does.  Brute force by design (every pair of windows compared,
 connected components by breadth-first search, least squares by numpy), so
 that it can be checked against the paper by eye.
 
-What is computed (paper, section "Detection rate" criteria and section
-"Localization", Eq. (2) with the leave-one-baseline-out check):
+What is computed (paper, section "Performance improvement", the selection
+criteria of the fringe search, and section "Localization", Eq. (2) with the
+leave-one-baseline-out check).  The criteria name no grouping rule; groups
+here are anchored at their strongest member, so that a long-lived RFI
+signal cannot chain distinct pulses into one:
 
-  baseline pulses: on one baseline of one scan, candidate windows whose AP
-    spans [t_start, t_start + W) share an AP are linked, transitively; a
-    linked group is a pulse of that baseline when its windows come from at
-    least `min_windows` distinct window lengths.  Its span is the union of
-    the spans; its representative is the window of highest SNR (ties: the
-    shorter window, then the earlier start).
-  single pulses: baseline pulses of one scan whose spans share an AP are
-    linked, transitively; a group is a single pulse when it holds at least
-    `min_baselines` distinct baselines.  A baseline with several pulses in
-    the group is represented by its highest-SNR one.
+  baseline pulses: on one baseline of one scan, repeatedly take the
+    strongest remaining candidate window (highest SNR; ties: the shorter
+    window, then the earlier start) and every remaining window whose AP
+    span [t_start, t_start + W) shares an AP with it; remove them.  The
+    group is a pulse of that baseline when its windows come from at least
+    `min_windows` distinct window lengths.  Its span is the union of its
+    windows' spans, its representative the anchor window.
+  single pulses: among the baseline pulses of one scan, repeatedly take the
+    strongest remaining one (by its representative: SNR, then the shorter
+    window, the earlier start, the lower baseline) and every remaining one
+    whose span shares an AP with its span; remove them.  The group is a
+    single pulse when it holds at least `min_baselines` distinct baselines;
+    a baseline with several pulses in it is represented by its strongest.
+    Single pulses are numbered from 0 over all scans in (scan, first AP of
+    the group, order found) order, rows within a pulse by baseline.
   localization: over a pulse's baselines, least squares for (dra, ddec) in
     tau_b - tau_cal_b = (dtau/dra)_b dra + (dtau/ddec)_b ddec, and the same
     solve leaving out each baseline in turn.
+  partials: of the geometric delay tau_g = t_2 - t_1 = -(b . s) / c of a
+    baseline b = r_2 - r_1 (Earth-fixed metres) toward a source at (ra, dec)
+    whose Greenwich hour angle is gast - ra (no precession, nutation, polar
+    motion or aberration: the a priori geometry of a small offset solve).
 """
 
 from __future__ import annotations
-
-from collections import deque
 
 import numpy as np
 
@@ -37,29 +47,23 @@ def _spans_share_ap(s1, e1, s2, e2):
     return s1 < e2 and s2 < e1
 
 
-def _components(n, linked):
-    """Connected components of the graph on 0..n-1 with edges linked(i, j)."""
-    seen = [False] * n
-    comps = []
-    for i in range(n):
-        if seen[i]:
-            continue
-        seen[i] = True
-        comp, q = [], deque([i])
-        while q:
-            k = q.popleft()
-            comp.append(k)
-            for j in range(n):
-                if not seen[j] and linked(k, j):
-                    seen[j] = True
-                    q.append(j)
-        comps.append(sorted(comp))
-    return comps
+def _window_strength(r):
+    return (float(r["snr"]), -int(r["window_ap"]), -int(r["t_start"]))
 
 
-def _best(rows, idx):
-    return max(idx, key=lambda k: (float(rows[k]["snr"]), -int(rows[k]["window_ap"]),
-                                   -int(rows[k]["t_start"])))
+def _anchored_groups(items, strength, span):
+    """Groups of `items`: repeatedly the strongest remaining item and every
+    remaining item whose span shares an AP with the anchor's; returns
+    (anchor, members) pairs in the order found."""
+    left = list(range(len(items)))
+    groups = []
+    while left:
+        anchor = max(left, key=lambda k: strength(items[k]))
+        s0, e0 = span(items[anchor])
+        members = [k for k in left if _spans_share_ap(*span(items[k]), s0, e0)]
+        left = [k for k in left if k not in members]
+        groups.append((anchor, members))
+    return groups
 
 
 def baseline_pulses(cands, min_windows=2):
@@ -69,43 +73,39 @@ def baseline_pulses(cands, min_windows=2):
     keys = sorted({(int(c["scan"]), int(c["baseline"])) for c in cands})
     for scan, b in keys:
         rows = cands[(cands["scan"] == scan) & (cands["baseline"] == b)]
-        st = [int(r["t_start"]) for r in rows]
-        en = [int(r["t_start"]) + int(r["window_ap"]) for r in rows]
-        comps = _components(len(rows), lambda i, j: _spans_share_ap(st[i], en[i], st[j], en[j]))
-        for comp in comps:
-            lengths = {int(rows[k]["window_ap"]) for k in comp}
+        span = lambda r: (int(r["t_start"]), int(r["t_start"]) + int(r["window_ap"]))
+        for anchor, members in _anchored_groups(rows, _window_strength, span):
+            lengths = {int(rows[k]["window_ap"]) for k in members}
             if len(lengths) < min_windows:
                 continue
-            out.append(dict(scan=scan, baseline=b, t_lo=min(st[k] for k in comp),
-                            t_hi=max(en[k] for k in comp), n_windows=len(comp),
-                            n_lengths=len(lengths), rep=rows[_best(rows, comp)]))
+            out.append(dict(scan=scan, baseline=b, t_lo=min(span(rows[k])[0] for k in members),
+                            t_hi=max(span(rows[k])[1] for k in members),
+                            n_windows=len(members), n_lengths=len(lengths), rep=rows[anchor]))
     return out
+
+
+def _pulse_strength(p):
+    return _window_strength(p["rep"]) + (-p["baseline"],)
 
 
 def single_pulses(cands, min_windows=2, min_baselines=5):
     """Rows (one per single pulse and baseline) as a list of dicts with the
-    PULSE_FIELDS, in (scan, pulse start, baseline) order; pulses numbered
-    from 0 in that order over all scans."""
+    PULSE_FIELDS, in (pulse, baseline) order."""
     bps = baseline_pulses(cands, min_windows)
-    rows = []
-    groups = []
+    found = []
     for scan in sorted({p["scan"] for p in bps}):
         ps = [p for p in bps if p["scan"] == scan]
-        comps = _components(len(ps), lambda i, j: _spans_share_ap(ps[i]["t_lo"], ps[i]["t_hi"],
-                                                                  ps[j]["t_lo"], ps[j]["t_hi"]))
-        for comp in comps:
-            if len({ps[k]["baseline"] for k in comp}) < min_baselines:
+        groups = _anchored_groups(ps, _pulse_strength, lambda p: (p["t_lo"], p["t_hi"]))
+        for order, (_, members) in enumerate(groups):
+            if len({ps[k]["baseline"] for k in members}) < min_baselines:
                 continue
-            groups.append((scan, min(ps[k]["t_lo"] for k in comp), [ps[k] for k in comp]))
-    groups.sort(key=lambda g: (g[0], g[1]))
-    for pid, (scan, _, members) in enumerate(groups):
-        by_b = {}
-        for p in members:
-            q = by_b.get(p["baseline"])
-            if q is None or (float(p["rep"]["snr"]), -p["t_lo"]) > (float(q["rep"]["snr"]), -q["t_lo"]):
-                by_b[p["baseline"]] = p
-        for b in sorted(by_b):
-            p = by_b[b]
+            found.append((scan, min(ps[k]["t_lo"] for k in members), order,
+                          [ps[k] for k in members]))
+    found.sort(key=lambda g: g[:3])
+    rows = []
+    for pid, (scan, _, _, members) in enumerate(found):
+        for b in sorted({p["baseline"] for p in members}):
+            p = max((q for q in members if q["baseline"] == b), key=_pulse_strength)
             r = p["rep"]
             rows.append(dict(scan=scan, pulse=pid, baseline=b, window_ap=int(r["window_ap"]),
                              t_start=int(r["t_start"]), k_rate=int(r["k_rate"]),

@@ -26,49 +26,60 @@ def check_baseline_pulses(mod):
     rows = [
         (0, 0, 2, 10, 5.0), (0, 0, 4, 9, 6.0),                      # two lengths overlap: pulse
         (0, 0, 2, 40, 7.0), (0, 0, 2, 41, 8.0),                     # one length only: none
-        (0, 0, 2, 60, 5.0), (0, 0, 8, 61, 5.0), (0, 0, 2, 68, 9.0), # chain 60-62 ~ 61-69 ~ 68-70
+        (0, 0, 2, 60, 5.0), (0, 0, 8, 61, 5.0), (0, 0, 2, 68, 9.0), # 60-62 does not touch the
+                                                                    # anchor 68-70: left alone
         (0, 1, 2, 10, 5.0), (0, 1, 4, 12, 5.0),                     # touching, no shared AP: none
     ]
-    ps = mod.baseline_pulses(_c(rows), min_windows=2)
+    ps = sorted(mod.baseline_pulses(_c(rows), min_windows=2), key=lambda p: (p["baseline"], p["t_lo"]))
     got = [(p["baseline"], p["t_lo"], p["t_hi"], p["n_windows"], p["n_lengths"],
             int(p["rep"]["t_start"])) for p in ps]
-    assert got == [(0, 9, 13, 2, 2, 9), (0, 60, 70, 3, 2, 68)]
-    # SNR ties: the shorter window, then the earlier start
+    assert got == [(0, 9, 13, 2, 2, 9), (0, 61, 70, 2, 2, 68)]
+    # SNR ties: the shorter window, then the earlier start, anchors the group
     ps = mod.baseline_pulses(_c([(0, 3, 4, 20, 5.0), (0, 3, 2, 21, 5.0), (0, 3, 2, 23, 5.0)]))
-    assert [(int(p["rep"]["window_ap"]), int(p["rep"]["t_start"])) for p in ps] == [(2, 21)]
+    assert [(int(p["rep"]["window_ap"]), int(p["rep"]["t_start"]), p["n_windows"]) for p in ps] \
+        == [(2, 21, 2)]
 
 
 def check_single_pulses(mod):
     # baseline pulses on 6 baselines around AP 100; baseline 5's is apart (AP 300)
     rows = []
     for b in range(6):
-        t = 100 + b if b < 5 else 300
+        t = 100 + b // 2 if b < 5 else 300
         rows += [(0, b, 2, t, 5.0 + b), (0, b, 4, t - 1, 4.0)]
     sp = mod.single_pulses(_c(rows), min_windows=2, min_baselines=5)
     assert [r["baseline"] for r in sp] == [0, 1, 2, 3, 4]
     assert {r["pulse"] for r in sp} == {0}
-    assert all(r["window_ap"] == 2 and r["t_start"] == 100 + r["baseline"] for r in sp)
-    assert [(r["t_lo"], r["t_hi"]) for r in sp] == [(99 + b, 103 + b) for b in range(5)]
+    assert all(r["window_ap"] == 2 and r["t_start"] == 100 + r["baseline"] // 2 for r in sp)
+    assert [(r["t_lo"], r["t_hi"]) for r in sp] == [(99 + b // 2, 103 + b // 2) for b in range(5)]
     assert mod.single_pulses(_c(rows), min_windows=2, min_baselines=6) == []
     # a second scan is matched on its own, and numbered after the first
     rows2 = rows + [(1, b, 2, 100, 5.0) for b in range(5)] + [(1, b, 8, 98, 5.0) for b in range(5)]
     sp2 = mod.single_pulses(_c(rows2), min_windows=2, min_baselines=5)
     assert [(r["scan"], r["pulse"]) for r in sp2] == [(0, 0)] * 5 + [(1, 1)] * 5
-    # four baselines, one of them with two pulses in the group: four distinct
-    # baselines, so no single pulse at five; at four, baseline 0 is represented
-    # by its higher-SNR pulse
-    rows3 = [(0, 0, 2, 50, 6.0), (0, 0, 4, 49, 1.0), (0, 0, 2, 55, 9.0), (0, 0, 4, 54, 1.0)]
-    for b in (1, 2, 3):
+    # a group of five baseline pulses on four baselines (baseline 0 has two,
+    # both touching the anchor on baseline 1): no single pulse at five; at
+    # four, baseline 0 is represented by its stronger pulse
+    rows3 = [(0, 1, 16, 40, 9.0), (0, 1, 8, 44, 3.0),
+             (0, 0, 2, 42, 6.0), (0, 0, 4, 41, 1.0), (0, 0, 2, 50, 7.0), (0, 0, 4, 49, 1.0)]
+    for b in (2, 3):
         rows3 += [(0, b, 8, 48, 5.0), (0, b, 4, 52, 5.0)]
     assert mod.single_pulses(_c(rows3), min_windows=2, min_baselines=5) == []
     sp3 = mod.single_pulses(_c(rows3), min_windows=2, min_baselines=4)
     assert [r["baseline"] for r in sp3] == [0, 1, 2, 3]
-    assert (sp3[0]["t_start"], sp3[0]["snr"]) == (55, 9.0)
-    # equal SNR: the earlier of the two pulses (its span starts first)
-    rows4 = [(0, 0, 2, 55, 6.0)] + rows3[1:2] + [(0, 0, 2, 50, 6.0)] + rows3[3:]
-    rows4 = rows4[2:] + rows4[:2]          # input order must not matter
+    assert (sp3[0]["t_start"], sp3[0]["snr"], sp3[0]["t_lo"]) == (50, 7.0, 49)
+    assert (sp3[1]["t_lo"], sp3[1]["t_hi"], sp3[2]["t_start"]) == (40, 56, 52)
+    # equal SNR and window: the earlier start; input order does not matter
+    rows4 = rows3[:4] + [(0, 0, 2, 50, 6.0)] + rows3[5:]
+    rows4 = rows4[3:] + rows4[:3]
     sp4 = mod.single_pulses(_c(rows4), min_windows=2, min_baselines=4)
-    assert (sp4[0]["t_start"], sp4[0]["t_lo"]) == (50, 49)
+    assert (sp4[0]["t_start"], sp4[0]["t_lo"]) == (42, 41)
+    # a long-lived signal on one baseline does not chain two pulses together
+    rows5 = [(0, 9, 32, t, 4.6) for t in range(0, 400, 16)] + \
+            [(0, 9, 16, t, 4.6) for t in range(0, 400, 8)]
+    for b in range(5):
+        rows5 += [(0, b, 2, 100, 8.0), (0, b, 4, 99, 6.0), (0, b, 2, 300, 8.0), (0, b, 4, 299, 6.0)]
+    sp5 = mod.single_pulses(_c(rows5), min_windows=2, min_baselines=5)
+    assert sorted({(r["pulse"], r["t_lo"]) for r in sp5 if r["baseline"] == 0}) == [(0, 99), (1, 299)]
 
 
 def check_localize(mod):
@@ -158,8 +169,8 @@ def _mutant(**overrides):
     m = types.ModuleType("mutant_match")
     m.__dict__.update({k: getattr(pm, k) for k in dir(pm) if not k.startswith("__")})
     m.__dict__.update(overrides)
-    for name in ("baseline_pulses", "single_pulses", "localize", "_components", "_best",
-                 "delay_partials"):
+    for name in ("baseline_pulses", "single_pulses", "localize", "_anchored_groups",
+                 "_window_strength", "_pulse_strength", "delay_partials"):
         if name in overrides:
             continue
         f = getattr(pm, name)
@@ -181,14 +192,12 @@ def _touching_links(s1, e1, s2, e2):
     return s1 <= e2 and s2 <= e1
 
 
-def _best_by_amp(rows, idx):
-    return max(idx, key=lambda k: (float(rows[k]["amp"]), -int(rows[k]["window_ap"]),
-                                   -int(rows[k]["t_start"])))
+def _strength_by_amp(r):
+    return (float(r["amp"]), -int(r["window_ap"]), -int(r["t_start"]))
 
 
-def _best_latest(rows, idx):
-    return max(idx, key=lambda k: (float(rows[k]["snr"]), int(rows[k]["window_ap"]),
-                                   int(rows[k]["t_start"])))
+def _strength_latest(r):
+    return (float(r["snr"]), int(r["window_ap"]), int(r["t_start"]))
 
 
 def _count_windows(cands, min_windows=2):
@@ -204,11 +213,31 @@ def _count_pulses(cands, min_windows=2, min_baselines=5):
     keep = []
     for pid in sorted({r["pulse"] for r in rows}):
         grp = [r for r in rows if r["pulse"] == pid]
-        n = sum(1 for p in bps if p["scan"] == grp[0]["scan"] and
-                any(p["t_lo"] < r["t_hi"] and r["t_lo"] < p["t_hi"] for r in grp))
+        anchor = max(grp, key=lambda r: (r["snr"], -r["window_ap"], -r["t_start"], -r["baseline"]))
+        n = sum(1 for p in bps if p["scan"] == anchor["scan"] and
+                p["t_lo"] < anchor["t_hi"] and anchor["t_lo"] < p["t_hi"])
         if n >= min_baselines:
             keep += grp
     return keep
+
+
+def _transitive_groups(items, strength, span):
+    # connected components of the overlap graph instead of anchored groups
+    n = len(items)
+    seen, groups = [False] * n, []
+    for i in range(n):
+        if seen[i]:
+            continue
+        seen[i], comp, stack = True, [i], [i]
+        while stack:
+            k = stack.pop()
+            for j in range(n):
+                if not seen[j] and pm._spans_share_ap(*span(items[k]), *span(items[j])):
+                    seen[j] = True
+                    comp.append(j)
+                    stack.append(j)
+        groups.append((max(comp, key=lambda k: strength(items[k])), comp))
+    return groups
 
 
 def _loo_keeps_all(tau, dtau_dra, dtau_ddec):
@@ -222,14 +251,15 @@ def _localize_swapped(tau, dtau_dra, dtau_ddec):
 
 @pytest.mark.parametrize("overrides", [
     dict(_spans_share_ap=_touching_links),
-    dict(_best=_best_by_amp),
-    dict(_best=_best_latest),
+    dict(_window_strength=_strength_by_amp),
+    dict(_window_strength=_strength_latest),
+    dict(_anchored_groups=_transitive_groups),
     dict(baseline_pulses=_count_windows),
     dict(single_pulses=_count_pulses),
     dict(localize=_loo_keeps_all),
     dict(localize=_localize_swapped),
-], ids=["touching-spans", "rep-by-amp", "rep-tie-latest", "count-windows", "count-pulses",
-        "loo-keeps-all", "partials-swapped"])
+], ids=["touching-spans", "rep-by-amp", "rep-tie-latest", "transitive-groups", "count-windows",
+        "count-pulses", "loo-keeps-all", "partials-swapped"])
 def test_planted_mistake_is_caught(overrides):
     assert _fails(_mutant(**overrides))
 
