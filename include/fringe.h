@@ -20,10 +20,12 @@
  * SNR = amp / sqrt(E) (0 when E = 0) are taken per window, and a window is a
  * candidate when SNR > snr_threshold (section "Detection rate": windows whose
  * normalised power exceeds a threshold).  Windows of length W start every
- * max(1, W/2) APs; a tail shorter than W is dropped.  Cross-window and
- * cross-baseline matching and localization are not part of this library.
+ * max(1, W/2) APs; a tail shorter than W is dropped.
  *
- * Every computation runs in HIP kernels on the GPU; there is no CPU path.
+ * Every step of the search runs in HIP kernels on the GPU; there is no CPU
+ * path.  The consumers of the candidate list (cross-window and
+ * cross-baseline matching, localization) are host code, declared in
+ * fringe_match.h.
  *
  * Conventions for every entry point:
  *   - returns 0 (FRINGE_OK) or a negative FRINGE_E_* code; never aborts or

@@ -1,7 +1,9 @@
-"""ctypes binding of libfringe (include/fringe.h): argument marshalling only.
+"""ctypes binding of libfringe (include/fringe.h, include/fringe_match.h):
+argument marshalling only.
 
 Every function here has the name of the C entry point it calls and does no
-computation of its own; all search work runs in the library's HIP kernels.
+computation of its own; all search work runs in the library's HIP kernels,
+the matching and localization of candidates in its host code.
 Device buffers are passed as integer addresses (e.g. torch.Tensor.data_ptr())
 and streams as integer hipStream_t handles (torch.cuda.Stream.cuda_stream).
 The library must have been built (python -m paper_2108_05602_amd.build);
@@ -41,6 +43,7 @@ ENTRY_POINTS = (
     "fringe_windows_get", "fringe_window_id", "fringe_grid_get", "fringe_profile_get",
     "fringe_plan_info", "fringe_set_gains", "fringe_set_shifts",
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
+    "fringe_match", "fringe_localize", "fringe_delay_partials",
 )
 
 
@@ -84,6 +87,20 @@ CANDIDATE_DTYPE = np.dtype([
 assert CANDIDATE_DTYPE.itemsize == ctypes.sizeof(fringe_candidate) == 56
 
 
+class fringe_match_params(Structure):
+    _fields_ = [("min_windows", c_int32), ("min_baselines", c_int32)]
+
+
+PULSE_DTYPE = np.dtype([
+    ("scan", np.int32), ("pulse", np.int32), ("baseline", np.int32), ("window_ap", np.int32),
+    ("t_start", np.int32), ("k_rate", np.int32), ("k_delay", np.int32), ("t_lo", np.int32),
+    ("t_hi", np.int32), ("n_windows", np.int32), ("n_lengths", np.int32),
+    ("amp", np.float32), ("snr", np.float32), ("reserved", np.int32),
+    ("delay_s", np.float64), ("rate_hz", np.float64),
+], align=True)
+assert PULSE_DTYPE.itemsize == 72
+
+
 class FringeError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         self.code = code
@@ -119,6 +136,11 @@ def load(path: Optional[str] = None):
     lib.fringe_strerror.restype = c_char_p
     lib.fringe_last_error.argtypes = []
     lib.fringe_last_error.restype = c_char_p
+    lib.fringe_match.argtypes = [c_void_p, c_int64, POINTER(fringe_match_params), c_void_p,
+                                 c_int64, POINTER(c_int64), POINTER(c_int64)]
+    dp = POINTER(c_double)
+    lib.fringe_localize.argtypes = [dp, dp, dp, c_int32, dp, dp, dp, dp]
+    lib.fringe_delay_partials.argtypes = [dp, c_int32, c_double, c_double, c_double, dp, dp]
     for name in ENTRY_POINTS:
         if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error"):
             getattr(lib, name).restype = c_int
@@ -282,6 +304,75 @@ def fringe_set_shifts(plan: int, scan: int, d_shifts) -> None:
 def fringe_plan_destroy(plan: int) -> None:
     if plan:
         load().fringe_plan_destroy(c_void_p(plan))
+
+
+def as_candidates(records: np.ndarray) -> np.ndarray:
+    """Records with the candidate fields (any field order or widths, extra
+    fields ignored) as a contiguous CANDIDATE_DTYPE array, copied by name."""
+    if records.dtype == CANDIDATE_DTYPE:
+        return np.ascontiguousarray(records)
+    out = np.zeros(len(records), CANDIDATE_DTYPE)
+    for name in CANDIDATE_DTYPE.names:
+        if name in records.dtype.names:
+            out[name] = records[name]
+        elif name != "reserved":
+            raise ValueError(f"candidate records lack the field {name!r}")
+    return out
+
+
+def fringe_match(candidates: np.ndarray, min_windows: int = 2, min_baselines: int = 5):
+    """Single pulses from a candidate list (CANDIDATE_DTYPE records):
+    (rows as a PULSE_DTYPE array in (pulse, baseline) order, number of pulses)."""
+    lib = load()
+    c = as_candidates(candidates)
+    p = fringe_match_params(int(min_windows), int(min_baselines))
+    n_rows, n_pulses = c_int64(0), c_int64(0)
+    cptr = c.ctypes.data_as(c_void_p) if len(c) else None
+    rc = lib.fringe_match(cptr, len(c), ctypes.byref(p), None, 0, ctypes.byref(n_rows),
+                          ctypes.byref(n_pulses))
+    if rc not in (FRINGE_OK, FRINGE_E_CAPACITY) or (rc == FRINGE_E_CAPACITY and n_rows.value == 0):
+        _check(rc, "fringe_match")
+    out = np.zeros(n_rows.value, PULSE_DTYPE)
+    if n_rows.value:
+        _check(lib.fringe_match(cptr, len(c), ctypes.byref(p), out.ctypes.data_as(c_void_p),
+                                len(out), ctypes.byref(n_rows), ctypes.byref(n_pulses)),
+               "fringe_match")
+    return out, int(n_pulses.value)
+
+
+def _f64(v) -> np.ndarray:
+    return np.ascontiguousarray(v, dtype=np.float64)
+
+
+def fringe_localize(tau, dtau_dra, dtau_ddec):
+    """Eq. (2) least squares: (sol (2,), rms, loo (n, 2), loo_rms (n,));
+    the leave-one-out arrays are empty for two baselines."""
+    t, a, d = _f64(tau).ravel(), _f64(dtau_dra).ravel(), _f64(dtau_ddec).ravel()
+    if not (len(t) == len(a) == len(d)):
+        raise ValueError("tau and the partials must have the same length")
+    n = len(t)
+    sol, rms = np.zeros(2), c_double(0)
+    loo, loo_rms = np.zeros((n, 2)), np.zeros(n)
+    dp = POINTER(c_double)
+    _check(load().fringe_localize(t.ctypes.data_as(dp), a.ctypes.data_as(dp), d.ctypes.data_as(dp),
+                                  n, sol.ctypes.data_as(dp), ctypes.byref(rms),
+                                  loo.ctypes.data_as(dp), loo_rms.ctypes.data_as(dp)),
+           "fringe_localize")
+    if n < 3:
+        loo, loo_rms = loo[:0], loo_rms[:0]
+    return sol, rms.value, loo, loo_rms
+
+
+def fringe_delay_partials(b_xyz, gast: float, ra: float, dec: float):
+    """(dtau/dra, dtau/ddec) in s/rad for Earth-fixed baseline vectors (n, 3) in metres."""
+    b = _f64(b_xyz).reshape(-1, 3)
+    n = len(b)
+    da, dd = np.zeros(n), np.zeros(n)
+    dp = POINTER(c_double)
+    _check(load().fringe_delay_partials(b.ctypes.data_as(dp), n, float(gast), float(ra),
+                                        float(dec), da.ctypes.data_as(dp), dd.ctypes.data_as(dp)),
+           "fringe_delay_partials")
+    return da, dd
 
 
 class Plan:

@@ -2,8 +2,10 @@
 
     python -m paper_2108_05602_amd.build
 
-Every source is compiled each call (a few tens of seconds); objects are
-built in parallel and linked into paper_2108_05602_amd/lib/libfringe.so.
+Every source is compiled each call (a few tens of seconds): the .hip
+sources with hipcc for gfx950, the host-only .cpp sources (the candidate
+consumers) with the host C++ compiler; objects are built in parallel and
+linked into paper_2108_05602_amd/lib/libfringe.so.
 """
 
 from __future__ import annotations
@@ -36,8 +38,19 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}"]
+
+
+def _cxx() -> str:
+    for cand in (os.environ.get("CXX"), shutil.which("g++"), shutil.which("c++")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("no host C++ compiler found")
+
+
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                  if f.endswith(".hip") or f.endswith(".cpp"))
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
@@ -47,13 +60,17 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
 
     def compile_one(src):
-        obj = os.path.join(objdir, os.path.basename(src)[:-4] + ".o")
-        cmd = [hipcc, *HIP_FLAGS, "-c", src, "-o", obj]
+        stem, ext = os.path.splitext(os.path.basename(src))
+        obj = os.path.join(objdir, stem + ext.replace(".", "_") + ".o")
+        if ext == ".cpp":
+            cmd = [_cxx(), *CXX_FLAGS, "-c", src, "-o", obj]
+        else:
+            cmd = [hipcc, *HIP_FLAGS, "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         err = "\n".join(l for l in (r.stderr or "").splitlines()
                         if "packed-fp32-ops" not in l)
         if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed on {src}:\n{err}")
+            raise RuntimeError(f"compile failed on {src}:\n{err}")
         if verbose and err.strip():
             print(err, file=sys.stderr)
         return obj

@@ -1228,3 +1228,9 @@ int fringe_plan_info(fringe_plan_t p, fringe_plan_summary* out) {
 void fringe_plan_destroy(fringe_plan_t p) { release(p); }
 
 }  // extern "C"
+
+namespace fringe {
+// Lets the host-only consumers (matching, localization) report their
+// failures through fringe_last_error.
+void set_last_error(const char* msg) { g_last_error = msg; }
+}  // namespace fringe

@@ -1,5 +1,5 @@
 """CPU-only checks of the C ABI: the library loads, exports every entry
-point declared in include/fringe.h, and its host-side validation and
+point declared in include/*.h, and its host-side validation and
 sizing behave as documented (no device work is done here)."""
 
 import ctypes
@@ -21,7 +21,9 @@ C2_W = [1, 2, 4, 8, 16, 32]
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "fringe.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc))
+                   if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
                        text, flags=re.M)
@@ -42,6 +44,8 @@ def test_struct_layouts():
     assert ctypes.sizeof(B.fringe_params) == 48
     assert ctypes.sizeof(B.fringe_candidate) == 56
     assert ctypes.sizeof(B.fringe_plan_summary) == 32
+    assert ctypes.sizeof(B.fringe_match_params) == 8
+    assert B.PULSE_DTYPE.itemsize == 72
 
 
 def test_strerror():
