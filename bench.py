@@ -166,6 +166,44 @@ def delay_only_leg(dev, spec, params, steps=5):
             "candidates": int(len(c))}
 
 
+def single_pulse_leg(cands, spec, reps=20):
+    """The candidate consumers on the timed search's candidates (host code):
+    matching into single pulses (paper criteria: 2 window lengths, 5
+    baselines) and one Eq. (2) solve with leave-one-out per pulse."""
+    import paper_2108_05602_amd as F
+    import synth
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rows, n_p = F.fringe_match(cands, 2, 5)
+    match_ms = (time.perf_counter() - t0) / reps * 1e3
+    spans = {}
+    for r in rows:
+        lo, hi = spans.get(int(r["pulse"]), (1 << 62, -1))
+        spans[int(r["pulse"])] = (min(lo, int(r["t_lo"])), max(hi, int(r["t_hi"])))
+    found = sum(1 for q in spec.pulses
+                if any(lo < q.start + q.width and q.start < hi for lo, hi in spans.values()))
+    # localization timing: each pulse's delays against partials of a random
+    # Earth-fixed array (the synthetic delays are not geometric, so only the
+    # solve's cost is measured here, not its answer)
+    rng = np.random.default_rng(0)
+    st = rng.normal(0, 3e6, (spec.n_stations, 3))
+    pairs = synth.baseline_pairs(spec.n_stations)
+    b_xyz = np.array([st[j] - st[i] for i, j in pairs])
+    da, dd = F.fringe_delay_partials(b_xyz, 1.0, 0.5, 0.6)
+    t0 = time.perf_counter()
+    n_solve = 0
+    for pid in spans:
+        sel = rows[rows["pulse"] == pid]
+        bl = sel["baseline"]
+        F.fringe_localize(sel["delay_s"], da[bl], dd[bl])
+        n_solve += 1
+    loc_ms = (time.perf_counter() - t0) * 1e3
+    return {"candidates": int(len(cands)), "single_pulses": int(n_p), "rows": int(len(rows)),
+            "injected": len(spec.pulses), "injected_found": int(found),
+            "match_ms": match_ms, "localize_ms_total": loc_ms, "solves": n_solve,
+            "host": "one CPU thread"}
+
+
 def dm_search_leg(dev, spec, params, n_dm=20, dm_max=500.0, steps=2):
     """A DM search of the same resident scan: n_dm trials (DM 0..dm_max,
     channels from 1.6 GHz up) as n_dm scans of one plan over the one cube,
@@ -457,6 +495,9 @@ def main():
         log("timing the one-window-per-launch path against the batched path")
         out["plain_vs_batched"] = plain_vs_batched(dev, spec, params)
         log("plain vs batched: " + json.dumps(out["plain_vs_batched"]))
+    log("single pulses from the candidates (host matching and localization)")
+    out["single_pulses"] = single_pulse_leg(cands, spec)
+    log("single pulses: " + json.dumps(out["single_pulses"]))
     log("delay-only search of the same scan")
     out["delay_only"] = delay_only_leg(dev, spec, params)
     log("delay-only: " + json.dumps(out["delay_only"]))
