@@ -5,8 +5,8 @@
  * touch no device memory); they take the candidate list that
  * candidates_get returns.
  *
- * Matching (paper, section "Performance improvement", the selection
- * criteria of the fringe search).  The criteria name no grouping rule;
+ * Matching (paper, section "Detection rate": the criteria a single pulse
+ * must meet).  The criteria name no grouping rule;
  * groups here are anchored at their strongest member (so that a long-lived
  * RFI signal, whose windows overlap one another for seconds, cannot chain
  * distinct pulses into one):
@@ -29,9 +29,9 @@
  * the offsets (dra, ddec) from the a priori position in
  *   tau_b - tau_cal_b = (dtau/dra)_b dra + (dtau/ddec)_b ddec
  * over a pulse's baselines b, and the same solve leaving out each baseline
- * in turn (the paper's check for a baseline whose delay is wrong: the
- * solutions that include it deviate; the fit without it has the smallest
- * residual).
+ * in turn (section "Localization accuracy": the check for a baseline whose
+ * delay is wrong, since the solutions that include it deviate; the fit
+ * without it has the smallest residual).
  *
  * Conventions as in fringe.h: 0 or a negative FRINGE_E_* code, detail in
  * fringe_last_error(); every call is reentrant (no shared state).

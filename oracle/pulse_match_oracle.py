@@ -1,13 +1,13 @@
 """Reference single-pulse matching and delay-only localization, plain Python.
 
 TEST INFRASTRUCTURE ONLY: nothing in the product path imports or runs it;
-the test suite does.  Brute force by design (every pair of windows compared,
-connected components by breadth-first search, least squares by numpy), so
-that it can be checked against the paper by eye.
+the test suite does.  Brute force by design (each anchor compared with every
+remaining item, distinct counts by sets, least squares by numpy), so that it
+can be checked against the paper by eye.
 
-What is computed (paper, section "Performance improvement", the selection
-criteria of the fringe search, and section "Localization", Eq. (2) with the
-leave-one-baseline-out check).  The criteria name no grouping rule; groups
+What is computed (paper: the single-pulse criteria of section "Detection
+rate"; Eq. (2) of section "Localization"; the leave-one-baseline-out check
+of section "Localization accuracy").  The criteria name no grouping rule; groups
 here are anchored at their strongest member, so that a long-lived RFI
 signal cannot chain distinct pulses into one:
 
