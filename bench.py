@@ -35,24 +35,28 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # HBM bytes of one fused-kernel launch on the full EVN-like scan, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
 # the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99990,
-# WRITE_SIZE x 1.0).  Valid only for the kernel sources they were taken on:
-# `traffic` is reported as null when the hash of csrc/ differs.
+# WRITE_SIZE x 1.0).  Valid only for the kernel and launch code they were
+# taken on: `traffic` is reported as null when the hash of those sources
+# (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "csrc_sha256": "b74e9547f50fbddcb0cc48ab64e6aff7a639d178e33b95933872eff1afb6ca93",
+    "kernel_sha256": "b74e9547f50fbddcb0cc48ab64e6aff7a639d178e33b95933872eff1afb6ca93",
     "fetch_bytes": 6598477490,
     "write_bytes": 1840910112,
 }
 
+# The fused search kernel of the EVN-like scan and the host code that sizes
+# and launches it.
+KERNEL_SOURCES = ("dev_common.h", "window_key.h", "fused_search.h", "kernels.h",
+                  "fused_p2_w32.hip", "fused_dispatch.hip", "fringe_api.hip")
 
-def csrc_hash():
-    import glob
+
+def kernel_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2108_05602_amd", "csrc", "*"))):
-        if f.endswith((".h", ".hip")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2108_05602_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -82,23 +86,73 @@ def algorithmic_flops(n_bl, n_ap, n_freq, window_aps, pad_f, pad_t):
     return delay, rate, peak
 
 
-def cpu_baseline(spec, params, n_bl=8, n_ap=4096):
-    """The CPU reference, as it stands, on a bounded sample of the same scan."""
-    from threadpoolctl import threadpool_info
+def cpu_baseline(spec, params, n_bl=24, n_ap=4096, n_bl_one=1):
+    """The CPU reference, as it stands, on a bounded sample of the same scan:
+    with numpy's BLAS pool (the reported value) and on one thread, plus the
+    projection of the full scan at the pool's rate."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import fringe_oracle as fo
-    xs = [spec.baseline(b, 0, n_ap).reshape(n_ap, -1) for b in range(n_bl)]
-    t0 = time.perf_counter()
-    n = 0
-    for b, x in enumerate(xs):
-        n += len(fo.search_baseline(x, params["window_aps"], params["pad_freq"],
-                                    params["pad_time"], spec.ap_seconds, spec.chan_width_hz,
-                                    baseline=b))
-    dt = time.perf_counter() - t0
+
+    def run(n_b):
+        xs = [spec.baseline(b, 0, n_ap).reshape(n_ap, -1) for b in range(n_b)]
+        t0 = time.perf_counter()
+        n = 0
+        for b, x in enumerate(xs):
+            n += len(fo.search_baseline(x, params["window_aps"], params["pad_freq"],
+                                        params["pad_time"], spec.ap_seconds, spec.chan_width_hz,
+                                        baseline=b))
+        return n, time.perf_counter() - t0
+
+    n, dt = run(n_bl)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        n1, dt1 = run(n_bl_one)
+    n_full = sum(n_w for _, _, n_w in window_levels(spec.n_ap, params["window_aps"])) * spec.n_baselines
     return {"value": n / dt, "unit": "windows/s", "cores": int(threads), "kind": "oracle",
             "sample": f"baselines 0-{n_bl - 1} x APs 0-{n_ap - 1} of the same scan, all "
-                      f"{len(params['window_aps'])} window lengths: {n} windows in {dt:.1f} s"}
+                      f"{len(params['window_aps'])} window lengths: {n} windows in {dt:.1f} s",
+            "one_thread": {"value": n1 / dt1, "sample": f"baseline 0 x APs 0-{n_ap - 1}: "
+                                                        f"{n1} windows in {dt1:.1f} s"},
+            "full_scan_projection_s": n_full / (n / dt)}
+
+
+def roof_probes(reps=5):
+    """Achievable roofs of this device, by the library's probe kernels: an
+    FP32 FMA loop (non-packed instructions, like the search) and a 1 GiB
+    HBM copy; best of `reps` launches, timed with HIP events on the stream
+    they run on."""
+    import torch
+
+    from paper_2108_05602_amd import binding as B
+    st = torch.cuda.current_stream()
+    n_blocks, iters = 256 * 16, 16384
+    out = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda:0")
+    best_fma = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        fl = B.fringe_probe_fma(n_blocks, iters, out.data_ptr(), st.cuda_stream)
+        e1.record(st)
+        e1.synchronize()
+        best_fma = max(best_fma, fl / (e0.elapsed_time(e1) / 1e3) / 1e12)
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    best_copy = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        B.fringe_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, st.cuda_stream)
+        e1.record(st)
+        e1.synchronize()
+        best_copy = max(best_copy, 2 * nbytes / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    assert torch.equal(src[:1024], dst[:1024]) and torch.isfinite(out).all()
+    del src, dst, out
+    return {"fp32_fma_tflops": best_fma, "hbm_copy_gbs": best_copy,
+            "published": {"fp32_tflops": PEAK_FP32_TFLOPS, "hbm_gbs": PEAK_HBM_GBS},
+            "method": f"FMA loop {n_blocks} x 256 lanes x 16 chains x {iters}; copy 1 GiB "
+                      f"read + 1 GiB written; best of {reps}"}
 
 
 def plain_vs_batched(dev, spec, params, n_bl=3, n_ap=4096, reps=5):
@@ -444,7 +498,7 @@ def main():
     cube_bytes = spec.nbytes()
     info_kb = params["pad_freq"] * spec.n_freq // 64   # delay-bin classes of 64 bins
     traffic = None
-    if fused and full and csrc_hash() == MEASURED_TRAFFIC["csrc_sha256"]:
+    if fused and full and kernel_hash() == MEASURED_TRAFFIC["kernel_sha256"]:
         traffic = MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]
     out = {
         "metric": "fringe-fit windows/s + HBM GB/s vs roofline; p50/p99 window latency",
@@ -513,6 +567,10 @@ def main():
         pts = out["serving"]["points"]
         out["p50_ms"] = next(p["p50_ms"] for p in pts if p["load"] == 1.0)
         out["p99_ms"] = next(p["p99_ms"] for p in pts if p["load"] == 1.0)
+    log("roof probes: FP32 FMA loop and HBM copy")
+    out["roofs_measured"] = roof_probes()
+    out["roofline"]["frac_of_measured_peak"] = achieved / out["roofs_measured"]["fp32_fma_tflops"]
+    log("roofs: " + json.dumps(out["roofs_measured"]))
     if not args.no_cpu_baseline:
         log("timing the CPU reference on its sample")
         out["cpu_baseline"] = cpu_baseline(spec, params)

@@ -1,5 +1,5 @@
-"""ctypes binding of libfringe (include/fringe.h, include/fringe_match.h):
-argument marshalling only.
+"""ctypes binding of libfringe (include/fringe.h, include/fringe_match.h,
+include/fringe_probe.h): argument marshalling only.
 
 Every function here has the name of the C entry point it calls and does no
 computation of its own; all search work runs in the library's HIP kernels,
@@ -44,6 +44,7 @@ ENTRY_POINTS = (
     "fringe_plan_info", "fringe_set_gains", "fringe_set_shifts",
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
     "fringe_match", "fringe_localize", "fringe_delay_partials",
+    "fringe_probe_fma", "fringe_probe_copy",
 )
 
 
@@ -141,6 +142,8 @@ def load(path: Optional[str] = None):
     dp = POINTER(c_double)
     lib.fringe_localize.argtypes = [dp, dp, dp, c_int32, dp, dp, dp, dp]
     lib.fringe_delay_partials.argtypes = [dp, c_int32, c_double, c_double, c_double, dp, dp]
+    lib.fringe_probe_fma.argtypes = [c_int64, c_int32, c_void_p, dp, c_void_p]
+    lib.fringe_probe_copy.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
     for name in ENTRY_POINTS:
         if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error"):
             getattr(lib, name).restype = c_int
@@ -373,6 +376,20 @@ def fringe_delay_partials(b_xyz, gast: float, ra: float, dec: float):
                                         float(dec), da.ctypes.data_as(dp), dd.ctypes.data_as(dp)),
            "fringe_delay_partials")
     return da, dd
+
+
+def fringe_probe_fma(n_blocks: int, iters: int, d_out: int, stream: int = 0) -> float:
+    """Enqueue the FP32 FMA-loop probe; returns the flops of the launch."""
+    fl = c_double(0)
+    _check(load().fringe_probe_fma(int(n_blocks), int(iters), c_void_p(d_out), ctypes.byref(fl),
+                                   c_void_p(int(stream) if stream else None)), "fringe_probe_fma")
+    return fl.value
+
+
+def fringe_probe_copy(d_src: int, d_dst: int, nbytes: int, stream: int = 0) -> None:
+    """Enqueue the HBM copy probe (nbytes read and nbytes written)."""
+    _check(load().fringe_probe_copy(c_void_p(d_src), c_void_p(d_dst), int(nbytes),
+                                    c_void_p(int(stream) if stream else None)), "fringe_probe_copy")
 
 
 class Plan:

@@ -48,6 +48,22 @@ def test_struct_layouts():
     assert B.PULSE_DTYPE.itemsize == 72
 
 
+def test_probe_argument_checks():
+    # host-side validation only: every call below is rejected before a launch
+    with pytest.raises(F.FringeError):
+        B.fringe_probe_fma(0, 10, 16)
+    with pytest.raises(F.FringeError):
+        B.fringe_probe_fma(1, 0, 16)
+    with pytest.raises(F.FringeError):
+        B.fringe_probe_fma(1, 10, 0)
+    with pytest.raises(F.FringeError):
+        B.fringe_probe_copy(16, 32, 15)
+    with pytest.raises(F.FringeError):
+        B.fringe_probe_copy(16, 40, 64)
+    with pytest.raises(F.FringeError):
+        B.fringe_probe_copy(0, 32, 64)
+
+
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert F.fringe_strerror(code)
