@@ -4,6 +4,7 @@
 
 #include <cstdint>
 
+#include "dev_common.h"
 #include "fringe_probe.h"
 
 namespace fringe {
@@ -18,12 +19,15 @@ constexpr int kChains = 16;
 __global__ __launch_bounds__(kProbeLanes) void fma_probe_kernel(float* __restrict__ out,
                                                                 int iters, float a, float b) {
   const int lane = threadIdx.x;
+  // operands in VGPRs: the accumulate form x += a * b (v_fmac_f32 with
+  // vector sources), the form of the search kernels' FMAs
+  const float av = fringe::in_vgpr(a), bv = fringe::in_vgpr(b);
   float x[kChains];
 #pragma unroll
   for (int c = 0; c < kChains; ++c) x[c] = 1.0f + 0.001f * float(lane + c);
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) x[c] = __builtin_fmaf(x[c], a, b);
+    for (int c = 0; c < kChains; ++c) x[c] = __builtin_fmaf(av, bv, x[c]);
   }
   float s = 0.0f;
 #pragma unroll
@@ -49,9 +53,9 @@ int fringe_probe_fma(int64_t n_blocks, int32_t iters, float* d_out, double* flop
     return FRINGE_E_INVALID;
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // a, b keep every chain near its fixed point b / (1 - a) = 1
+  // each chain grows by a * b = 1e-6 per step: finite for any iters
   hipLaunchKernelGGL(fma_probe_kernel, dim3(uint32_t(n_blocks)), dim3(kProbeLanes), 0, st,
-                     d_out, int(iters), 0.999f, 0.001f);
+                     d_out, int(iters), 0.001f, 0.001f);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     fringe::set_last_error(hipGetErrorString(e));
