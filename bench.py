@@ -34,14 +34,14 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 
 # HBM bytes of one fused-kernel launch on the full EVN-like scan, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
-# the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99990,
+# the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99989,
 # WRITE_SIZE x 1.0).  Valid only for the kernel and launch code they were
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "b74e9547f50fbddcb0cc48ab64e6aff7a639d178e33b95933872eff1afb6ca93",
-    "fetch_bytes": 6598477490,
-    "write_bytes": 1840910112,
+    "kernel_sha256": "0c7a61cf0dd6e08cbb34b759b071c1e5976e5fa513243c6bb72893a33bc07f61",
+    "fetch_bytes": 6622832179,
+    "write_bytes": 1843507168,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
