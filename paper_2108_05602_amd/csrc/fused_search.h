@@ -9,7 +9,9 @@
 // lane l loads and folds f = l (contiguous loads), one LDS permute moves the
 // fold to lane bitrev6(f), then six radix-2 decimation-in-time stages
 // across the wave (partners exchanged on the LDS crossbar: ds_swizzle and
-// ds_bpermute, no LDS memory) leave X_t of lane m's bin in lane m.  Each lane keeps the last W_max APs of its bin's
+// ds_bpermute, no LDS memory) leave X_t of lane m's bin in lane m (in the
+// full search two APs at a time, their exchanges interleaved so that one
+// crossbar latency serves both).  Each lane keeps the last W_max APs of its bin's
 // spectrum in registers: the APs come in periods of P = W_max / 2 that are
 // unrolled, so every window that ends in a period has compile-time register
 // positions; after the period the newer half moves down.  Every window that
@@ -44,18 +46,24 @@ __device__ __forceinline__ float xchg(float v, int addr32) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(addr32, __float_as_int(v)));
 }
 
-// One DIT stage of half-span D.  Lanes with bit D set ("b" lanes) first
-// multiply their value by w (w = 1 on "a" lanes); then a' = a + w b and
-// b' = a - w b, i.e. new = s * own + partner with s = +1 on a lanes, -1 on
-// b lanes.
-template <int D>
-__device__ __forceinline__ float2 dit_stage(float2 v, float2 w, float s, bool rot, int addr32) {
-  // D = 2: the twiddle is 1 or -i (rot), applied by selects
-  const float2 t = (D == 1) ? v
-                 : (D == 2) ? make_float2(rot ? v.y : v.x, rot ? -v.x : v.y)
-                            : c_mul(v, w);
-  const float px = xchg<D>(t.x, addr32), py = xchg<D>(t.y, addr32);
-  return make_float2(fmaf(s, t.x, px), fmaf(s, t.y, py));
+// One DIT stage of half-span D on N independent values (N APs: their
+// exchanges are issued together, so one crossbar latency serves all N).
+// Lanes with bit D set ("b" lanes) first multiply their value by w (w = 1
+// on "a" lanes); then a' = a + w b and b' = a - w b, i.e. new = s * own +
+// partner with s = +1 on a lanes, -1 on b lanes.
+template <int D, int N>
+__device__ __forceinline__ void dit_stage(float2 (&v)[N], float2 w, float s, bool rot,
+                                          int addr32) {
+  float2 t[N], p[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n)  // D = 2: the twiddle is 1 or -i (rot), applied by selects
+    t[n] = (D == 1) ? v[n]
+         : (D == 2) ? make_float2(rot ? v[n].y : v[n].x, rot ? -v[n].x : v[n].y)
+                    : c_mul(v[n], w);
+#pragma unroll
+  for (int n = 0; n < N; ++n) p[n] = make_float2(xchg<D>(t[n].x, addr32), xchg<D>(t[n].y, addr32));
+#pragma unroll
+  for (int n = 0; n < N; ++n) v[n] = make_float2(fmaf(s, t[n].x, p[n].x), fmaf(s, t[n].y, p[n].y));
 }
 
 struct LaneConsts {
@@ -66,14 +74,14 @@ struct LaneConsts {
   float2 wfold;  // w_M^{c f'} of this lane's f'
 };
 
-__device__ __forceinline__ float2 xlane_dit(float2 v, const LaneConsts& k) {
-  v = dit_stage<1>(v, k.w[0], k.s[0], false, k.addr32);
-  v = dit_stage<2>(v, k.w[1], k.s[1], k.rot2, k.addr32);
-  v = dit_stage<4>(v, k.w[2], k.s[2], false, k.addr32);
-  v = dit_stage<8>(v, k.w[3], k.s[3], false, k.addr32);
-  v = dit_stage<16>(v, k.w[4], k.s[4], false, k.addr32);
-  v = dit_stage<32>(v, k.w[5], k.s[5], false, k.addr32);
-  return v;
+template <int N>
+__device__ __forceinline__ void xlane_dit(float2 (&v)[N], const LaneConsts& k) {
+  dit_stage<1>(v, k.w[0], k.s[0], false, k.addr32);
+  dit_stage<2>(v, k.w[1], k.s[1], k.rot2, k.addr32);
+  dit_stage<4>(v, k.w[2], k.s[2], false, k.addr32);
+  dit_stage<8>(v, k.w[3], k.s[3], false, k.addr32);
+  dit_stage<16>(v, k.w[4], k.s[4], false, k.addr32);
+  dit_stage<32>(v, k.w[5], k.s[5], false, k.addr32);
 }
 
 constexpr int ilog2c(int v) { return v > 1 ? 1 + ilog2c(v / 2) : 0; }
@@ -105,13 +113,18 @@ constexpr int site_level(int i, int k) {
 }  // namespace fused
 
 template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
-__global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __restrict__ tab,
-                                                           int n_tab) {
+__global__ void __launch_bounds__(64)
+fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   constexpr int WMAX = 1 << LOGWMAX;
   constexpr int P = WMAX / 2;          // APs per unrolled period
   constexpr int HS = 2 * P;            // history registers (complex)
   constexpr int PD = HFMAX > 4 ? 1 : 2;  // prefetch depth in APs
-  static_assert(P % PD == 0 && P >= 4, "period");
+  // APs whose delay transforms run together (their crossbar exchanges
+  // interleaved): the prefetched ones in the full search, where that hides
+  // exchange latency behind the rate transforms; one at a time in the
+  // delay-only search, which measured faster so (fewer live registers).
+  constexpr int G = PT > 0 ? PD : 1;
+  static_assert(P % PD == 0 && P % G == 0 && P >= 4, "period");
 
   const int lane = threadIdx.x;
   // the entry (scan slab) that owns this block
@@ -260,38 +273,51 @@ __global__ void __launch_bounds__(64) fused_search_kernel(const FusedArgs* __res
     });
     static_for<0, P>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
-      constexpr int fs = i % PD;
       const int t = p0 + i;
-      // delay transform of AP t for this class: fold, then across the wave.
+      // delay transform of APs t .. t + G - 1 for this class (transformed
+      // together at the first of them): fold, then across the wave.
       // Samples outside the data (past the scan's end, lanes past a band
       // narrower than the fold) are zeroed on a uniform branch, so APs with
       // none spend nothing on it.
-      if (!(band_full && t < T)) {
-        const bool t_in = t < T;
+      if constexpr (i % G == 0) {
+        float2 z[G];
+        static_for<0, G>([&](auto di) {
+          constexpr int e = decltype(di)::value;
+          constexpr int fs = (i + e) % PD;  // prefetch slot of AP t + e
+          const int te = t + e;
+          if (!(band_full && te < T)) {
+            const bool t_in = te < T;
 #pragma unroll
-        for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
+            for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
+          }
+          if (has_g) {
+#pragma unroll
+            for (int h = 0; h < HFMAX; ++h)
+              pre[fs][h] = c_mul(pre[fs][h], ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0));
+          }
+          z[e] = pre[fs][0];
+#pragma unroll
+          for (int h = 1; h < HFMAX; ++h) z[e] = c_add(z[e], c_mul(pre[fs][h], wh[h]));
+          if (PT > 0 && cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
+            float es = 0.f;
+#pragma unroll
+            for (int h = 0; h < HFMAX; ++h) es += c_norm(pre[fs][h]);
+            const float en = wave_sum_dpp(es);
+            if (lane == 0 && te < own_hi) eb[te] = en;
+          }
+          load_ap(te + PD, pre[fs]);
+          // lane l folded f = l; the transform wants f' = bitrev6(l) in lane l
+          z[e] = c_mul(make_float2(
+              __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z[e].x))),
+              __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z[e].y)))),
+              kc.wfold);
+        });
+        fused::xlane_dit(z, kc);
+        static_for<0, G>([&](auto di) {
+          constexpr int e = decltype(di)::value;
+          hist[P + i + e] = z[e];
+        });
       }
-      if (has_g) {
-#pragma unroll
-        for (int h = 0; h < HFMAX; ++h)
-          pre[fs][h] = c_mul(pre[fs][h], ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0));
-      }
-      float2 z = pre[fs][0];
-#pragma unroll
-      for (int h = 1; h < HFMAX; ++h) z = c_add(z, c_mul(pre[fs][h], wh[h]));
-      if (PT > 0 && cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
-        float es = 0.f;
-#pragma unroll
-        for (int h = 0; h < HFMAX; ++h) es += c_norm(pre[fs][h]);
-        const float e = wave_sum_dpp(es);
-        if (lane == 0 && t < own_hi) eb[t] = e;
-      }
-      load_ap(t + PD, pre[fs]);
-      // lane l folded f = l; the transform wants f' = bitrev6(l) in lane l
-      z = make_float2(
-          __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z.x))),
-          __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z.y))));
-      hist[P + i] = fused::xlane_dit(c_mul(z, kc.wfold), kc);
 
       // every window that ends at AP t (and is reported: within the data,
       // at or after the first AP the call reports, starting in this chunk)
