@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "0c7a61cf0dd6e08cbb34b759b071c1e5976e5fa513243c6bb72893a33bc07f61",
-    "fetch_bytes": 6622832179,
-    "write_bytes": 1843507168,
+    "kernel_sha256": "43c8da630b48346e6f5d1faa10cdd982680a604a9c9ec74b41dbcf8b45729de8",
+    "fetch_bytes": 7818569568,
+    "write_bytes": 1999077440,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
