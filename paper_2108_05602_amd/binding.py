@@ -7,7 +7,9 @@ the matching and localization of candidates in its host code.
 Device buffers are passed as integer addresses (e.g. torch.Tensor.data_ptr())
 and streams as integer hipStream_t handles (torch.cuda.Stream.cuda_stream).
 The library must have been built (python -m paper_2108_05602_amd.build);
-loading fails loudly otherwise.
+loading fails loudly otherwise.  In a process that also uses torch, import
+torch first: the library then binds to the HIP runtime torch has loaded
+(loaded first, it would bring a second runtime that sees no device).
 """
 
 from __future__ import annotations
