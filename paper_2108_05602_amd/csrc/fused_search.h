@@ -223,9 +223,19 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
     constexpr int d = decltype(di)::value;
     load_ap(own_lo + d, pre[d]);
   });
+  // full search: the last 2P APs of this lane's bin.  Delay-only search:
+  // instead, per length 2^L the coherent sums of the windows that ended in
+  // the last 2P APs (sum[L][P + i] for a window ending at position i of the
+  // period), each window being the sum of its two halves; only the few
+  // sums a later window still needs stay live in registers.
   float2 hist[HS];
+  float2 sum[LOGWMAX + 1][HS];
 #pragma unroll
-  for (int k = 0; k < HS; ++k) hist[k] = make_float2(0.f, 0.f);
+  for (int k = 0; k < HS; ++k) {
+    hist[k] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int L = 0; L <= LOGWMAX; ++L) sum[L][k] = make_float2(0.f, 0.f);
+  }
 
   const auto eb = gptr(a.e + static_cast<int64_t>(b) * T);
   // per window length 2^L: searched or not, and the part index of the
@@ -315,7 +325,8 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
         fused::xlane_dit(z, kc);
         static_for<0, G>([&](auto di) {
           constexpr int e = decltype(di)::value;
-          hist[P + i + e] = z[e];
+          if constexpr (PT > 0) hist[P + i + e] = z[e];
+          else sum[0][P + i + e] = z[e];
         });
       }
 
@@ -325,18 +336,23 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
       if constexpr (PT == 0) {
         // delay-only: each window's APs summed coherently; the power of the
         // sum in this lane's bin is its key, and the class's power sum goes
-        // to the mean over the delay axis.  The windows ending here are
+        // to the mean over the delay axis.  The window (s, 2^L) is the sum of
+        // (s, 2^(L-1)), which ended 2^(L-1) APs ago, and (s + 2^(L-1),
+        // 2^(L-1)), which ends here (every length is summed, searched or
+        // not, as the next one's halves).  The windows ending here are
         // reduced together (independent DPP chains interleaved).
+        static_for<1, LOGWMAX + 1>([&](auto li) {
+          constexpr int L = decltype(li)::value;
+          if constexpr (fused::window_site<P>(i, L))
+            sum[L][P + i] = c_add(sum[L - 1][P + i - (1 << (L - 1))], sum[L - 1][P + i]);
+        });
         constexpr int NS = fused::window_sites<P, LOGWMAX>(i);
         uint32_t key[NS], mx[NS];
         float ps[NS];
         static_for<0, NS>([&](auto ki) {
           constexpr int k = decltype(ki)::value;
-          constexpr int W = 1 << fused::site_level<P, LOGWMAX>(i, k);
-          constexpr int base = P + i + 1 - W;
-          float2 sum = hist[base];
-          static_for<1, W>([&](auto ui) { sum = c_add(sum, hist[base + decltype(ui)::value]); });
-          ps[k] = c_norm(sum);
+          constexpr int L = fused::site_level<P, LOGWMAX>(i, k);
+          ps[k] = c_norm(sum[L][P + i]);
           key[k] = __float_as_uint(ps[k]);
           mx[k] = key[k];
         });
@@ -382,7 +398,11 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
       }
     });
 #pragma unroll
-    for (int k = 0; k < P; ++k) hist[k] = hist[P + k];
+    for (int k = 0; k < P; ++k) {
+      hist[k] = hist[P + k];
+#pragma unroll
+      for (int L = 0; L <= LOGWMAX; ++L) sum[L][k] = sum[L][P + k];
+    }
   }
 }
 
