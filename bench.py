@@ -208,11 +208,12 @@ def delay_only_leg(dev, spec, params, steps=5):
             kern += plan.profile()["rate_ms"]
         dt = (time.perf_counter() - t0) / steps
     m_f = params["pad_freq"] * spec.n_freq
-    # algorithmic work: the delay FFT of every AP, W - 1 complex adds and the
-    # power, max and power sum of each window's M_f bins
+    # algorithmic work: the delay FFT of every AP; per window and bin one
+    # complex add (a window is the sum of its two halves; none for W = 1)
+    # and the power, max and power sum
     flops = spec.n_baselines * spec.n_ap * 5.0 * m_f * math.log2(m_f)
     for w, s_, n in window_levels(spec.n_ap, params["window_aps"]):
-        flops += spec.n_baselines * n * m_f * (2.0 * (w - 1) + 5.0)
+        flops += spec.n_baselines * n * m_f * ((2.0 if w > 1 else 0.0) + 5.0)
     k_ms = kern / steps
     return {"windows_per_s": n_win / dt, "ms_per_step": dt * 1e3, "kernel_ms": k_ms,
             "kernel_tflops_algorithmic": flops / (k_ms * 1e-3) / 1e12,
