@@ -109,25 +109,24 @@ std::vector<BaselinePulse> baseline_pulses(const fringe_candidate* c, int64_t n,
     int64_t j = i + 1;
     while (j < n && c[idx[j]].scan == c[idx[i]].scan && c[idx[j]].baseline == c[idx[i]].baseline)
       ++j;
-    const fringe_candidate* g = c;
-    const int64_t* gi = idx.data() + i;
+    const int64_t* gi = idx.data() + i;  // the run's candidates, strongest first
     local.resize(j - i);
-    for (int64_t k = 0; k < j - i; ++k) local[k] = k;  // strength order within the run
-    auto span = [g, gi](int64_t k) {
-      const fringe_candidate& w = g[gi[k]];
+    for (int64_t k = 0; k < j - i; ++k) local[k] = k;
+    auto span = [c, gi](int64_t k) {
+      const fringe_candidate& w = c[gi[k]];
       return std::pair<int64_t, int64_t>(w.t_start, int64_t(w.t_start) + w.window_ap);
     };
     anchored_groups(j - i, local, span, [&](int64_t anchor, const std::vector<int64_t>& mem) {
       lengths.clear();
       int64_t lo = INT64_MAX, hi = INT64_MIN;
       for (int64_t k : mem) {
-        lengths.push_back(g[gi[k]].window_ap);
+        lengths.push_back(c[gi[k]].window_ap);
         lo = std::min(lo, span(k).first);
         hi = std::max(hi, span(k).second);
       }
       int32_t n_len = count_distinct(lengths);
       if (n_len >= min_windows)
-        out.push_back({g[gi[anchor]].scan, g[gi[anchor]].baseline, int32_t(lo), int32_t(hi),
+        out.push_back({c[gi[anchor]].scan, c[gi[anchor]].baseline, int32_t(lo), int32_t(hi),
                        int32_t(mem.size()), n_len, gi[anchor]});
     });
     i = j;
