@@ -259,10 +259,11 @@ def single_pulse_leg(cands, spec, reps=20):
             "host": "one CPU thread"}
 
 
-def dm_search_leg(dev, spec, params, n_dm=20, dm_max=500.0, steps=2):
+def dm_search_leg(dev, spec, params, n_dm=20, dm_max=500.0, steps=2, delay_only=False):
     """A DM search of the same resident scan: n_dm trials (DM 0..dm_max,
     channels from 1.6 GHz up) as n_dm scans of one plan over the one cube,
-    each with its dedispersion shifts; windows/s over all trials."""
+    each with its dedispersion shifts; windows/s over all trials.  With
+    delay_only, the paper's own dedispersed search (rate bin 0)."""
     import torch
 
     import paper_2108_05602_amd as F
@@ -274,7 +275,8 @@ def dm_search_leg(dev, spec, params, n_dm=20, dm_max=500.0, steps=2):
     st = torch.cuda.current_stream()
     with F.Plan([d] * n_dm, params["window_aps"], pad_freq=params["pad_freq"],
                 pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],
-                max_candidates=1 << 22, flags=F.FRINGE_PROFILE) as plan:
+                max_candidates=1 << 22,
+                flags=F.FRINGE_PROFILE | (F.FRINGE_DELAY_ONLY if delay_only else 0)) as plan:
         for s_, sh in enumerate(shifts):
             plan.set_shifts(s_, sh.data_ptr())
         n_win = plan.info()["n_windows"]
@@ -294,6 +296,61 @@ def dm_search_leg(dev, spec, params, n_dm=20, dm_max=500.0, steps=2):
             "windows": n_win, "windows_per_s": n_win / dt, "ms_per_step": dt * 1e3,
             "ms_per_dm_trial": dt * 1e3 / n_dm, "fused_kernel_ms": kern / steps,
             "fused_launches": launches, "candidates": int(len(c))}
+
+
+def dm_prepass_leg(dev, spec, params, n_dm=20, dm_max=500.0, group=10, steps=2):
+    """The paper's dedispersed delay-only search by the dedispersion pass
+    (fringe_dedisperse): per group of trials, each trial's cube dedispersed
+    into a buffer of its own, then one search of the group's buffers
+    without shifts; windows/s over all trials, the pass timed alone too."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    from paper_2108_05602_amd.dedisp import channel_freqs_hz, dm_shifts
+    d = spec.desc()
+    freqs = channel_freqs_hz(1.6e9, d["n_if"], d["n_chan"], d["chan_width_hz"])
+    dms = np.linspace(0.0, dm_max, n_dm)
+    shifts = [torch.from_numpy(dm_shifts(dm, freqs, d["ap_seconds"])).cuda() for dm in dms]
+    bufs = [torch.empty_like(dev) for _ in range(group)]
+    st = torch.cuda.current_stream()
+    with F.Plan([d] * group, params["window_aps"], pad_freq=params["pad_freq"],
+                pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],
+                max_candidates=1 << 22, flags=F.FRINGE_DELAY_ONLY | F.FRINGE_PROFILE) as plan:
+        ptrs = [b_.data_ptr() for b_ in bufs]
+
+        def step():
+            n_c, kern = 0, 0.0
+            for g0 in range(0, n_dm, group):
+                for k in range(group):
+                    F.fringe_dedisperse(dev.data_ptr(), ptrs[k], spec.n_baselines, spec.n_ap,
+                                        spec.n_freq, shifts[g0 + k].data_ptr(), st.cuda_stream)
+                plan.search(ptrs, st.cuda_stream)
+                n_c += len(plan.candidates(capacity=1 << 22))
+                kern += plan.profile()["rate_ms"]
+            return n_c, kern
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            n_c, kern = step()
+        dt = (time.perf_counter() - t0) / steps
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for k in range(group):
+            F.fringe_dedisperse(dev.data_ptr(), ptrs[k], spec.n_baselines, spec.n_ap,
+                                spec.n_freq, shifts[k].data_ptr(), st.cuda_stream)
+        e1.record(st)
+        e1.synchronize()
+        pass_ms = e0.elapsed_time(e1) / group
+        n_win = plan.info()["n_windows"] * (n_dm // group)
+    del bufs
+    return {"dm_trials": n_dm, "dm_max": dm_max, "group": group, "windows": n_win,
+            "windows_per_s": n_win / dt, "ms_per_step": dt * 1e3,
+            "ms_per_dm_trial": dt * 1e3 / n_dm, "pass_ms_per_trial": pass_ms,
+            "pass_hbm_gbs": 2 * spec.nbytes() / (pass_ms * 1e-3) / 1e9,
+            "fused_kernel_ms_per_trial": kern / n_dm, "candidates": int(n_c),
+            "buffers_gb": group * spec.nbytes() / 1e9}
 
 
 def graph_vs_eager(dev, spec, params, n_bl=15, n_ap=976, rounds=6, reps=50):
@@ -559,6 +616,12 @@ def main():
     log("DM search: 20 dedispersed trials of the same scan in one plan")
     out["dm_search"] = dm_search_leg(dev, spec, params)
     log("DM search: " + json.dumps(out["dm_search"]))
+    log("DM search, delay-only (the paper's dedispersed search)")
+    out["dm_search_delay_only"] = dm_search_leg(dev, spec, params, delay_only=True)
+    log("DM search, delay-only: " + json.dumps(out["dm_search_delay_only"]))
+    log("DM search, delay-only, by the dedispersion pass")
+    out["dm_search_delay_only_pass"] = dm_prepass_leg(dev, spec, params)
+    log("DM search, delay-only, pass: " + json.dumps(out["dm_search_delay_only_pass"]))
     log("small batch plan: eager launches vs graph replay")
     out["graph_vs_eager"] = graph_vs_eager(dev, spec, params)
     log("graph vs eager: " + json.dumps(out["graph_vs_eager"]))

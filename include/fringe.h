@@ -201,6 +201,24 @@ int fringe_set_gains(fringe_plan_t plan, int32_t scan, const fringe_cf32* d_gain
  * of samples. */
 int fringe_set_shifts(fringe_plan_t plan, int32_t scan, const int32_t* d_shifts);
 
+/* Dedispersion as a pass of its own, for plans without shifts (paper:
+ * section "Code optimization", step 4): d_out[b][t][f] = d_in[b][t + d_f][f],
+ * 0 where t + d_f >= n_ap, d_f = d_shifts[f] clamped to [0, n_ap] (the
+ * semantics of fringe_set_shifts).  d_in and d_out: device cubes of
+ * n_baselines x n_ap x n_freq complex64 in the layout above (n_freq = F =
+ * n_if * n_chan), not overlapping; d_shifts: device array of n_freq int32.
+ * The caller owns all three and keeps them valid until the work on
+ * hip_stream (a hipStream_t; NULL = default stream) has completed.
+ * Asynchronous.  Searching the result without shifts gives exactly what
+ * fringe_set_shifts gives on the original; the pass reads each input line
+ * once per output row, where the in-kernel shifts read it once per delay-bin
+ * class of the search, so it is the faster route for the delay-only search,
+ * whose kernel is bound by those reads, at the price of a cube-sized buffer.
+ * Errors: FRINGE_E_INVALID for null pointers, sizes below 1 or overlapping
+ * buffers; FRINGE_E_HIP for a failed launch. */
+int fringe_dedisperse(const fringe_cf32* d_in, fringe_cf32* d_out, int32_t n_baselines,
+                      int32_t n_ap, int32_t n_freq, const int32_t* d_shifts, void* hip_stream);
+
 /* Kernel times of the last search of a plan made with FRINGE_PROFILE,
  * measured with HIP events recorded on the search's stream around each
  * launch (waits for the search).  Times in milliseconds, summed over the

@@ -11,7 +11,7 @@ positions (fringe_match, fringe_localize, fringe_delay_partials).
 from .binding import (CANDIDATE_DTYPE, PULSE_DTYPE, FRINGE_DELAY_ONLY, FRINGE_DUMP_GRID, FRINGE_GRAPH, FRINGE_PLAIN, FRINGE_PROFILE, FRINGE_STREAMING, FringeError, Plan,
                       candidates_get, fringe_grid_get, fringe_last_error, fringe_plan,
                       fringe_plan_check, fringe_plan_destroy, fringe_plan_info, fringe_profile_get, fringe_search,
-                      fringe_set_gains, fringe_set_shifts, fringe_match, fringe_localize,
+                      fringe_set_gains, fringe_set_shifts, fringe_dedisperse, fringe_match, fringe_localize,
                       fringe_delay_partials,
                       fringe_strerror, fringe_window_id, fringe_windows_get, load)
 
@@ -19,7 +19,7 @@ __all__ = [
     "CANDIDATE_DTYPE", "PULSE_DTYPE", "FRINGE_DELAY_ONLY", "FRINGE_DUMP_GRID", "FRINGE_GRAPH", "FRINGE_PLAIN", "FRINGE_PROFILE", "FRINGE_STREAMING", "FringeError", "Plan",
     "candidates_get", "fringe_grid_get", "fringe_last_error", "fringe_plan",
     "fringe_plan_check", "fringe_plan_destroy", "fringe_plan_info", "fringe_profile_get", "fringe_search",
-    "fringe_set_gains", "fringe_set_shifts", "fringe_match", "fringe_localize",
+    "fringe_set_gains", "fringe_set_shifts", "fringe_dedisperse", "fringe_match", "fringe_localize",
     "fringe_delay_partials",
     "fringe_strerror", "fringe_window_id", "fringe_windows_get", "load",
 ]

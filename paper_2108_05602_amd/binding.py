@@ -43,7 +43,7 @@ FRINGE_DELAY_ONLY = 0x20
 ENTRY_POINTS = (
     "fringe_plan_check", "fringe_plan", "fringe_search", "candidates_get",
     "fringe_windows_get", "fringe_window_id", "fringe_grid_get", "fringe_profile_get",
-    "fringe_plan_info", "fringe_set_gains", "fringe_set_shifts",
+    "fringe_plan_info", "fringe_set_gains", "fringe_set_shifts", "fringe_dedisperse",
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
     "fringe_match", "fringe_localize", "fringe_delay_partials",
     "fringe_probe_fma", "fringe_probe_copy",
@@ -144,6 +144,8 @@ def load(path: Optional[str] = None):
     dp = POINTER(c_double)
     lib.fringe_localize.argtypes = [dp, dp, dp, c_int32, dp, dp, dp, dp]
     lib.fringe_delay_partials.argtypes = [dp, c_int32, c_double, c_double, c_double, dp, dp]
+    lib.fringe_dedisperse.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                      c_void_p]
     lib.fringe_probe_fma.argtypes = [c_int64, c_int32, c_void_p, dp, c_void_p]
     lib.fringe_probe_copy.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
     for name in ENTRY_POINTS:
@@ -378,6 +380,15 @@ def fringe_delay_partials(b_xyz, gast: float, ra: float, dec: float):
                                         float(dec), da.ctypes.data_as(dp), dd.ctypes.data_as(dp)),
            "fringe_delay_partials")
     return da, dd
+
+
+def fringe_dedisperse(d_in: int, d_out: int, n_baselines: int, n_ap: int, n_freq: int,
+                      d_shifts: int, stream: int = 0) -> None:
+    """Enqueue the dedispersion pass: d_out[b][t][f] = d_in[b][t + d_f][f]."""
+    _check(load().fringe_dedisperse(c_void_p(d_in), c_void_p(d_out), int(n_baselines), int(n_ap),
+                                    int(n_freq), c_void_p(d_shifts),
+                                    c_void_p(int(stream) if stream else None)),
+           "fringe_dedisperse")
 
 
 def fringe_probe_fma(n_blocks: int, iters: int, d_out: int, stream: int = 0) -> float:

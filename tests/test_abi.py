@@ -48,6 +48,19 @@ def test_struct_layouts():
     assert B.PULSE_DTYPE.itemsize == 72
 
 
+def test_dedisperse_argument_checks():
+    # host-side validation only: rejected before any launch
+    for args in [(0, 4096, 1, 10, 8, 64), (64, 0, 1, 10, 8, 64), (64, 4096, 0, 10, 8, 64),
+                 (64, 4096, 1, 0, 8, 64), (64, 4096, 1, 10, 8, 0)]:
+        with pytest.raises(F.FringeError) as e:
+            F.fringe_dedisperse(*args)
+        assert e.value.code == B.FRINGE_E_INVALID
+    # overlapping input and output (1 x 10 x 8 samples of 8 bytes = 640 bytes)
+    with pytest.raises(F.FringeError) as e:
+        F.fringe_dedisperse(4096, 4096 + 320, 1, 10, 8, 64)
+    assert "overlap" in str(e.value)
+
+
 def test_probe_argument_checks():
     # host-side validation only: every call below is rejected before a launch
     with pytest.raises(F.FringeError):
