@@ -229,3 +229,88 @@ def test_dedisperse_pass_then_search_equals_shifted_search(delay_only):
     assert t_shift.tobytes() == t_pass.tobytes()
     assert c_shift.tobytes() == c_pass.tobytes()
     del buf
+
+
+def test_evn_full_scan_one_dm_trial():
+    """The full EVN-like scan searched with the shifts of DM 500 (the largest
+    trial of the benchmark's DM search, shifts up to 112 APs), checked
+    against the reference on the dedispersed data: 300 random windows, every
+    window within 1 % of the threshold, 300 above it, and the candidates."""
+    import os
+
+    import torch
+
+    import oracle.fringe_oracle as fo
+    import paper_2108_05602_amd as F
+    from paper_2108_05602_amd.dedisp import channel_freqs_hz, dm_shifts
+    spec = synth.c2()
+    p = synth.C2_PARAMS
+    print("case: full EVN-like scan, DM 500", flush=True)
+    v = spec.full(threads=min(16, os.cpu_count() or 1))
+    fv = v.reshape(spec.n_baselines, spec.n_ap, -1)
+    desc = spec.desc()
+    freqs = channel_freqs_hz(1.6e9, desc["n_if"], desc["n_chan"], desc["chan_width_hz"])
+    d = dm_shifts(500.0, freqs, desc["ap_seconds"]).astype(np.int32)
+    dmax = int(d.max())
+    dev = torch.from_numpy(v).to("cuda:0")
+    dd = to_device(d)
+    stream = torch.cuda.current_stream().cuda_stream
+    thr, pf, pt = p["snr_threshold"], p["pad_freq"], p["pad_time"]
+    t_all = spec.n_ap
+
+    def ref_rows(rows):
+        out = []
+        m_f = pf * spec.n_freq
+        for g in rows:
+            w, t0, b = int(g["window_ap"]), int(g["t_start"]), int(g["baseline"])
+            # the reference's dedispersion of a slice reaching dmax APs past the
+            # window (or the scan's end) equals the whole scan's on the window
+            sl = fv[b][None, t0:min(t_all, t0 + w + dmax)]
+            seg = fo.dedisperse(sl, np.minimum(d, sl.shape[1]))[0, :w]
+            r = fo.search_window(seg, 0, w, pf, pt)
+            m_t = pt * w
+            out.append((0, b, w, t0, r.k_rate, r.k_delay, r.amp, r.snr, r.energy,
+                        fo.signed_bin(r.k_delay, m_f) / (m_f * spec.chan_width_hz),
+                        fo.signed_bin(r.k_rate, m_t) / (m_t * spec.ap_seconds), r.margin))
+        return np.array(out, dtype=fo.TABLE_DTYPE)
+
+    def run(threshold):
+        plan = F.Plan([desc], p["window_aps"], pad_freq=pf, pad_time=pt, snr_threshold=threshold,
+                      max_candidates=1 << 20)
+        plan.set_shifts(0, dd.data_ptr())
+        plan.search([dev.data_ptr()], stream)
+        return plan
+
+    plan = run(thr)
+    cands = plan.candidates()
+    rng = np.random.default_rng(500)
+    n_win = plan.info()["n_windows"]
+    srows = plan.windows(np.sort(rng.choice(n_win, 300, replace=False)))
+    plan.close()
+    low = run(0.99 * thr)
+    above = low.candidates()
+    low.close()
+    band = above[above["snr"] <= 1.01 * thr]
+    high = above[above["snr"] > 1.01 * thr]
+    print(f"{len(cands)} candidates, {len(band)} in the 1 % band", flush=True)
+    assert len(band) < 8000
+
+    def dedispersed(s, b):   # only for the rare ambiguous windows
+        return fo.dedisperse(fv[b][None], d)[0]
+
+    compare_windows(srows, ref_rows(srows), dedispersed, pf, pt, "sample")
+    ref_b = ref_rows(band)
+    compare_windows(band, ref_b, dedispersed, pf, pt, "band")
+    pick = np.sort(rng.choice(len(high), min(300, len(high)), replace=False))
+    ref_h = ref_rows(high[pick])
+    compare_windows(high[pick], ref_h, dedispersed, pf, pt, "high")
+    assert np.all(ref_h["snr"] > thr)
+
+    def key(r):
+        return (int(r["baseline"]), int(r["window_ap"]), int(r["t_start"]))
+    got = [key(c) for c in cands]
+    assert got == sorted(got)
+    want = {key(r) for r in ref_b if r["snr"] > thr} | {key(r) for r in high}
+    amb = {key(r) for r in ref_b if abs(r["snr"] - thr) < 1e-4 * thr}
+    assert (set(got) ^ want) <= amb
+    del dev
