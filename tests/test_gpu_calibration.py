@@ -125,3 +125,87 @@ def test_null_gains_and_streaming():
         b = bmap[(int(r["baseline"]), int(r["window_ap"]), int(r["t_start"]))]
         for k in fields:
             assert r[k] == b[k], k
+
+
+def test_evn_full_scan_with_gains():
+    """The full EVN-like scan searched with per-baseline, per-channel gains
+    (instrumental delays per IF, phases, amplitude scales, 6 flagged
+    channels: the benchmark's calibrated leg), checked against the reference
+    on the calibrated data: 300 random windows, the threshold band, 300 windows
+    above it, and the candidates."""
+    import os
+
+    import torch
+
+    import oracle.fringe_oracle as fo
+    import paper_2108_05602_amd as F
+    spec = synth.c2()
+    p = synth.C2_PARAMS
+    print("case: full EVN-like scan with gains", flush=True)
+    v = spec.full(threads=min(16, os.cpu_count() or 1))
+    fv = v.reshape(spec.n_baselines, spec.n_ap, -1)
+    desc = spec.desc()
+    rng = np.random.default_rng(7)
+    f = np.arange(spec.n_freq)
+    tau = np.repeat(rng.uniform(-20e-9, 20e-9, (spec.n_baselines, desc["n_if"])), desc["n_chan"], 1)
+    phi = np.repeat(rng.uniform(0, 2 * np.pi, (spec.n_baselines, desc["n_if"])), desc["n_chan"], 1)
+    g = (rng.uniform(0.8, 1.2, (spec.n_baselines, spec.n_freq)) *
+         np.exp(-1j * (2 * np.pi * f[None, :] * desc["chan_width_hz"] * tau + phi))).astype(np.complex64)
+    g[:, 100:106] = 0
+    dev = torch.from_numpy(v).to("cuda:0")
+    dg = to_device(g)
+    stream = torch.cuda.current_stream().cuda_stream
+    thr, pf, pt = p["snr_threshold"], p["pad_freq"], p["pad_time"]
+
+    def ref_rows(rows):
+        out = []
+        m_f = pf * spec.n_freq
+        for r_ in rows:
+            w, t0, b = int(r_["window_ap"]), int(r_["t_start"]), int(r_["baseline"])
+            seg = fo.calibrate(fv[b][None, t0:t0 + w], g[b][None])[0]
+            r = fo.search_window(seg, 0, w, pf, pt)
+            m_t = pt * w
+            out.append((0, b, w, t0, r.k_rate, r.k_delay, r.amp, r.snr, r.energy,
+                        fo.signed_bin(r.k_delay, m_f) / (m_f * spec.chan_width_hz),
+                        fo.signed_bin(r.k_rate, m_t) / (m_t * spec.ap_seconds), r.margin))
+        return np.array(out, dtype=fo.TABLE_DTYPE)
+
+    def run(threshold):
+        plan = F.Plan([desc], p["window_aps"], pad_freq=pf, pad_time=pt, snr_threshold=threshold,
+                      max_candidates=1 << 20)
+        plan.set_gains(0, dg.data_ptr())
+        plan.search([dev.data_ptr()], stream)
+        return plan
+
+    plan = run(thr)
+    cands = plan.candidates()
+    rng2 = np.random.default_rng(701)
+    srows = plan.windows(np.sort(rng2.choice(plan.info()["n_windows"], 300, replace=False)))
+    plan.close()
+    low = run(0.99 * thr)
+    above = low.candidates()
+    low.close()
+    band = above[above["snr"] <= 1.01 * thr]
+    high = above[above["snr"] > 1.01 * thr]
+    print(f"{len(cands)} candidates, {len(band)} in the 1 % band", flush=True)
+    assert len(band) < 8000
+
+    def calibrated(s, b):   # only for the rare ambiguous windows
+        return fo.calibrate(fv[b][None], g[b][None])[0]
+
+    compare_windows(srows, ref_rows(srows), calibrated, pf, pt, "sample")
+    ref_b = ref_rows(band)
+    compare_windows(band, ref_b, calibrated, pf, pt, "band")
+    pick = np.sort(rng2.choice(len(high), min(300, len(high)), replace=False))
+    ref_h = ref_rows(high[pick])
+    compare_windows(high[pick], ref_h, calibrated, pf, pt, "high")
+    assert np.all(ref_h["snr"] > thr)
+
+    def key(r):
+        return (int(r["baseline"]), int(r["window_ap"]), int(r["t_start"]))
+    got = [key(c) for c in cands]
+    assert got == sorted(got)
+    want = {key(r) for r in ref_b if r["snr"] > thr} | {key(r) for r in high}
+    amb = {key(r) for r in ref_b if abs(r["snr"] - thr) < 1e-4 * thr}
+    assert (set(got) ^ want) <= amb
+    del dev
