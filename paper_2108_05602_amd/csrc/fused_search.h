@@ -71,7 +71,6 @@ struct LaneConsts {
   float s[6];    // stage signs
   bool rot2;     // stage D = 2 twiddle is -i (b lane with bit 0 set)
   int addr32;    // 4 * (lane ^ 32), the D = 32 exchange's source
-  float2 wfold;  // w_M^{c f'} of this lane's f'
 };
 
 template <int N>
@@ -151,7 +150,6 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   const int rev_addr = fl * 4;  // ds_bpermute source lane bitrev6(lane), in bytes
   fused::LaneConsts kc;
   const float2* tw = a.tw;
-  kc.wfold = ld_global(tw + ((cls * fl) & (M - 1)));
 #pragma unroll
   for (int st = 0; st < 6; ++st) {
     const int d = 1 << st;
@@ -204,15 +202,34 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
     for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h] + toff, 0);
   };
   const bool band_full = F == 64 * HFMAX;  // every lane in band for every fold
-  // calibration: the baseline's gains, read where they are applied (cache
-  // hits after the first AP; held in registers they would cost occupancy).
-  // Their buffer holds exactly the baseline's F gains, so lanes past the
-  // band read zeros.
+  // The fold's coefficients per lane l (f' = l) and h: the calibration gain
+  // of channel l + 64 h (1 without gains), the fold twiddle w_R^{c h} and
+  // the twiddle w_M^{c l} applied before the permute (the same value the
+  // permute's destination lane would apply), so a calibrated AP costs what
+  // an uncalibrated one does; |g|^2 scales the AP energies.  The gains'
+  // buffer holds exactly the baseline's F gains, so lanes past the band read
+  // zeros.
   const bool has_g = a.gains != nullptr;
-  const auto grs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float2*>(has_g ? a.gains + static_cast<int64_t>(b) * F : a.tw), static_cast<short>(0),
-      static_cast<int>(static_cast<uint32_t>(F) * sizeof(float2)), kBufferWord3);
-  const uint32_t lane8 = static_cast<uint32_t>(lane) * sizeof(float2);
+  const float2 wsrc = ld_global(tw + ((cls * lane) & (M - 1)));
+  float2 gw[HFMAX];
+  float gn[HFMAX];
+#pragma unroll
+  for (int h = 0; h < HFMAX; ++h) {
+    gw[h] = c_mul(wh[h], wsrc);
+    gn[h] = 1.f;
+  }
+  if (has_g) {
+    const auto grs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float2*>(a.gains + static_cast<int64_t>(b) * F), static_cast<short>(0),
+        static_cast<int>(static_cast<uint32_t>(F) * sizeof(float2)), kBufferWord3);
+    const uint32_t lane8 = static_cast<uint32_t>(lane) * sizeof(float2);
+#pragma unroll
+    for (int h = 0; h < HFMAX; ++h) {
+      const float2 g = ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0);
+      gw[h] = c_mul(g, c_mul(wh[h], wsrc));
+      gn[h] = c_norm(g);
+    }
+  }
   auto sample = [&](float2 x, int h, bool t_in) {
     const bool ok = t_in && lane_in[h];
     return make_float2(ok ? x.x : 0.f, ok ? x.y : 0.f);
@@ -300,27 +317,21 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
 #pragma unroll
             for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
           }
-          if (has_g) {
+          z[e] = c_mul(pre[fs][0], gw[0]);
 #pragma unroll
-            for (int h = 0; h < HFMAX; ++h)
-              pre[fs][h] = c_mul(pre[fs][h], ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0));
-          }
-          z[e] = pre[fs][0];
-#pragma unroll
-          for (int h = 1; h < HFMAX; ++h) z[e] = c_add(z[e], c_mul(pre[fs][h], wh[h]));
+          for (int h = 1; h < HFMAX; ++h) z[e] = c_add(z[e], c_mul(pre[fs][h], gw[h]));
           if (PT > 0 && cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
             float es = 0.f;
 #pragma unroll
-            for (int h = 0; h < HFMAX; ++h) es += c_norm(pre[fs][h]);
+            for (int h = 0; h < HFMAX; ++h) es = fmaf(gn[h], c_norm(pre[fs][h]), es);
             const float en = wave_sum_dpp(es);
             if (lane == 0 && te < own_hi) eb[te] = en;
           }
           load_ap(te + PD, pre[fs]);
           // lane l folded f = l; the transform wants f' = bitrev6(l) in lane l
-          z[e] = c_mul(make_float2(
+          z[e] = make_float2(
               __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z[e].x))),
-              __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z[e].y)))),
-              kc.wfold);
+              __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z[e].y))));
         });
         fused::xlane_dit(z, kc);
         static_for<0, G>([&](auto di) {
