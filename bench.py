@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "745469d649e1c9acf7980338f23923828264ec727c88f0220b52b79ff611e9ef",
-    "fetch_bytes": 7824574622,
-    "write_bytes": 1997904352,
+    "kernel_sha256": "691ddf232c98fbb579aaba4ca4746b1410197ccd48073a7688136a63488a3f29",
+    "fetch_bytes": 8814923817,
+    "write_bytes": 2044090272,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
