@@ -457,7 +457,8 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
     import torch
 
     import synth
-    from paper_2108_05602_amd.serve import FringeServer, poisson_schedule, run_schedule
+    from paper_2108_05602_amd.serve import (FringeBatchServer, FringeServer, poisson_schedule,
+                                            run_schedule)
     specs = synth.c4_subarrays(n_sub, n_chunks=n_distinct, chunk_ap=chunk_ap)
     dev, host = [], []
     for s in specs:
@@ -474,8 +475,8 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
            "chunks_per_point": per_sub * n_sub,
            "staging": f"first {n_distinct} chunks of each subarray's stream resident in HBM, replayed"}
 
-    def run(payloads, sched):
-        srv = FringeServer(subs, WS_C4, snr_threshold=4.5)
+    def run(payloads, sched, server=FringeServer):
+        srv = server(subs, WS_C4, snr_threshold=4.5)
         try:
             run_schedule(srv, [(0.0, s, k) for s in range(n_sub) for k in range(2)], payloads)
             st = run_schedule(srv, sched, payloads)
@@ -501,6 +502,16 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
     hp = run(ph, poisson_schedule(n_sub, per_sub, 0.5 * hs["chunks_per_s"] / n_sub, seed=7))
     hp["load"] = 0.5
     out["pinned_host"] = {"r_star_chunks_per_s": hs["chunks_per_s"], "point": hp}
+    # the same loads through one launch per step over all waiting subarrays
+    bsat = run(pd, [(0.0, s, k) for s in range(n_sub) for k in range(per_sub)], FringeBatchServer)
+    out["batched"] = {"r_star_chunks_per_s": bsat["chunks_per_s"], "saturated": bsat, "points": []}
+    for x in loads:
+        s = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)),
+                FringeBatchServer)
+        s["load"] = x
+        out["batched"]["points"].append(s)
+        log(f"serving (batched) load {x} of the per-subarray R*: p50 {s['p50_ms']:.3f} ms, "
+            f"p99 {s['p99_ms']:.3f} ms, {s['chunks_per_s']:.0f} chunks/s")
     return out
 
 

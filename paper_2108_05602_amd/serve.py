@@ -16,6 +16,12 @@ concurrently on their own streams.  A request's latency is the time from its
 arrival to its candidate list being on the host.  All search work runs in
 libfringe's kernels; this module only moves data into slots, launches and
 polls.
+
+FringeBatchServer is the other arrangement: one streaming plan whose scans
+are the subarrays, and one search call per step over the next chunk of every
+subarray that has one waiting, so one fused launch covers them all (small
+subarrays no longer leave the GPU half empty); a chunk that arrives during a
+step joins the next one.
 """
 
 from __future__ import annotations
@@ -206,3 +212,95 @@ def poisson_schedule(n_subs: int, n_chunks: int, rate_per_sub: float, seed: int 
         t = np.cumsum(rng.exponential(1.0 / rate_per_sub, n_chunks))
         sched += [(float(t[k]), s, k) for k in range(n_chunks)]
     return sched
+
+
+def stream_windows(desc: dict, window_aps, seq: int) -> int:
+    """Windows a streaming search reports for chunk seq of a subarray: those
+    whose last AP lies in the chunk (chunks of desc["n_ap"] APs)."""
+    c = int(desc["n_ap"])
+    lo, hi = seq * c, (seq + 1) * c          # last AP in [lo, hi)
+    n = 0
+    for w in window_aps:
+        st = max(1, w // 2)
+        first = max(0, lo - w + 1)           # start range [first, hi - w]
+        last = hi - w
+        if last < first:
+            continue
+        j0 = -(-first // st)
+        j1 = last // st
+        n += max(0, j1 - j0 + 1)
+    return n * int(desc["n_baselines"])
+
+
+class FringeBatchServer:
+    """Continuous-batching server with one launch per step over every
+    subarray that has a chunk waiting (the same API as FringeServer)."""
+
+    def __init__(self, subarrays: Sequence[dict], window_aps, *, pad_freq: int = 4,
+                 pad_time: int = 2, snr_threshold: float = 4.5, max_candidates: int = 1 << 18,
+                 device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.subs = [dict(s) for s in subarrays]
+        self.window_aps = list(window_aps)
+        self.plan = Plan(self.subs, window_aps, pad_freq=pad_freq, pad_time=pad_time,
+                         snr_threshold=snr_threshold, max_candidates=max_candidates,
+                         flags=FRINGE_STREAMING)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.slots = [torch.empty(s["n_baselines"] * s["n_ap"] * s["n_if"] * s["n_chan"],
+                                  dtype=torch.complex64, device=self.device) for s in self.subs]
+        self.queues = [collections.deque() for _ in self.subs]
+        self.batch: Optional[tuple] = None    # (requests, event, payload refs)
+        self.clock0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.clock0
+
+    def submit(self, req: Request) -> None:
+        self.queues[req.sub].append(req)
+
+    def inflight(self) -> int:
+        return len(self.batch[0]) if self.batch else 0
+
+    def poll(self) -> List[Result]:
+        out = []
+        if self.batch is not None and self.batch[1].query():
+            reqs = self.batch[0]
+            cands = self.plan.candidates()
+            done = self.now()
+            for r in reqs:
+                mine = cands[cands["scan"] == r.sub]
+                out.append(Result(r.sub, r.seq, r.arrival, done, mine,
+                                  stream_windows(self.subs[r.sub], self.window_aps, r.seq)))
+            self.batch = None
+        if self.batch is None:
+            self._launch()
+        return out
+
+    def close(self):
+        self.plan.close()
+
+    def _launch(self):
+        torch = self.torch
+        reqs = [q.popleft() for q in self.queues if q]
+        if not reqs:
+            return
+        st = self.stream
+        st.wait_stream(torch.cuda.current_stream())
+        ptrs: List[Optional[int]] = [None] * len(self.subs)
+        keep = []
+        for r in reqs:
+            pay = r.payload
+            if pay.device == self.device and pay.is_contiguous():
+                src = pay
+            else:
+                src = self.slots[r.sub][:pay.numel()].view(pay.shape)
+                with torch.cuda.stream(st):
+                    src.copy_(pay, non_blocking=True)
+            keep.append(src)
+            ptrs[r.sub] = src.data_ptr()
+        self.plan.search(ptrs, st.cuda_stream)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        self.batch = (reqs, ev, keep)

@@ -92,3 +92,29 @@ def test_admission_budget():
     assert one.max_inflight == 1 and len(one.results) == 3 * N_CHUNKS
     with pytest.raises(MemoryError):
         FringeServer(subs, WS, snr_threshold=4.5, hbm_budget_bytes=plan_bytes + chunk_bytes // 2)
+
+
+def test_batch_server_equals_per_subarray_server():
+    """One launch per step over every waiting subarray (FringeBatchServer)
+    gives every chunk the same candidates, bit for bit, and the same window
+    count as the per-subarray server."""
+    from paper_2108_05602_amd.serve import FringeBatchServer, poisson_schedule, run_schedule
+    specs, vis, payloads, subs = _setup()
+    print("case: batched server vs per-subarray server, 3 subarrays x 6 chunks", flush=True)
+    sched = poisson_schedule(3, N_CHUNKS, 2000.0, seed=3)
+    ref = {(r.sub, r.seq): r for r in _serve(subs, payloads, sched).results}
+    srv = FringeBatchServer(subs, WS, snr_threshold=4.5)
+    try:
+        got = run_schedule(srv, sched, payloads)
+    finally:
+        srv.close()
+    assert len(got.results) == 3 * N_CHUNKS
+    assert got.max_inflight >= 2
+    for r in got.results:
+        q = ref[(r.sub, r.seq)]
+        assert _fields(r.candidates) == _fields(q.candidates), (r.sub, r.seq)
+        assert r.n_windows == q.n_windows
+    # a subarray's chunks come back in order
+    for s in range(3):
+        seqs = [r.seq for r in got.results if r.sub == s]
+        assert seqs == sorted(seqs)
