@@ -244,8 +244,10 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     if (si.nwb_max > (int64_t(1) << 30) || nw > (int64_t(1) << 40) ||
         int64_t(data_len(si, sz.streaming)) > (int64_t(1) << 30))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: too many windows", s);
-    // the fused kernel addresses one baseline's samples with 32-bit offsets
-    if (sz.fused && (int64_t(data_len(si, sz.streaming)) + 1) * F * int64_t(sizeof(float2)) >= (int64_t(1) << 32))
+    // the fused kernel (every plan's windows of at most kFusedMaxWindow APs)
+    // addresses one baseline's samples with 32-bit offsets
+    if (sz.lv.W[0] <= kFusedMaxWindow &&
+        (int64_t(data_len(si, sz.streaming)) + 1) * F * int64_t(sizeof(float2)) >= (int64_t(1) << 32))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: a baseline holds 4 GiB or more of samples", s);
     si.full.win_off = win_off;
     si.grid_off = grid_off;
@@ -960,6 +962,17 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       da.pad_f = p->params.pad_freq;
       FRINGE_TIMED(0, launch_delay_fft(da, st), "delay transform launch");
 
+      // the windows of at most kFusedMaxWindow APs: the fused kernel, on the
+      // same slab (its own delay transform; same window numbering and
+      // partials); only the longer ones read the spectra written above
+      int l0 = 0;
+      while (l0 < z.lv.n && z.lv.W[l0] <= kFusedMaxWindow) ++l0;
+      if (l0 > 0 && hfus[ui].n_pairs > 0) {
+        FRINGE_TIMED(1, launch_fused(d_fus + ui, 1, fused_blocks(hfus[ui]), kernel_pad_t,
+                                     z.lv.W[l0 - 1], hfus[ui].hf, p->grid != nullptr, st),
+                     "fused search launch (short windows)");
+      }
+
       RateArgs ra{};
       ra.X = p->X;
       ra.part = p->part + u.part_off;
@@ -980,6 +993,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       ra.pad_t = si.pad_t;
       ra.nwb = int(c.nwb);
       ra.t_emit = c.t_emit;
+      ra.l0 = l0;
       for (int l = 0; l <= kMaxLevels; ++l) ra.lvl_off[l] = int(c.lvl_off[l]);
       for (int l = 0; l < kMaxLevels; ++l) ra.lvl_j0[l] = c.lvl_j0[l];
       ra.lv = z.lv;

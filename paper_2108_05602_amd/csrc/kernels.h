@@ -61,6 +61,7 @@ struct RateArgs {
   int nb, T, M, log_m, n_kb, chunk, n_chunks, w_max, buf_slots, pad_t;
   int nwb;
   int t_emit;          // windows must end at or after this AP (streaming)
+  int l0;              // first level searched here (shorter ones go to the fused kernel)
   int lvl_off[kMaxLevels + 1];
   int lvl_j0[kMaxLevels];
   LevelTable lv;

@@ -19,9 +19,10 @@
 // in flight.  The lane's rate key goes through a 64-lane DPP max and one
 // lane stores the bin-block's result (window_key.h).
 //
-// This kernel serves plans with windows longer than 64 APs; shorter ones use
-// the fused kernel (fused_search.h), which also does the delay transform and
-// keeps the history in registers.
+// This kernel serves the windows longer than 64 APs (levels l0 and up);
+// shorter ones go to the fused kernel (fused_search.h), which does its own
+// delay transform and keeps the history in registers, also in plans that
+// have long windows.
 #include "kernels.h"
 #include "window_key.h"
 
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(64) rate_peak_kernel(RateArgs a) {
       constexpr int i = decltype(ii)::value;
       if (i < nqn) pre[i] = xcol[static_cast<int64_t>(tn + i) * M];
     });
-    for (int li = 0; li < a.lv.n; ++li) {
+    for (int li = a.l0; li < a.lv.n; ++li) {
       const int W = a.lv.W[li];
       const int s = a.lv.s[li];
       const int lo = max(max(tb, a.t_emit) - W + 1, own_lo);

@@ -125,6 +125,13 @@ def test_validation_errors():
     assert _code(lambda: chk([dict(ok, n_if=1, n_chan=8)], [4], pad_freq=4)) == B.FRINGE_E_UNSUPPORTED
     assert _code(lambda: chk([dict(ok, n_if=16, n_chan=128)], [4], pad_freq=4)) == B.FRINGE_E_UNSUPPORTED
     assert "power of two" in F.fringe_last_error() or F.fringe_last_error()
+    # a baseline of 4 GiB or more of samples: not with windows of at most 64
+    # APs (the fused kernel's 32-bit offsets serve them, also in plans that
+    # have longer windows); windows longer than 64 APs alone are fine
+    big = dict(ok, n_baselines=1, n_ap=600000, n_if=16, n_chan=64)
+    assert _code(lambda: chk([big], [64, 128])) == B.FRINGE_E_UNSUPPORTED
+    assert "4 GiB" in F.fringe_last_error()
+    assert chk([big], [128])["n_windows"] > 0
 
 
 def test_budget():
