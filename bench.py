@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "691ddf232c98fbb579aaba4ca4746b1410197ccd48073a7688136a63488a3f29",
-    "fetch_bytes": 8814923817,
-    "write_bytes": 2044090272,
+    "kernel_sha256": "f437ffe56b09392e070ed2870b720cfca6fe23bc259b2099c333087d2a97ac90",
+    "fetch_bytes": 8757093670,
+    "write_bytes": 2047807898,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
