@@ -35,7 +35,7 @@ namespace fringe {
 namespace {
 
 constexpr int kQ = 8;                 // APs per load batch
-constexpr int kWaves = 4;             // waves per work group
+constexpr int kWaves = 8;             // waves per work group
 constexpr int kQW = kQ / kWaves;      // APs each wave loads per batch
 constexpr int kRing = kMaxWindowAp;   // ring slots per bin (the window length)
 constexpr int kLogRing = 7;
@@ -47,7 +47,7 @@ typedef __attribute__((address_space(3))) volatile uint64_t LdsU64;
 
 template <int PT, bool DUMP>
 // Two work groups per CU (the ring takes 64 KB of LDS): two waves per SIMD.
-__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(DUMP ? 2 : 4)))
 rate_peak_kernel(RateArgs a) {
   extern __shared__ float2 ring[];  // [kRing][64], then kWaves uint64 partials
   uint64_t* wave_pk = reinterpret_cast<uint64_t*>(ring + kRing * kBinsPerWave);
