@@ -102,6 +102,8 @@ SHAPES = [
     (1, 300, 8, 8, [1, 128], 4, 2),                    # W = 128 (S = 8), T not a multiple
     (2, 1100, 4, 16, [1, 2, 4, 8, 16, 32], 4, 2),      # several time chunks per wave
     (1, 40, 32, 32, [2, 4, 8], 4, 1),                  # M_f = 4096, pad_time 1
+    (2, 1400, 4, 16, [64, 128], 4, 1),                 # W = 128 at pad_time 1, two time chunks
+    (1, 2200, 2, 32, [128], 4, 2),                     # W = 128 alone, three chunks, ragged tail
 ]
 
 
