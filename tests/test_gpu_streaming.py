@@ -61,7 +61,8 @@ def _streamed(desc, vis, ws, thr, chunk):
 @pytest.mark.parametrize("ws,chunks", [
     ([1, 2, 4, 8, 16, 32], [976, 244, 61, 1000, 7]),
     ([1, 4, 64], [300, 61]),
-], ids=["fused", "two-pass"])
+    ([1, 4, 64, 128], [300, 61]),
+], ids=["fused", "fused-64", "two-pass"])
 def test_stream_equals_batch(ws, chunks):
     spec = synth.evn_scan(4021, 3, 2928, 8, 32, 1.024e-3, 16e6, 3, width_max=32, n_tones=1)
     vis = spec.full()
