@@ -46,7 +46,9 @@ static_assert(kQ % kWaves == 0 && (kRing / 2) % kQ == 0, "batches tile the strid
 typedef __attribute__((address_space(3))) volatile uint64_t LdsU64;
 
 template <int PT, bool DUMP>
-// Two work groups per CU (the ring takes 64 KB of LDS): two waves per SIMD.
+// Two work groups per CU (the ring takes 64 KB of LDS): four waves per SIMD,
+// registers capped to fit; the grid-dump variant (tests) keeps two, so as not
+// to spill.
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(DUMP ? 2 : 4)))
 rate_peak_kernel(RateArgs a) {
   extern __shared__ float2 ring[];  // [kRing][64], then kWaves uint64 partials
