@@ -1,17 +1,28 @@
 #!/usr/bin/env python3
 """Fringe-search benchmark on one MI355X.
 
-Workload: the EVN-like single scan (10 stations = 45 baselines, 58600 APs of
-1.024 ms = 60 s, 8 IF x 32 channels of 0.5 MHz, Gaussian noise, 20 pulses,
-10 narrowband RFI tones), windows of 1, 2, 4, 8, 16, 32 APs at 50 % overlap,
-4x delay padding, 2x rate padding, threshold 4.5: 7,745,940 windows.
+Headline workload: the batched uneven set of 200 scans (10-120 s of
+1.024 ms APs, 3-12 stations = 3-66 baselines, 8 or 16 IF x 16/32/64
+channels of 16 MHz IFs, pulses one per 3 s and narrowband RFI tones one per
+6 s), windows of 1-64 APs at 50 % overlap, 4x delay / 2x rate padding,
+threshold 4.5: about 1.1 G windows over 1.3 TB of visibilities, more than
+the GPU holds.  The scans are generated on the device in waves of at most
+--wave-gb of visibilities; each wave is one plan (one fused launch per fold
+class of its bands), searched W times untimed and then K times timed.  A
+step is one search of every wave (plus each search's candidate copy to the
+host): ms_per_step is the sum over the waves of their timed search, each
+bracketed by device synchronisations, averaged over the K steps; the
+generation of a wave is outside every timed region, its data already in HBM
+when each of its searches starts.
 
-A step is one full search of the resident cube (delay transform, rate
-transform + peak, finalize, candidate compaction) plus the copy of the
-candidate list to the host.  Prints one JSON line on stdout; progress goes
-to stderr.
+Further keys: the EVN-like single scan (45 baselines x 58,600 APs x 256
+channels, windows 1-32 APs) with its calibrated, delay-only, DM-search,
+plain-path, graph and serving legs; the large dense scan (66 baselines x
+117,200 APs x 1,024 channels, windows 1-128 APs, 63.4 GB, generated on the
+device); roof probes; the CPU reference on a bounded sample of the
+headline workload.  Prints one JSON line on stdout; progress goes to stderr.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--only c3|c2]
 """
 
 from __future__ import annotations
@@ -517,40 +528,228 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
 
 WS_C4 = [1, 2, 4, 8, 16, 32]
 
+C3_WORKLOAD = ("Batched uneven: 200 scans of 10-120 s (1.024 ms APs), 3-12 stations (3-66 baselines), "
+               "8 or 16 IF x {16,32,64} chan complex64 (16 MHz IFs), pulses and narrowband RFI, "
+               "windows 1-64 AP at 50% overlap, 4x delay / 2x rate padding, SNR > 4.5; generated on "
+               "the device in HBM-budgeted waves, one plan per wave")
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--stations", type=int, default=10, help="(smaller values: quick check only)")
-    ap.add_argument("--n-ap", type=int, default=58600, help="(smaller values: quick check only)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="before the search, copy a MIB-MiB device buffer once (a plain copy "
-                         "kernel of known size for scaling hardware byte counters)")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
 
+def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None):
+    """The batched uneven workload: per wave, generate its scans on the
+    device, build one plan, search it `warmup` times untimed and `steps`
+    times timed (each search with its candidate copy, bracketed by device
+    synchronisations).  Step k's time is the sum over the waves of their
+    k-th timed search.  cpu_sample, if a list, receives host copies of a
+    few baselines' first APs from one scan of each band width (the CPU
+    reference's sample of this workload)."""
     import torch
 
     import paper_2108_05602_amd as F
     import synth
+    from synth import device as sd
+    specs = synth.c3(n_scans=n_scans)
+    p = synth.C3_PARAMS
+    groups = sd.waves(specs, int(wave_gb * 1e9))
+    st = torch.cuda.current_stream()
+    step_s = [0.0] * steps
+    fused_ms = fin_ms = comp_ms = 0.0
+    fused_n = 0
+    n_windows = n_cands = cube = 0
+    fl = [0.0, 0.0, 0.0]
+    part_bytes = e_bytes = 0
+    sampled_f = set()
+    waves_out = []
+    log(f"C3: {len(specs)} scans, {sum(s.nbytes() for s in specs) / 1e12:.3f} TB in "
+        f"{len(groups)} waves of <= {wave_gb} GB")
+    for wi, idx in enumerate(groups):
+        t0 = time.perf_counter()
+        tens = [sd.generate(specs[i]) for i in idx]
+        torch.cuda.synchronize()
+        gen_s = time.perf_counter() - t0
+        descs = [specs[i].desc() for i in idx]
+        with F.Plan(descs, p["window_aps"], pad_freq=p["pad_freq"], pad_time=p["pad_time"],
+                    snr_threshold=p["snr_threshold"], max_candidates=1 << 22,
+                    flags=F.FRINGE_PROFILE) as plan:
+            ptrs = [t.data_ptr() for t in tens]
+            for _ in range(warmup):
+                plan.search(ptrs, st.cuda_stream)
+                plan.candidates()
+            wt = []
+            for k in range(steps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                plan.search(ptrs, st.cuda_stream)
+                c = plan.candidates()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                step_s[k] += dt
+                wt.append(dt)
+                pr = plan.profile()
+                fused_ms += pr["rate_ms"]
+                fused_n += pr["rate_launches"]
+                fin_ms += pr["finalize_ms"]
+                comp_ms += pr["compact_ms"]
+            nw = plan.info()["n_windows"]
+        n_windows += nw
+        n_cands += len(c)
+        wb = 0
+        for i in idx:
+            sp = specs[i]
+            d_, r_, k_ = algorithmic_flops(sp.n_baselines, sp.n_ap, sp.n_freq, p["window_aps"],
+                                           p["pad_freq"], p["pad_time"])
+            fl[0] += d_
+            fl[1] += r_
+            fl[2] += k_
+            wb += sp.nbytes()
+            n_cls = p["pad_freq"] * sp.n_freq // 64
+            nw_s = sum(n for _, _, n in window_levels(sp.n_ap, p["window_aps"])) * sp.n_baselines
+            part_bytes += nw_s * n_cls * 8
+            e_bytes += sp.n_baselines * sp.n_ap * 4
+        cube += wb
+        if cpu_sample is not None:
+            for j, i in enumerate(idx):
+                sp = specs[i]
+                if sp.n_freq in sampled_f:
+                    continue
+                sampled_f.add(sp.n_freq)
+                t_n = min(4096, sp.n_ap)
+                for b in range(min(3, sp.n_baselines)):
+                    cpu_sample.append((i, b, sp, tens[j][b, :t_n].reshape(t_n, -1).cpu().numpy()))
+        waves_out.append({"scans": len(idx), "gb": wb / 1e9, "windows": nw, "candidates": int(len(c)),
+                          "gen_s": gen_s, "search_ms_median": float(np.median(wt)) * 1e3})
+        log(f"C3 wave {wi}: {len(idx)} scans, {wb / 1e9:.1f} GB, {nw} windows, generated in "
+            f"{gen_s:.1f} s, search {np.median(wt) * 1e3:.1f} ms, {len(c)} candidates")
+        del tens
+        torch.cuda.empty_cache()
+    ms = float(np.mean(step_s)) * 1e3
+    flops_step = fl[0] + fl[1] + fl[2]
+    launches_per_step = fused_n / steps
+    avg_launch_s = fused_ms / max(1, fused_n) / 1e3
+    flops_per_launch = flops_step / launches_per_step
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    return {
+        "value": n_windows / (ms / 1e3), "ms_per_step": ms, "windows": n_windows, "cube_bytes": cube,
+        "candidates": n_cands, "waves": waves_out, "scans": len(specs),
+        "roofline": {
+            "bound": "alu",
+            "kernel": "fused_search_kernel (delay FFT + rate FFT + |G|^2 peak; one launch per wave "
+                      "and fold class)",
+            "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "algorithmic_flops_per_launch": flops_per_launch,
+            "algorithmic_bytes_per_launch": (cube + part_bytes + e_bytes) / launches_per_step,
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "launches_per_step": launches_per_step,
+        },
+        "kernel_ms_per_step": {"fused_ms": fused_ms / steps, "finalize_ms": fin_ms / steps,
+                               "compact_ms": comp_ms / steps},
+        "tflops_algorithmic_step": flops_step / (ms / 1e3) / 1e12,
+        "hbm_gbs_algorithmic": cube / (ms / 1e3) / 1e9,
+    }
 
+
+def cpu_baseline_c3(sample, params):
+    """The CPU reference, as it stands, on the headline workload's sample:
+    baselines 0-2 x the first 4,096 APs of the first scan of each band
+    width (copied from the device-generated cubes), every window length;
+    with numpy's BLAS pool (the reported value) and, on the narrowest of
+    them, one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import fringe_oracle as fo
+
+    def run(items):
+        n = 0
+        t0 = time.perf_counter()
+        for i, b, sp, x in items:
+            n += len(fo.search_baseline(x, params["window_aps"], params["pad_freq"],
+                                        params["pad_time"], sp.ap_seconds, sp.chan_width_hz,
+                                        scan=i, baseline=b))
+        return n, time.perf_counter() - t0
+
+    n, dt = run(sample)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        n1, dt1 = run(sample[:1])
+    desc = "; ".join(f"scan {i} (F = {sp.n_freq}) baseline {b} x APs 0-{x.shape[0] - 1}"
+                     for i, b, sp, x in sample)
+    return {"value": n / dt, "unit": "windows/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{desc}: {n} windows in {dt:.1f} s",
+            "one_thread": {"value": n1 / dt1, "sample": f"the first of these: {n1} windows in "
+                                                        f"{dt1:.1f} s"}}
+
+
+def large_dense_leg(steps=2):
+    """The large dense scan (66 BL x 117,200 AP x 1,024 chan, 63.4 GB,
+    windows 1-128 APs), generated on the device: windows/s of full
+    searches and each kernel's time and algorithmic rate."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    import synth
+    from synth import device as sd
+    spec = synth.c5()
+    p = synth.C5_PARAMS
+    t0 = time.perf_counter()
+    dev = sd.generate(spec)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    st = torch.cuda.current_stream()
+    with F.Plan([spec.desc()], p["window_aps"], pad_freq=p["pad_freq"], pad_time=p["pad_time"],
+                snr_threshold=p["snr_threshold"], max_candidates=1 << 22,
+                flags=F.FRINGE_PROFILE) as plan:
+        plan.search([dev.data_ptr()], st.cuda_stream)
+        plan.candidates()
+        ts, prof = [], []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan.search([dev.data_ptr()], st.cuda_stream)
+            c = plan.candidates()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+            prof.append(plan.profile())
+        n_win = plan.info()["n_windows"]
+        slab = plan.info()["slab_baselines"]
+    del dev
+    torch.cuda.empty_cache()
+    dt = float(np.mean(ts))
+    pr = {k: float(np.mean([q[k] for q in prof])) for k in prof[0]}
+    m_f = p["pad_freq"] * spec.n_freq
+    nb, T = spec.n_baselines, spec.n_ap
+    short = [w for w in p["window_aps"] if w <= 64]
+    long_ = [w for w in p["window_aps"] if w > 64]
+    d_fl, r_s, k_s = algorithmic_flops(nb, T, spec.n_freq, short, p["pad_freq"], p["pad_time"])
+    _, r_l, k_l = algorithmic_flops(nb, T, spec.n_freq, long_, p["pad_freq"], p["pad_time"])
+    total = d_fl + r_s + k_s + r_l + k_l
+    return {"workload": "large dense scan: 66 BL x 117200 AP (0.512 ms) x 16 IF x 64 chan complex64, "
+                        "windows 1-128 AP, 63.4 GB, generated on the device",
+            "windows": n_win, "windows_per_s": n_win / dt, "ms_per_search": dt * 1e3,
+            "generate_s": gen_s, "slab_baselines": slab, "candidates": int(len(c)),
+            "kernel_ms": {"delay_fft": pr["delay_ms"], "fused_and_rate": pr["rate_ms"],
+                          "finalize": pr["finalize_ms"], "compact": pr["compact_ms"]},
+            "launches": {"delay_fft": pr["delay_launches"], "fused_and_rate": pr["rate_launches"]},
+            "tflops_algorithmic": total / dt / 1e12,
+            "frac_fp32_peak": total / dt / 1e12 / PEAK_FP32_TFLOPS,
+            "delay_fft_hbm_gbs": (nb * T * (spec.n_freq + m_f) * 8) / (pr["delay_ms"] * 1e-3) / 1e9
+            if pr["delay_ms"] > 0 else None}
+
+
+def evn_scan_legs(args, out):
+    """The EVN-like single scan: its own search (5 steps), then the legs
+    that compare paths on it."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    import synth
     params = dict(synth.C2_PARAMS)
     spec = synth.c2(n_stations=args.stations, n_ap=args.n_ap)
     full = args.stations == 10 and args.n_ap == 58600
-    log(f"generating {spec.n_baselines} BL x {spec.n_ap} AP x {spec.n_freq} ch "
+    log(f"EVN scan: generating {spec.n_baselines} BL x {spec.n_ap} AP x {spec.n_freq} ch "
         f"({spec.nbytes() / 1e9:.2f} GB)")
-    t0 = time.perf_counter()
     v = spec.full(threads=min(16, os.cpu_count() or 1))
-    log(f"generated in {time.perf_counter() - t0:.1f} s; copying to cuda:0")
     dev = torch.from_numpy(v).to("cuda:0")
     del v
     torch.cuda.synchronize()
@@ -563,137 +762,166 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {n} bytes read, {n} bytes written")
         del src, dst
-    desc = spec.desc()
-    plan = F.Plan([desc], params["window_aps"], pad_freq=params["pad_freq"],
+    steps = args.evn_steps
+    plan = F.Plan([spec.desc()], params["window_aps"], pad_freq=params["pad_freq"],
                   pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],
                   max_candidates=1 << 20, flags=F.FRINGE_PROFILE)
-    info = plan.info()
-    n_win = info["n_windows"]
+    n_win = plan.info()["n_windows"]
     stream = torch.cuda.current_stream()
-    log(f"plan: {n_win} windows, {info['device_bytes'] / 1e9:.2f} GB device, "
-        f"{info['slab_baselines']} baselines per slab")
-    for i in range(args.warmup):
+    for _ in range(2):
         plan.search([dev.data_ptr()], stream.cuda_stream)
-        c = plan.candidates()
-        log(f"warmup {i}: {len(c)} candidates")
+        plan.candidates()
     torch.cuda.synchronize()
-    kern = {"delay_ms": 0.0, "rate_ms": 0.0, "finalize_ms": 0.0, "compact_ms": 0.0,
-            "rate_launches": 0}
+    kern = {"delay_ms": 0.0, "rate_ms": 0.0, "finalize_ms": 0.0, "compact_ms": 0.0}
+    launches = 0
     t_wall = time.perf_counter()
-    for i in range(args.steps):
+    for _ in range(steps):
         plan.search([dev.data_ptr()], stream.cuda_stream)
         cands = plan.candidates()
         prof = plan.profile()
-        for k in ("delay_ms", "rate_ms", "finalize_ms", "compact_ms"):
+        for k in kern:
             kern[k] += prof[k]
-        kern["rate_launches"] += prof["rate_launches"]
+        launches += prof["rate_launches"]
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms_per_step = wall / args.steps * 1e3
-    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {len(cands)} candidates")
-    per_step = {k: kern[k] / args.steps for k in ("delay_ms", "rate_ms", "finalize_ms", "compact_ms")}
-    log("kernel ms/step " + json.dumps({k: round(x, 3) for k, x in per_step.items()}))
-
+    ms = (time.perf_counter() - t_wall) / steps * 1e3
+    plan.close()
     d_fl, r_fl, p_fl = algorithmic_flops(spec.n_baselines, spec.n_ap, spec.n_freq,
-                                         params["window_aps"], params["pad_freq"],
-                                         params["pad_time"])
-    # dominant kernel: the fused search kernel does the delay transform, rate
-    # transform and peak; on the two-pass path the rate kernel does the last two
-    fused = kern["delay_ms"] == 0.0
-    launches = kern["rate_launches"]
+                                         params["window_aps"], params["pad_freq"], params["pad_time"])
     avg_launch_s = kern["rate_ms"] / max(1, launches) / 1e3
-    kernel_flops = (d_fl if fused else 0.0) + r_fl + p_fl
-    flops_per_launch = kernel_flops * args.steps / max(1, launches)
+    flops_per_launch = (d_fl + r_fl + p_fl) * steps / max(1, launches)
     achieved = flops_per_launch / avg_launch_s / 1e12
-    cube_bytes = spec.nbytes()
-    info_kb = params["pad_freq"] * spec.n_freq // 64   # delay-bin classes of 64 bins
+    n_cls = params["pad_freq"] * spec.n_freq // 64
     traffic = None
-    if fused and full and kernel_hash() == MEASURED_TRAFFIC["kernel_sha256"]:
+    if full and kernel_hash() == MEASURED_TRAFFIC["kernel_sha256"]:
         traffic = MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]
-    out = {
-        "metric": "fringe-fit windows/s + HBM GB/s vs roofline; p50/p99 window latency",
-        "value": n_win / (ms_per_step / 1e3),
-        "unit": "windows/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": ("EVN-like single scan: 45 baselines x 58600 AP x 8 IF x 32 chan complex64, "
-                         "windows 1-32 AP at 50% overlap, 4x delay / 2x rate padding, SNR > 4.5")
-            if full else f"reduced EVN-like scan: {spec.n_baselines} BL x {spec.n_ap} AP (quick check)",
-            "windows": n_win,
-            "cube_bytes": cube_bytes,
-            "parallelism": "single GPU",
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": ("fused_search_kernel (delay FFT + rate FFT + |G|^2 peak)" if fused
-                       else "rate_peak_kernel (rate FFT + |G|^2 peak)"),
-            "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "algorithmic_flops_per_launch": flops_per_launch,
-            # visibilities in, one 8-byte partial peak per window and delay-bin
-            # class out, one 4-byte energy per AP and baseline out
-            "algorithmic_bytes_per_launch": (cube_bytes + n_win * info_kb * 8 +
-                                             spec.n_baselines * spec.n_ap * 4) if fused else None,
-            "avg_launch_ms": avg_launch_s * 1e3,
-            "launches_per_step": launches / args.steps,
-        },
-        "hbm_gbs_algorithmic": cube_bytes / (ms_per_step / 1e3) / 1e9,
-        "hbm_frac_algorithmic": cube_bytes / (ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBS,
-        "tflops_algorithmic_step": (d_fl + r_fl + p_fl) / (ms_per_step / 1e3) / 1e12,
-        "kernel_ms_per_step": per_step,
-        "candidates": int(len(cands)),
-    }
+    ev = {"workload": ("EVN-like single scan: 45 baselines x 58600 AP x 8 IF x 32 chan complex64, "
+                       "windows 1-32 AP at 50% overlap, 4x delay / 2x rate padding, SNR > 4.5")
+          if full else f"reduced EVN-like scan: {spec.n_baselines} BL x {spec.n_ap} AP (quick check)",
+          "windows": n_win, "cube_bytes": spec.nbytes(), "windows_per_s": n_win / (ms / 1e3),
+          "ms_per_step": ms, "steps": steps,
+          "kernel_ms_per_step": {k: x / steps for k, x in kern.items()},
+          "candidates": int(len(cands)),
+          "roofline": {"bound": "alu", "kernel": "fused_search_kernel<2, 5, 4>",
+                       "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                       "algorithmic_flops_per_launch": flops_per_launch,
+                       "algorithmic_bytes_per_launch": spec.nbytes() + n_win * n_cls * 8 +
+                       spec.n_baselines * spec.n_ap * 4,
+                       "avg_launch_ms": avg_launch_s * 1e3}}
+    out["evn_scan"] = ev
+    log("EVN scan: " + json.dumps({k: ev[k] for k in ("windows_per_s", "ms_per_step")}))
     if not args.no_plain:
         log("timing the one-window-per-launch path against the batched path")
-        out["plain_vs_batched"] = plain_vs_batched(dev, spec, params)
-        log("plain vs batched: " + json.dumps(out["plain_vs_batched"]))
+        ev["plain_vs_batched"] = plain_vs_batched(dev, spec, params)
+        log("plain vs batched: " + json.dumps(ev["plain_vs_batched"]))
     log("single pulses from the candidates (host matching and localization)")
-    out["single_pulses"] = single_pulse_leg(cands, spec)
-    log("single pulses: " + json.dumps(out["single_pulses"]))
+    ev["single_pulses"] = single_pulse_leg(cands, spec)
     log("calibrated search of the same scan")
-    out["calibrated"] = calibrated_leg(dev, spec, params)
-    log("calibrated: " + json.dumps(out["calibrated"]))
+    ev["calibrated"] = calibrated_leg(dev, spec, params)
     log("delay-only search of the same scan")
-    out["delay_only"] = delay_only_leg(dev, spec, params)
-    log("delay-only: " + json.dumps(out["delay_only"]))
+    ev["delay_only"] = delay_only_leg(dev, spec, params)
+    log("delay-only: " + json.dumps(ev["delay_only"]))
     log("DM search: 20 dedispersed trials of the same scan in one plan")
-    out["dm_search"] = dm_search_leg(dev, spec, params)
-    log("DM search: " + json.dumps(out["dm_search"]))
+    ev["dm_search"] = dm_search_leg(dev, spec, params)
     log("DM search, delay-only (the paper's dedispersed search)")
-    out["dm_search_delay_only"] = dm_search_leg(dev, spec, params, delay_only=True)
-    log("DM search, delay-only: " + json.dumps(out["dm_search_delay_only"]))
+    ev["dm_search_delay_only"] = dm_search_leg(dev, spec, params, delay_only=True)
     log("DM search, delay-only, by the dedispersion pass")
-    out["dm_search_delay_only_pass"] = dm_prepass_leg(dev, spec, params)
-    log("DM search, delay-only, pass: " + json.dumps(out["dm_search_delay_only_pass"]))
+    ev["dm_search_delay_only_pass"] = dm_prepass_leg(dev, spec, params)
     log("small batch plan: eager launches vs graph replay")
-    out["graph_vs_eager"] = graph_vs_eager(dev, spec, params)
-    log("graph vs eager: " + json.dumps(out["graph_vs_eager"]))
-    if not args.no_serving:
-        log("serving: streamed subarrays, saturated rate and Poisson loads")
-        out["serving"] = serving_latency()
-        pts = out["serving"]["points"]
-        out["p50_ms"] = next(p["p50_ms"] for p in pts if p["load"] == 1.0)
-        out["p99_ms"] = next(p["p99_ms"] for p in pts if p["load"] == 1.0)
-    log("roof probes: FP32 FMA loop and HBM copy")
-    out["roofs_measured"] = roof_probes()
-    out["roofline"]["frac_of_measured_peak"] = achieved / out["roofs_measured"]["fp32_fma_tflops"]
-    log("roofs: " + json.dumps(out["roofs_measured"]))
+    ev["graph_vs_eager"] = graph_vs_eager(dev, spec, params)
     if not args.no_cpu_baseline:
-        log("timing the CPU reference on its sample")
-        out["cpu_baseline"] = cpu_baseline(spec, params)
-    plan.close()
+        log("timing the CPU reference on the EVN scan's sample")
+        ev["cpu_baseline"] = cpu_baseline(spec, params)
+    del dev
+    torch.cuda.empty_cache()
+    return ev
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--only", choices=["c3", "c2"], default=None,
+                    help="run only the headline (c3) or only the EVN-scan legs (c2)")
+    ap.add_argument("--wave-gb", type=float, default=150.0,
+                    help="visibilities per wave of the headline workload")
+    ap.add_argument("--c3-scans", type=int, default=200, help="(fewer: quick check only)")
+    ap.add_argument("--evn-steps", type=int, default=5)
+    ap.add_argument("--stations", type=int, default=10, help="EVN scan (smaller: quick check only)")
+    ap.add_argument("--n-ap", type=int, default=58600, help="EVN scan (smaller: quick check only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the EVN search, copy a MIB-MiB device buffer once (a plain copy "
+                         "kernel of known size for scaling hardware byte counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2108_05602_amd as F
+    import synth
+    F.load()
+    torch.cuda.init()
+
+    out = {"metric": "fringe-fit windows/s + HBM GB/s vs roofline; p50/p99 window latency",
+           "unit": "windows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic"}
+    sample = []
+    if args.only != "c2":
+        h = c3_headline(args.steps, args.warmup, args.wave_gb, n_scans=args.c3_scans,
+                        cpu_sample=None if args.no_cpu_baseline else sample)
+        out["value"] = h["value"]
+        out["ms_per_step"] = h["ms_per_step"]
+        out["config"] = {"workload": C3_WORKLOAD if args.c3_scans == 200 else
+                         f"reduced batched uneven set: first {args.c3_scans} scans (quick check)",
+                         "scans": h["scans"], "windows": h["windows"], "cube_bytes": h["cube_bytes"],
+                         "waves": len(h["waves"]), "parallelism": "single GPU"}
+        out["roofline"] = h["roofline"]
+        for k in ("kernel_ms_per_step", "tflops_algorithmic_step", "hbm_gbs_algorithmic",
+                  "candidates", "waves"):
+            out[k] = h[k]
+        out["hbm_frac_algorithmic"] = h["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
+        log(f"C3 headline: {h['value'] / 1e6:.1f} M windows/s, {h['ms_per_step']:.1f} ms per step, "
+            f"fused kernels {h['roofline']['achieved']:.1f} TFLOP/s")
+    if args.only != "c3":
+        ev = evn_scan_legs(args, out)
+        if args.only == "c2":
+            out["value"] = ev["windows_per_s"]
+            out["ms_per_step"] = ev["ms_per_step"]
+            out["steps"] = ev["steps"]
+            out["config"] = {"workload": ev["workload"], "windows": ev["windows"],
+                             "cube_bytes": ev["cube_bytes"], "parallelism": "single GPU"}
+            out["roofline"] = ev["roofline"]
+        if not args.no_large:
+            log("large dense scan (generated on the device)")
+            out["large_dense"] = large_dense_leg()
+            log("large dense: " + json.dumps(out["large_dense"]))
+        if not args.no_serving:
+            log("serving: streamed subarrays, saturated rate and Poisson loads")
+            out["serving"] = serving_latency()
+            pts = out["serving"]["points"]
+            out["p50_ms"] = next(p["p50_ms"] for p in pts if p["load"] == 1.0)
+            out["p99_ms"] = next(p["p99_ms"] for p in pts if p["load"] == 1.0)
+        log("roof probes: FP32 FMA loop and HBM copy")
+        out["roofs_measured"] = roof_probes()
+        out["roofline"]["frac_of_measured_peak"] = (out["roofline"]["achieved"] /
+                                                    out["roofs_measured"]["fp32_fma_tflops"])
+        log("roofs: " + json.dumps(out["roofs_measured"]))
+    if sample:
+        log("timing the CPU reference on the headline workload's sample")
+        out["cpu_baseline"] = cpu_baseline_c3(sample, synth.C3_PARAMS)
+        log("cpu baseline: " + json.dumps(out["cpu_baseline"]))
+    elif args.only == "c2" and "cpu_baseline" in out.get("evn_scan", {}):
+        out["cpu_baseline"] = out["evn_scan"]["cpu_baseline"]
     print(json.dumps(out), flush=True)
 
 

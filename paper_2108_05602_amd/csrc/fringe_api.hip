@@ -104,12 +104,16 @@ struct ScanInfo {
 // launch, with its place in the work buffers.
 struct Unit {
   int scan, b0, nb;
+  int fc;                             // fold class of the scan's band (fused kernel)
   uint64_t e_off, part_off;           // element offsets in the energy / peak buffers
 };
 
-// Units [u0, u1) share one fused launch and one finalize launch.
+// Units [u0, u1) share one fused launch and one finalize launch; every unit
+// of a group has the group's fold class, so each launch runs the kernel
+// instantiation its own bands need.
 struct Group {
   int u0, u1;
+  int fc;
 };
 
 constexpr int64_t kMaxPlainWindows = int64_t(1) << 21;
@@ -249,6 +253,11 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     if (sz.lv.W[0] <= kFusedMaxWindow &&
         (int64_t(data_len(si, sz.streaming)) + 1) * F * int64_t(sizeof(float2)) >= (int64_t(1) << 32))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: a baseline holds 4 GiB or more of samples", s);
+    // ... and folds at most 16 x 64 channels per lane
+    if (sz.lv.W[0] <= kFusedMaxWindow && F > 16 * kBinsPerWave)
+      return fail(FRINGE_E_UNSUPPORTED,
+                  "scan %d: windows of at most %d APs need n_if * n_chan <= %d (got %lld)", s,
+                  kFusedMaxWindow, 16 * kBinsPerWave, (long long)F);
     si.full.win_off = win_off;
     si.grid_off = grid_off;
     win_off += nw;
@@ -270,14 +279,10 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
       return fail(FRINGE_E_INVALID, "FRINGE_DUMP_GRID needs %llu bytes (> %llu): tests only",
                   (unsigned long long)sz.grid_bytes, (unsigned long long)kMaxDumpBytes);
   }
-  uint64_t tw_bytes = 0;
-  for (int lm = 6; lm <= 12; ++lm)
-    for (auto& si : sz.scans)
-      if (si.log_m == lm) { tw_bytes += (uint64_t(1) << lm) * sizeof(float2); break; }
   if ((p->flags & FRINGE_PLAIN) && sz.n_windows > kMaxPlainWindows)
     return fail(FRINGE_E_UNSUPPORTED, "FRINGE_PLAIN is for at most %lld windows (timing subsets)",
                 (long long)kMaxPlainWindows);
-  sz.fixed_bytes = sz.table_bytes + sz.blk_bytes + sz.cand_bytes + sz.grid_bytes + tw_bytes +
+  sz.fixed_bytes = sz.table_bytes + sz.blk_bytes + sz.cand_bytes + sz.grid_bytes +
                    sz.stage_bytes + 64;
 
   // Work buffers: process each scan in slabs of baselines that fit.
@@ -300,32 +305,43 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     }
     si.slab_nb = int(std::min<int64_t>(nb, si.d.n_baselines));
   }
-  // Units in scan and baseline order.  Fused plans pack consecutive units
-  // into groups whose work buffers fit the cap, so one launch serves many
-  // scans; two-pass plans give every unit a group of its own.
-  uint64_t g_e = 0, g_part = 0, max_e = 0, max_part = 0;
+  // Units: slabs of baselines, in scan and baseline order within each fold
+  // class.  Fused plans pack consecutive units of one class into groups
+  // whose work buffers fit the cap, so one launch serves many scans with
+  // the instantiation their bands need; two-pass plans give every unit a
+  // group of its own.
+  std::vector<Unit> all;
   for (int s = 0; s < n_scans; ++s) {
     const ScanInfo& si = sz.scans[s];
+    for (int b0 = 0; b0 < si.d.n_baselines; b0 += si.slab_nb)
+      all.push_back(Unit{s, b0, std::min(si.slab_nb, si.d.n_baselines - b0),
+                         fused_fold_class(si.F), 0, 0});
+  }
+  if (sz.fused)
+    std::stable_sort(all.begin(), all.end(),
+                     [](const Unit& x, const Unit& y) { return x.fc < y.fc; });
+  uint64_t g_e = 0, g_part = 0, max_e = 0, max_part = 0;
+  for (Unit u : all) {
+    const ScanInfo& si = sz.scans[u.scan];
     const uint64_t t = uint64_t(data_len(si, sz.streaming));
-    for (int b0 = 0; b0 < si.d.n_baselines; b0 += si.slab_nb) {
-      const int nb = std::min(si.slab_nb, si.d.n_baselines - b0);
-      const uint64_t e_u = uint64_t(nb) * t;
-      const uint64_t part_u = uint64_t(si.n_kb) * nb * si.nwb_max;
-      const bool open = !sz.groups.empty() && sz.groups.back().u1 == int(sz.units.size());
-      if (!sz.fused || !open ||
-          (g_e + e_u) * sizeof(float) + (g_part + part_u) * part_bytes(sz.delay_only) > cap) {
-        sz.groups.push_back(Group{int(sz.units.size()), int(sz.units.size())});
-        g_e = g_part = 0;
-      }
-      sz.units.push_back(Unit{s, b0, nb, g_e, g_part});
-      sz.groups.back().u1 = int(sz.units.size());
-      g_e += e_u;
-      g_part += part_u;
-      max_e = std::max(max_e, g_e);
-      max_part = std::max(max_part, g_part);
-      if (!sz.fused)
-        sz.scratch_x = std::max<uint64_t>(sz.scratch_x, uint64_t(nb) * t * si.M * sizeof(float2));
+    const uint64_t e_u = uint64_t(u.nb) * t;
+    const uint64_t part_u = uint64_t(si.n_kb) * u.nb * si.nwb_max;
+    const bool open = !sz.groups.empty() && sz.groups.back().fc == u.fc;
+    if (!sz.fused || !open ||
+        (g_e + e_u) * sizeof(float) + (g_part + part_u) * part_bytes(sz.delay_only) > cap) {
+      sz.groups.push_back(Group{int(sz.units.size()), int(sz.units.size()), u.fc});
+      g_e = g_part = 0;
     }
+    u.e_off = g_e;
+    u.part_off = g_part;
+    sz.units.push_back(u);
+    sz.groups.back().u1 = int(sz.units.size());
+    g_e += e_u;
+    g_part += part_u;
+    max_e = std::max(max_e, g_e);
+    max_part = std::max(max_part, g_part);
+    if (!sz.fused)
+      sz.scratch_x = std::max<uint64_t>(sz.scratch_x, uint64_t(u.nb) * t * si.M * sizeof(float2));
   }
   sz.scratch_e = max_e * sizeof(float);
   sz.scratch_part = max_part * sizeof(uint64_t);
@@ -342,28 +358,40 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
 // Time chunk of the fused kernel's work items.  A wave searches the windows
 // starting in its chunk and transforms the chunk plus W_max - 1 APs of halo,
 // so long chunks waste less on halos and short chunks give more, shorter
-// waves.  Take the longest chunk (a multiple of the kernel period, at least
-// 64 APs) that still gives every wave slot of the device kWaveRounds waves;
-// when even 64 does not, 64 (the latency-bound case of small grids).
-constexpr int kWavesPerSimd = 3;   // occupancy of the fused kernel
+// waves.  Per fold class (one kernel instantiation), take the longest chunk
+// (a multiple of the kernel period, at least 64 APs) that still gives every
+// wave slot of the device kWaveRounds waves, the slots being the CUs times
+// the waves that instantiation keeps resident per CU; when even 64 does not,
+// 64 (the latency-bound case of small grids).
 constexpr int kWaveRounds = 16;
-void tune_chunks(Sizing* sz, int n_cu) {
-  if (!sz->fused) return;
+int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel) {
+  if (!sz->fused) return FRINGE_OK;
   const int period = fused_period(sz->w_max);
-  const int64_t target = int64_t(kWaveRounds) * n_cu * 4 * kWavesPerSimd;
-  int best = 64;
-  for (int c = 1024; c >= 64; c /= 2) {
-    if (c % period) continue;
-    int64_t waves = 0;
-    for (const auto& si : sz->scans) {
-      waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_kb;
+  for (int fc : {4, 8, 16}) {
+    int n_class = 0;
+    for (const auto& si : sz->scans) n_class += fused_fold_class(si.F) == fc ? 1 : 0;
+    if (n_class == 0) continue;
+    int occ = 0;
+    const hipError_t he =
+        launch_fused(nullptr, 0, 0, pad_t_kernel, sz->w_max, fc, false, nullptr, &occ);
+    if (he != hipSuccess) return hip_fail(he, "fused kernel occupancy");
+    const int64_t target = int64_t(kWaveRounds) * n_cu * std::max(1, occ);
+    int best = 64;
+    for (int c = 1024; c >= 64; c /= 2) {
+      if (c % period) continue;
+      int64_t waves = 0;
+      for (const auto& si : sz->scans)
+        if (fused_fold_class(si.F) == fc)
+          waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_kb;
+      if (waves >= target) {
+        best = c;
+        break;
+      }
     }
-    if (waves >= target) {
-      best = c;
-      break;
-    }
+    for (auto& si : sz->scans)
+      if (fused_fold_class(si.F) == fc) si.chunk = best;
   }
-  for (auto& si : sz->scans) si.chunk = best;
+  return FRINGE_OK;
 }
 
 ScanDev make_scan_dev(const ScanInfo& si, const CallScan& c) {
@@ -411,7 +439,7 @@ struct fringe_plan_s {
   int64_t* d_total = nullptr;
   ScanDev* d_scans = nullptr;      // scan table of the last search (inside an arena)
   float2* grid = nullptr;
-  float2* tw[13] = {};
+  const float2* tw[13] = {};        // twiddle tables (the library's, not owned)
   int64_t* h_total = nullptr;      // pinned
   fringe_candidate* h_cands = nullptr;  // pinned, the first n_prefetch records
   int64_t n_prefetch = 0;
@@ -458,8 +486,6 @@ void release(fringe_plan_t p) {
                   p->d_total, p->grid, p->d_ids, p->d_recs, p->d_arena[0], p->d_arena[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
-  for (auto* t : p->tw)
-    if (t) (void)hipFree(t);
   for (auto& st : p->streams)
     for (auto* b : st.stage)
       if (b) (void)hipFree(b);
@@ -539,6 +565,10 @@ int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, Ca
   StreamState& ss = p->streams[s];
   const int64_t A = ss.consumed;
   const int C = si.d.n_ap;
+  // start APs are reported as int32 (fringe_candidate.t_start)
+  if (A + C > int64_t(INT32_MAX))
+    return fail(FRINGE_E_UNSUPPORTED,
+                "subarray %d: the stream would pass 2^31 - 1 APs (start APs are int32)", s);
   const int64_t origin = std::max<int64_t>(0, floor_to(A - (p->sz.w_max - 1), p->sz.align));
   const int halo = int(A - origin);
   const int nxt = ss.cur ^ 1;
@@ -760,7 +790,11 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
     release(p);
     return hip_fail(he, "hipDeviceGetAttribute");
   }
-  tune_chunks(&p->sz, std::max(1, n_cu));
+  if ((rc = tune_chunks(&p->sz, std::max(1, n_cu),
+                        p->sz.delay_only ? 0 : params->pad_time)) != FRINGE_OK) {
+    release(p);
+    return rc;
+  }
   const Sizing& z = p->sz;
   const int ns = int(z.scans.size());
   if ((rc = dev_alloc(&p->X, z.scratch_x, "delay spectra")) ||
@@ -798,22 +832,12 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
       return hip_fail(he, "descriptor staging");
     }
   }
-  // twiddle tables exp(-2 pi i k / M), rounded from double
+  // twiddle tables exp(-2 pi i k / M): the library's compile-time tables
   for (auto& si : z.scans) {
     if (p->tw[si.log_m]) continue;
-    std::vector<float2> t(size_t(si.M));
-    for (int k = 0; k < si.M; ++k) {
-      const double a = -2.0 * M_PI * double(k) / double(si.M);
-      t[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
-    }
-    if ((rc = dev_alloc(&p->tw[si.log_m], t.size() * sizeof(float2), "twiddles"))) {
+    if ((he = twiddles_for(si.M, &p->tw[si.log_m])) != hipSuccess) {
       release(p);
-      return rc;
-    }
-    he = hipMemcpy(p->tw[si.log_m], t.data(), t.size() * sizeof(float2), hipMemcpyHostToDevice);
-    if (he != hipSuccess) {
-      release(p);
-      return hip_fail(he, "hipMemcpy(twiddles)");
+      return hip_fail(he, "twiddle table");
     }
   }
   p->n_prefetch = std::min(p->params.max_candidates, kCandPrefetch);
@@ -843,6 +867,11 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     for (int s = 0; s < ns; ++s)
       if (!d_vis[s]) return fail(FRINGE_E_INVALID, "scan %d: null visibility pointer", s);
   hipError_t he;
+  // The plan's buffers (work buffers, window table, candidates, streaming
+  // stages) are reused by every search: a search on another stream than the
+  // last one first waits for the last one to finish.
+  if (p->searched && st != p->last_stream && (he = hipStreamWaitEvent(st, p->done, 0)) != hipSuccess)
+    return hip_fail(he, "waiting for the previous search");
   p->prof_used = 0;
 #define FRINGE_TIMED(kind, call, what)                                        \
   do {                                                                        \
@@ -883,7 +912,6 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   auto* sdev = reinterpret_cast<ScanDev*>(p->tables.data() + L.scans);
   for (int s = 0; s < ns; ++s) sdev[s] = make_scan_dev(z.scans[s], p->call[s]);
   std::vector<int64_t> grp_blocks(z.groups.size(), 0), grp_windows(z.groups.size(), 0);
-  int hf_max = 1;
   if (plain) {
     plain_tables(p, data);
   } else {
@@ -903,7 +931,6 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
         if (!p->call_present[u.scan]) fin[ui].slab_windows = 0;
         fin[ui].win_begin = grp_windows[g];
         grp_windows[g] += fin[ui].slab_windows;
-        if (fus[ui].n_pairs > 0) hf_max = std::max(hf_max, fus[ui].hf);
       }
     }
   }
@@ -934,8 +961,8 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     for (size_t g = 0; g < z.groups.size(); ++g) {
       const int u0 = z.groups[g].u0, n = z.groups[g].u1 - z.groups[g].u0;
       if (grp_windows[g] == 0) continue;
-      FRINGE_TIMED(1, launch_fused(d_fus + u0, n, grp_blocks[g], kernel_pad_t, z.w_max, hf_max,
-                                   p->grid != nullptr, st), "fused search launch");
+      FRINGE_TIMED(1, launch_fused(d_fus + u0, n, grp_blocks[g], kernel_pad_t, z.w_max,
+                                   z.groups[g].fc, p->grid != nullptr, st), "fused search launch");
       FRINGE_TIMED(2, launch_finalize(d_fin + u0, n, grp_windows[g], st), "finalize launch");
     }
   } else {

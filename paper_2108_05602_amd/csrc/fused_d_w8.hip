@@ -5,9 +5,10 @@
 namespace fringe {
 
 hipError_t launch_fused_d_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
-                             hipStream_t st) {
-  if (hf_max <= 4) return launch_fused_t<0, 3, 4, false>(tab, n, blocks, st);
-  return launch_fused_t<0, 3, 16, false>(tab, n, blocks, st);
+                             hipStream_t st, int* occ) {
+  if (hf_max <= 4) return launch_fused_t<0, 3, 4, false>(tab, n, blocks, st, occ);
+  if (hf_max <= 8) return launch_fused_t<0, 3, 8, false>(tab, n, blocks, st, occ);
+  return launch_fused_t<0, 3, 16, false>(tab, n, blocks, st, occ);
 }
 
 }  // namespace fringe

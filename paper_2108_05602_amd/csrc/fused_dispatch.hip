@@ -4,23 +4,30 @@
 namespace fringe {
 
 hipError_t launch_fused_p1_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
-                              hipStream_t st);
+                              hipStream_t st, int* occ);
 hipError_t launch_fused_p1_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
-                              hipStream_t st);
+                              hipStream_t st, int* occ);
 hipError_t launch_fused_p2_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
-                              hipStream_t st);
+                              hipStream_t st, int* occ);
 hipError_t launch_fused_p2_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
-                              hipStream_t st);
+                              hipStream_t st, int* occ);
 hipError_t launch_fused_p1_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
-                              hipStream_t st);
+                              hipStream_t st, int* occ);
 hipError_t launch_fused_p2_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max, bool dump,
-                              hipStream_t st);
+                              hipStream_t st, int* occ);
 hipError_t launch_fused_d_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
-                             hipStream_t st);
+                             hipStream_t st, int* occ);
 hipError_t launch_fused_d_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
-                             hipStream_t st);
+                             hipStream_t st, int* occ);
 hipError_t launch_fused_d_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
-                             hipStream_t st);
+                             hipStream_t st, int* occ);
+
+// Fold class of a band of F channels: the HFMAX of the instantiation that
+// serves it (64-channel folds per lane, rounded up to 4, 8 or 16).
+int fused_fold_class(int F) {
+  const int hf = (F + kBinsPerWave - 1) / kBinsPerWave;
+  return hf <= 4 ? 4 : (hf <= 8 ? 8 : 16);
+}
 
 // APs per unrolled period of the kernel that serves w_max.
 int fused_period(int w_max) { return w_max <= 8 ? 4 : (w_max <= 32 ? 16 : 32); }
@@ -33,23 +40,23 @@ int64_t fused_blocks(const FusedArgs& a) {
 }
 
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
-                        int w_max, int hf_max, bool dump, hipStream_t st) {
+                        int w_max, int hf_max, bool dump, hipStream_t st, int* occ) {
   if (hf_max > 16 || w_max > kFusedMaxWindow) return hipErrorInvalidValue;
   if (pad_t == 0) {
     if (dump) return hipErrorInvalidValue;
-    if (w_max <= 8) return launch_fused_d_w3(d_tab, n_tab, n_blocks, hf_max, st);
-    if (w_max <= 32) return launch_fused_d_w5(d_tab, n_tab, n_blocks, hf_max, st);
-    return launch_fused_d_w6(d_tab, n_tab, n_blocks, hf_max, st);
+    if (w_max <= 8) return launch_fused_d_w3(d_tab, n_tab, n_blocks, hf_max, st, occ);
+    if (w_max <= 32) return launch_fused_d_w5(d_tab, n_tab, n_blocks, hf_max, st, occ);
+    return launch_fused_d_w6(d_tab, n_tab, n_blocks, hf_max, st, occ);
   }
   if (pad_t == 1) {
-    if (w_max <= 8) return launch_fused_p1_w3(d_tab, n_tab, n_blocks, hf_max, dump, st);
-    if (w_max <= 32) return launch_fused_p1_w5(d_tab, n_tab, n_blocks, hf_max, dump, st);
-    return launch_fused_p1_w6(d_tab, n_tab, n_blocks, hf_max, dump, st);
+    if (w_max <= 8) return launch_fused_p1_w3(d_tab, n_tab, n_blocks, hf_max, dump, st, occ);
+    if (w_max <= 32) return launch_fused_p1_w5(d_tab, n_tab, n_blocks, hf_max, dump, st, occ);
+    return launch_fused_p1_w6(d_tab, n_tab, n_blocks, hf_max, dump, st, occ);
   }
   if (pad_t == 2) {
-    if (w_max <= 8) return launch_fused_p2_w3(d_tab, n_tab, n_blocks, hf_max, dump, st);
-    if (w_max <= 32) return launch_fused_p2_w5(d_tab, n_tab, n_blocks, hf_max, dump, st);
-    return launch_fused_p2_w6(d_tab, n_tab, n_blocks, hf_max, dump, st);
+    if (w_max <= 8) return launch_fused_p2_w3(d_tab, n_tab, n_blocks, hf_max, dump, st, occ);
+    if (w_max <= 32) return launch_fused_p2_w5(d_tab, n_tab, n_blocks, hf_max, dump, st, occ);
+    return launch_fused_p2_w6(d_tab, n_tab, n_blocks, hf_max, dump, st, occ);
   }
   return hipErrorInvalidValue;
 }

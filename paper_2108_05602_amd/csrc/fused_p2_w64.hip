@@ -4,10 +4,11 @@
 namespace fringe {
 
 hipError_t launch_fused_p2_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
-                               bool dump, hipStream_t st) {
-  if (dump) return launch_fused_t<2, 6, 16, true>(tab, n, blocks, st);
-  if (hf_max <= 4) return launch_fused_t<2, 6, 4, false>(tab, n, blocks, st);
-  return launch_fused_t<2, 6, 16, false>(tab, n, blocks, st);
+                               bool dump, hipStream_t st, int* occ) {
+  if (dump) return launch_fused_t<2, 6, 16, true>(tab, n, blocks, st, occ);
+  if (hf_max <= 4) return launch_fused_t<2, 6, 4, false>(tab, n, blocks, st, occ);
+  if (hf_max <= 8) return launch_fused_t<2, 6, 8, false>(tab, n, blocks, st, occ);
+  return launch_fused_t<2, 6, 16, false>(tab, n, blocks, st, occ);
 }
 
 }  // namespace fringe

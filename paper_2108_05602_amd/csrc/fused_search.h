@@ -111,8 +111,11 @@ constexpr int site_level(int i, int k) {
 
 }  // namespace fused
 
+// Two waves per SIMD at least: the 64-AP history with 16 folds sits just
+// above the 256 registers of that occupancy, and holding it there costs a
+// few rematerialisations, not spills.
 template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DUMP ? 1 : 2)))
 fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   constexpr int WMAX = 1 << LOGWMAX;
   constexpr int P = WMAX / 2;          // APs per unrolled period
@@ -160,25 +163,25 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   }
   kc.rot2 = (lane & 2) != 0 && (lane & 1) != 0;
   kc.addr32 = (lane ^ 32) * 4;
-  float2 wh[HFMAX];  // fold twiddles w_R^{c h} (uniform, kept in vector registers)
-#pragma unroll
-  for (int h = 0; h < HFMAX; ++h) {
-    const float2 w = ld_global(tw + (((cls * h) * 64) & (M - 1)));
-    wh[h] = make_float2(in_vgpr(w.x), in_vgpr(w.y));
-  }
+  // Wide bands (more than 4 folds) keep the per-lane fold coefficients and,
+  // with dedispersion, the shifted load offsets in LDS, read back per AP:
+  // in registers they would push the kernel with a 64-AP history to one
+  // wave per SIMD.  Narrow bands keep both in registers.
+  constexpr bool TAB_LDS = HFMAX > 4;
+  __shared__ f32x2_t s_gw[TAB_LDS ? HFMAX : 1][64];
+  __shared__ uint32_t s_off[TAB_LDS ? HFMAX : 1][64];
+  typedef const volatile __attribute__((address_space(3))) f32x2_t* LdsGw;
+  typedef const volatile __attribute__((address_space(3))) uint32_t* LdsOff;
 
   const float2* xb = a.vis + static_cast<int64_t>(b) * a.vis_stride;
   // Loads are unconditional and in bounds (the AP clamped to T - 1, lanes
-  // past the band reading sample 0); what lies outside the data is zeroed
-  // where it is used, so no load has to complete before later work issues.
+  // past the band reading sample 0 or past the row, where the buffer's range
+  // check returns zeros); what lies outside the data is zeroed where it is
+  // used, so no load has to complete before later work issues.
   bool lane_in[HFMAX];
-  uint32_t lane_off[HFMAX];  // byte offset of the lane's sample in an AP row
 #pragma unroll
-  for (int h = 0; h < HFMAX; ++h) {
-    const int f = lane + 64 * h;  // natural order: each load is one contiguous segment
-    lane_in[h] = h < hf && f < F;
-    lane_off[h] = lane_in[h] ? static_cast<uint32_t>(f) * sizeof(float2) : 0u;
-  }
+  for (int h = 0; h < HFMAX; ++h) lane_in[h] = h < hf && lane + 64 * h < F;
+  const uint32_t lane8 = static_cast<uint32_t>(lane) * sizeof(float2);
   // (a baseline's data is < 4 GiB, checked at plan time)
   const uint32_t row_bytes = static_cast<uint32_t>(F) * sizeof(float2);
   // dedispersion: channel f of AP t is read from AP t + d_f.  The shift is
@@ -187,19 +190,42 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // turns the reads past the data into zeros (with shifts a baseline is
   // < 1 GiB, so no offset wraps).  Without shifts every read is in range.
   const bool has_s = a.shifts != nullptr;
-  if (has_s) {
+  // byte offset of the lane's sample of fold h in an AP row (natural order:
+  // each load is one contiguous segment)
+  auto shifted_off = [&](int h) -> uint32_t {
+    if (!lane_in[h]) return 0u;
+    uint32_t o = lane8 + static_cast<uint32_t>(64 * sizeof(float2) * h);
+    if (has_s) o += static_cast<uint32_t>(min(max(a.shifts[lane + 64 * h], 0), T)) * row_bytes;
+    return o;
+  };
+  uint32_t lane_off[TAB_LDS ? 1 : HFMAX];
 #pragma unroll
-    for (int h = 0; h < HFMAX; ++h)
-      if (lane_in[h])
-        lane_off[h] += static_cast<uint32_t>(min(max(a.shifts[lane + 64 * h], 0), T)) * row_bytes;
+  for (int h = 0; h < (TAB_LDS ? 1 : HFMAX); ++h) lane_off[h] = shifted_off(h);
+  if constexpr (TAB_LDS) {
+    if (has_s) {
+#pragma unroll
+      for (int h = 0; h < HFMAX; ++h) s_off[h][lane] = shifted_off(h);
+    }
   }
   const auto vrs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float2*>(xb), static_cast<short>(0),
       static_cast<int>(static_cast<uint32_t>(T) * row_bytes), kBufferWord3);
   auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
     const uint32_t toff = static_cast<uint32_t>(min(t, T - 1)) * row_bytes;
+    if constexpr (TAB_LDS) {
+      if (has_s) {
+        const LdsOff so = (LdsOff)(&s_off[0][lane]);
 #pragma unroll
-    for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h] + toff, 0);
+        for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, so[64 * h] + toff, 0);
+      } else {
+#pragma unroll
+        for (int h = 0; h < HFMAX; ++h)
+          dst[h] = ld_buffer(vrs, lane8 + toff, static_cast<uint32_t>(64 * sizeof(float2) * h));
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h] + toff, 0);
+    }
   };
   const bool band_full = F == 64 * HFMAX;  // every lane in band for every fold
   // The fold's coefficients per lane l (f' = l) and h: the calibration gain
@@ -211,25 +237,41 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // zeros.
   const bool has_g = a.gains != nullptr;
   const float2 wsrc = ld_global(tw + ((cls * lane) & (M - 1)));
-  float2 gw[HFMAX];
-  float gn[HFMAX];
-#pragma unroll
-  for (int h = 0; h < HFMAX; ++h) {
-    gw[h] = c_mul(wh[h], wsrc);
-    gn[h] = 1.f;
-  }
-  if (has_g) {
-    const auto grs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float2*>(a.gains + static_cast<int64_t>(b) * F), static_cast<short>(0),
-        static_cast<int>(static_cast<uint32_t>(F) * sizeof(float2)), kBufferWord3);
-    const uint32_t lane8 = static_cast<uint32_t>(lane) * sizeof(float2);
+  const auto grs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2*>(has_g ? a.gains + static_cast<int64_t>(b) * F : a.gains),
+      static_cast<short>(0), static_cast<int>(static_cast<uint32_t>(F) * sizeof(float2)),
+      kBufferWord3);
+  auto coef = [&](int h) -> float2 {
+    const float2 w = ld_global(tw + (((cls * h) * 64) & (M - 1)));  // w_R^{c h}
+    const float2 ww = c_mul(make_float2(in_vgpr(w.x), in_vgpr(w.y)), wsrc);
+    if (!has_g) return ww;
+    return c_mul(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0), ww);
+  };
+  float2 gw[TAB_LDS ? 1 : HFMAX];
+  float gn[TAB_LDS ? 1 : HFMAX];
+  if constexpr (TAB_LDS) {
 #pragma unroll
     for (int h = 0; h < HFMAX; ++h) {
-      const float2 g = ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0);
-      gw[h] = c_mul(g, c_mul(wh[h], wsrc));
-      gn[h] = c_norm(g);
+      const float2 c = coef(h);
+      s_gw[h][lane] = f32x2_t{c.x, c.y};
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < HFMAX; ++h) {
+      gw[h] = coef(h);
+      gn[h] = has_g ? c_norm(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0)) : 1.f;
     }
   }
+  // coefficient h of this lane (from LDS: |g|^2 = |coefficient|^2 up to
+  // rounding, the twiddles having unit modulus)
+  auto coef_of = [&](int h) -> float2 {
+    if constexpr (TAB_LDS) {
+      const f32x2_t v = ((LdsGw)(&s_gw[0][lane]))[64 * h];
+      return make_float2(v.x, v.y);
+    } else {
+      return gw[h];
+    }
+  };
   auto sample = [&](float2 x, int h, bool t_in) {
     const bool ok = t_in && lane_in[h];
     return make_float2(ok ? x.x : 0.f, ok ? x.y : 0.f);
@@ -317,13 +359,18 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
 #pragma unroll
             for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
           }
-          z[e] = c_mul(pre[fs][0], gw[0]);
+          z[e] = c_mul(pre[fs][0], coef_of(0));
 #pragma unroll
-          for (int h = 1; h < HFMAX; ++h) z[e] = c_add(z[e], c_mul(pre[fs][h], gw[h]));
+          for (int h = 1; h < HFMAX; ++h) z[e] = c_add(z[e], c_mul(pre[fs][h], coef_of(h)));
           if (PT > 0 && cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
             float es = 0.f;
 #pragma unroll
-            for (int h = 0; h < HFMAX; ++h) es = fmaf(gn[h], c_norm(pre[fs][h]), es);
+            for (int h = 0; h < HFMAX; ++h) {
+              float gh;
+              if constexpr (TAB_LDS) gh = has_g ? c_norm(coef_of(h)) : 1.f;
+              else gh = gn[h];
+              es = fmaf(gh, c_norm(pre[fs][h]), es);
+            }
             const float en = wave_sum_dpp(es);
             if (lane == 0 && te < own_hi) eb[te] = en;
           }
@@ -417,8 +464,14 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   }
 }
 
+// Launches the instantiation, or with occ set, stores the work groups (one
+// wave each) it keeps resident per CU and launches nothing.
 template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
-hipError_t launch_fused_t(const FusedArgs* tab, int n_tab, int64_t blocks, hipStream_t st) {
+hipError_t launch_fused_t(const FusedArgs* tab, int n_tab, int64_t blocks, hipStream_t st,
+                          int* occ) {
+  if (occ)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        occ, reinterpret_cast<const void*>(&fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP>), 64, 0);
   if (blocks == 0 || n_tab == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL((fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP>),

@@ -123,6 +123,10 @@ struct CompactArgs {
 
 constexpr int kCompactBlock = 1024;  // windows per compaction block
 
+// exp(-2 pi i k / m), k < m, for m a power of two in [64, 4096]: device
+// address of the library's compile-time table on the current device.
+hipError_t twiddles_for(int m, const float2** out);
+
 hipError_t launch_delay_fft(const DelayArgs& a, hipStream_t st);
 hipError_t launch_rate_peak(const RateArgs& a, hipStream_t st);
 // Fused path for plans whose longest window is at most kFusedMaxWindow APs.
@@ -130,10 +134,14 @@ constexpr int kFusedMaxWindow = 64;
 int fused_period(int w_max);
 // Blocks that entry `a` occupies in a fused launch.
 int64_t fused_blocks(const FusedArgs& a);
+// Fold class (4, 8 or 16 folds of 64 channels per lane) serving F channels.
+int fused_fold_class(int F);
 // d_tab: n_tab entries in device memory; hf_max: the largest entry hf;
-// pad_t = 0 selects the delay-only search (rate bin 0 only).
+// pad_t = 0 selects the delay-only search (rate bin 0 only).  With occ set,
+// nothing is launched: *occ receives the chosen instantiation's resident
+// work groups (of one wave) per CU.
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
-                        int w_max, int hf_max, bool dump, hipStream_t st);
+                        int w_max, int hf_max, bool dump, hipStream_t st, int* occ = nullptr);
 hipError_t launch_finalize(const FinalizeArgs* d_tab, int n_tab, int64_t n_windows,
                            hipStream_t st);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t st);

@@ -132,6 +132,13 @@ def test_validation_errors():
     assert _code(lambda: chk([big], [64, 128])) == B.FRINGE_E_UNSUPPORTED
     assert "4 GiB" in F.fringe_last_error()
     assert chk([big], [128])["n_windows"] > 0
+    # the fused kernel folds at most 16 x 64 channels per lane: wider bands
+    # (M_f = 4096 at pad 2 or 1) only with windows longer than 64 APs
+    wide = dict(ok, n_if=32, n_chan=64)
+    assert _code(lambda: chk([wide], [4], pad_freq=2)) == B.FRINGE_E_UNSUPPORTED
+    assert "16 x 64" in F.fringe_last_error() or "<= 1024" in F.fringe_last_error()
+    assert _code(lambda: chk([dict(wide, n_if=64)], [1, 2], pad_freq=1)) == B.FRINGE_E_UNSUPPORTED
+    assert chk([dict(wide, n_ap=300)], [128], pad_freq=2)["n_windows"] > 0
 
 
 def test_budget():

@@ -301,9 +301,10 @@ def test_plain_path_equals_batched():
 def test_batched_uneven_scans_one_launch():
     """Scans of uneven baselines, lengths and channel counts (8/16 IF x
     16/32/64 chan, windows up to 64 APs) searched by one plan: one fused
-    launch per group of scans.  Equal to per-scan plans field by field, and
-    to the reference on sampled windows; a tight HBM budget splits the scans
-    into several groups with the same results."""
+    launch per fold class of their bands (the kernel instantiation each
+    band needs).  Equal to per-scan plans field by field, and to the
+    reference on sampled windows; a tight HBM budget splits the scans into
+    several groups with the same results."""
     import paper_2108_05602_amd as F
     print("case: batched uneven scans", flush=True)
     specs = synth.c3(n_scans=6, max_ap=600, max_stations=5)
@@ -313,7 +314,9 @@ def test_batched_uneven_scans_one_launch():
     args = (p["window_aps"], p["pad_freq"], p["pad_time"], p["snr_threshold"])
     plan, table, cands = run_gpu(descs, vis, *args, flags=F.FRINGE_PROFILE)
     prof = plan.profile()
-    assert prof["rate_launches"] == 1 and prof["finalize_launches"] == 1, prof
+    classes = {min(16, max(4, 1 << math.ceil(math.log2(max(1, s.n_freq // 64))))) for s in specs}
+    assert len(classes) > 1, "the sample should mix fold classes"
+    assert prof["rate_launches"] == len(classes) == prof["finalize_launches"], prof
     for s in range(len(specs)):
         p1, t1, _ = run_gpu([descs[s]], [vis[s]], *args)
         sub = table[table["scan"] == s]

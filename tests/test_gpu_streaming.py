@@ -141,3 +141,37 @@ def test_stream_skipped_subarray_and_ids():
     # subarray 1: chunks 0,1,2,3 = the whole 400-AP scan: every window once
     batch1, _ = _batch(specs[1].desc(), vis[1], ws, 4.5)
     assert sorted(got[1]) == sorted(_key(r)[1:] for r in batch1)
+
+
+def test_stream_alternating_streams():
+    """Chunks of one streaming plan searched on two HIP streams in turn (each
+    search waits for the previous one, whose stage it reads): streamed ==
+    batch, bit for bit."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    spec = synth.evn_scan(4031, 3, 1952, 8, 32, 1.024e-3, 16e6, 3, width_max=32, n_tones=1)
+    vis = spec.full()
+    desc = spec.desc()
+    ws, thr, chunk = [1, 2, 4, 8, 16, 32], 4.5, 244
+    print(f"case: alternating streams, chunk {chunk}", flush=True)
+    batch, _ = _batch(desc, vis, ws, thr)
+    bmap = {_key(r): r for r in batch}
+    dev = torch.from_numpy(vis).cuda()
+    pieces = [dev[:, t0:t0 + chunk].contiguous() for t0 in range(0, vis.shape[1], chunk)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    got = []
+    with F.Plan([dict(desc, n_ap=chunk)], ws, pad_freq=4, pad_time=2, snr_threshold=thr,
+                flags=F.FRINGE_STREAMING) as p:
+        for i, piece in enumerate(pieces):
+            p.search([piece.data_ptr()], streams[i % 2].cuda_stream)
+            n = p.info()["n_windows"]
+            if n:
+                got.append(p.windows(np.arange(n)))
+    table = np.concatenate(got)
+    assert {_key(r) for r in table} == set(bmap)
+    for r in table:
+        b = bmap[_key(r)]
+        for f in ("k_rate", "k_delay", "amp", "snr", "energy"):
+            assert r[f] == b[f], (_key(r), f)
