@@ -98,23 +98,39 @@ struct ScanInfo {
   int stage_len;                      // streaming: APs of halo + chunk
   int slab_nb;                        // baselines per pass
   int chunk;                          // search-kernel time tiling
+  // Spectra mode: each slab's delay spectra X[b][t][k_f] are written to HBM
+  // by the delay-transform kernel and the rate kernels read them (windows
+  // longer than 64 APs need it; wide bands use it by default).  x_short:
+  // the windows of at most 64 APs read X too (a baseline's spectra under
+  // 4 GiB), rather than transforming the visibilities themselves.
+  bool spectra;
+  bool x_short;
 };
 
 // A slab of baselines of one scan: one entry of a fused (or finalize)
 // launch, with its place in the work buffers.
 struct Unit {
   int scan, b0, nb;
-  int fc;                             // fold class of the scan's band (fused kernel)
+  int fc;                             // kernel of its short windows: fold class or kFoldSpectra
+  bool spectra;                       // spectra mode (a group of its own)
   uint64_t e_off, part_off;           // element offsets in the energy / peak buffers
 };
 
 // Units [u0, u1) share one fused launch and one finalize launch; every unit
-// of a group has the group's fold class, so each launch runs the kernel
-// instantiation its own bands need.
+// of a group has the group's kernel class, so each launch runs the kernel
+// instantiation its own bands need.  A spectra-mode unit is a group of its
+// own: delay transform into the spectra buffer, rate kernels, finalize.
 struct Group {
   int u0, u1;
   int fc;
+  bool spectra;
 };
+
+// Bands of at least this fold class are searched in spectra mode by
+// default: with 16 folds per lane the fused kernel's reads of every
+// channel by each of the 64 delay-bin classes bound it, and the spectra
+// round trip through HBM costs less.
+constexpr int kSpectraMinFold = 16;
 
 constexpr int64_t kMaxPlainWindows = int64_t(1) << 21;
 constexpr size_t kArenaAlign = 256;
@@ -140,13 +156,15 @@ struct Sizing {
 
 int data_len(const ScanInfo& s, bool streaming) { return streaming ? s.stage_len : s.d.n_ap; }
 
+int unit_class(const ScanInfo& si) { return si.x_short ? kFoldSpectra : fused_fold_class(si.F); }
+
 // Bytes per window and delay-bin class: the peak key, and with the
 // delay-only search the class's power sum.
 size_t part_bytes(bool delay_only) { return sizeof(uint64_t) + (delay_only ? sizeof(float) : 0); }
 
-uint64_t per_baseline_scratch(const ScanInfo& s, bool fused, bool streaming, bool delay_only) {
+uint64_t per_baseline_scratch(const ScanInfo& s, bool streaming, bool delay_only) {
   const uint64_t t = uint64_t(data_len(s, streaming));
-  const uint64_t x = fused ? 0 : t * s.M * sizeof(float2);
+  const uint64_t x = s.spectra ? t * s.M * sizeof(float2) : 0;
   return x + t * sizeof(float) + uint64_t(s.n_kb) * s.nwb_max * part_bytes(delay_only);
 }
 
@@ -264,6 +282,14 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     grid_off += si.grid_per_bl * d.n_baselines;
     // time chunk of one work item: a multiple of the fused kernel's period
     si.chunk = sz.fused ? 256 : std::min(1024, std::max(128, 8 * sz.w_max));
+    // spectra mode: required for windows longer than 64 APs; by default for
+    // wide bands of the full search (not with FRINGE_PLAIN, whose launches
+    // are one window each)
+    const bool x_fits =
+        (int64_t(data_len(si, sz.streaming)) + 1) * M * int64_t(sizeof(float2)) < (int64_t(1) << 32);
+    si.spectra = !sz.fused || (!sz.delay_only && !(p->flags & FRINGE_PLAIN) && x_fits &&
+                               fused_fold_class(si.F) >= kSpectraMinFold);
+    si.x_short = si.spectra && x_fits;
     if (sz.streaming)
       sz.stage_bytes += 2 * uint64_t(d.n_baselines) * si.stage_len * F * sizeof(float2);
     sz.scans.push_back(si);
@@ -295,7 +321,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     cap = p->hbm_budget_bytes - sz.fixed_bytes;
   }
   for (auto& si : sz.scans) {
-    const uint64_t per = per_baseline_scratch(si, sz.fused, sz.streaming, sz.delay_only);
+    const uint64_t per = per_baseline_scratch(si, sz.streaming, sz.delay_only);
     int64_t nb = int64_t(cap / per);
     if (nb < 1) {
       if (p->hbm_budget_bytes > 0)
@@ -314,22 +340,22 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
   for (int s = 0; s < n_scans; ++s) {
     const ScanInfo& si = sz.scans[s];
     for (int b0 = 0; b0 < si.d.n_baselines; b0 += si.slab_nb)
-      all.push_back(Unit{s, b0, std::min(si.slab_nb, si.d.n_baselines - b0),
-                         fused_fold_class(si.F), 0, 0});
+      all.push_back(Unit{s, b0, std::min(si.slab_nb, si.d.n_baselines - b0), unit_class(si),
+                         si.spectra, 0, 0});
   }
-  if (sz.fused)
-    std::stable_sort(all.begin(), all.end(),
-                     [](const Unit& x, const Unit& y) { return x.fc < y.fc; });
+  std::stable_sort(all.begin(), all.end(), [](const Unit& x, const Unit& y) {
+    return x.spectra != y.spectra ? y.spectra : x.fc < y.fc;
+  });
   uint64_t g_e = 0, g_part = 0, max_e = 0, max_part = 0;
   for (Unit u : all) {
     const ScanInfo& si = sz.scans[u.scan];
     const uint64_t t = uint64_t(data_len(si, sz.streaming));
     const uint64_t e_u = uint64_t(u.nb) * t;
     const uint64_t part_u = uint64_t(si.n_kb) * u.nb * si.nwb_max;
-    const bool open = !sz.groups.empty() && sz.groups.back().fc == u.fc;
-    if (!sz.fused || !open ||
-        (g_e + e_u) * sizeof(float) + (g_part + part_u) * part_bytes(sz.delay_only) > cap) {
-      sz.groups.push_back(Group{int(sz.units.size()), int(sz.units.size()), u.fc});
+    const bool open = !sz.groups.empty() && !sz.groups.back().spectra && !u.spectra &&
+                      sz.groups.back().fc == u.fc;
+    if (!open || (g_e + e_u) * sizeof(float) + (g_part + part_u) * part_bytes(sz.delay_only) > cap) {
+      sz.groups.push_back(Group{int(sz.units.size()), int(sz.units.size()), u.fc, u.spectra});
       g_e = g_part = 0;
     }
     u.e_off = g_e;
@@ -340,7 +366,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     g_part += part_u;
     max_e = std::max(max_e, g_e);
     max_part = std::max(max_part, g_part);
-    if (!sz.fused)
+    if (u.spectra)
       sz.scratch_x = std::max<uint64_t>(sz.scratch_x, uint64_t(u.nb) * t * si.M * sizeof(float2));
   }
   sz.scratch_e = max_e * sizeof(float);
@@ -365,11 +391,11 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
 // 64 (the latency-bound case of small grids).
 constexpr int kWaveRounds = 16;
 int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel) {
-  if (!sz->fused) return FRINGE_OK;
+  if (!sz->fused) return FRINGE_OK;  // windows longer than 64 APs: the plan's fixed chunk
   const int period = fused_period(sz->w_max);
-  for (int fc : {4, 8, 16}) {
+  for (int fc : {kFoldSpectra, 4, 8, 16}) {
     int n_class = 0;
-    for (const auto& si : sz->scans) n_class += fused_fold_class(si.F) == fc ? 1 : 0;
+    for (const auto& si : sz->scans) n_class += unit_class(si) == fc ? 1 : 0;
     if (n_class == 0) continue;
     int occ = 0;
     const hipError_t he =
@@ -381,7 +407,7 @@ int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel) {
       if (c % period) continue;
       int64_t waves = 0;
       for (const auto& si : sz->scans)
-        if (fused_fold_class(si.F) == fc)
+        if (unit_class(si) == fc)
           waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_kb;
       if (waves >= target) {
         best = c;
@@ -389,7 +415,7 @@ int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel) {
       }
     }
     for (auto& si : sz->scans)
-      if (fused_fold_class(si.F) == fc) si.chunk = best;
+      if (unit_class(si) == fc) si.chunk = best;
   }
   return FRINGE_OK;
 }
@@ -629,6 +655,15 @@ FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan
   for (int l = 0; l < kMaxLevels; ++l) fu.lvl_j0[l] = c.lvl_j0[l];
   for (int L = 0; L < 8; ++L) fu.lvl_of_log[L] = -1;
   for (int l = 0; l < z.lv.n; ++l) fu.lvl_of_log[z.lv.logW[l]] = l;
+  if (si.x_short) {
+    // the short windows read the slab's delay spectra, into which the
+    // delay-transform kernel has applied gains and shifts
+    fu.vis = p->X;
+    fu.vis_stride = int64_t(c.T) * si.M;
+    fu.F = si.M;
+    fu.gains = nullptr;
+    fu.shifts = nullptr;
+  }
   return fu;
 }
 
@@ -926,7 +961,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
         fus[ui] = fused_entry(p, si, c, u, data[u.scan], stride);
         if (!p->call_present[u.scan]) fus[ui].n_pairs = 0;
         fus[ui].block_off = grp_blocks[g];
-        grp_blocks[g] += z.fused ? fused_blocks(fus[ui]) : 0;
+        grp_blocks[g] += fused_blocks(fus[ui]);
         fin[ui] = finalize_entry(p, si, c, u);
         if (!p->call_present[u.scan]) fin[ui].slab_windows = 0;
         fin[ui].win_begin = grp_windows[g];
@@ -957,27 +992,33 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
                                    false, st), "plain fused launch");
       FRINGE_TIMED(2, launch_finalize(d_fin + i, 1, 1, st), "plain finalize launch");
     }
-  } else if (z.fused) {
-    for (size_t g = 0; g < z.groups.size(); ++g) {
-      const int u0 = z.groups[g].u0, n = z.groups[g].u1 - z.groups[g].u0;
-      if (grp_windows[g] == 0) continue;
-      FRINGE_TIMED(1, launch_fused(d_fus + u0, n, grp_blocks[g], kernel_pad_t, z.w_max,
-                                   z.groups[g].fc, p->grid != nullptr, st), "fused search launch");
-      FRINGE_TIMED(2, launch_finalize(d_fin + u0, n, grp_windows[g], st), "finalize launch");
-    }
   } else {
     const auto* hfus = reinterpret_cast<const FusedArgs*>(p->tables.data() + L.fused);
+    // levels served by the fused kernel (windows of at most 64 APs)
+    int l0 = 0;
+    while (l0 < z.lv.n && z.lv.W[l0] <= kFusedMaxWindow) ++l0;
     for (size_t g = 0; g < z.groups.size(); ++g) {
-      const int ui = z.groups[g].u0;  // two-pass groups hold one unit
+      const Group& gr = z.groups[g];
+      if (grp_windows[g] == 0) continue;
+      if (!gr.spectra) {
+        FRINGE_TIMED(1, launch_fused(d_fus + gr.u0, gr.u1 - gr.u0, grp_blocks[g], kernel_pad_t,
+                                     z.w_max, gr.fc, p->grid != nullptr, st),
+                     "fused search launch");
+        FRINGE_TIMED(2, launch_finalize(d_fin + gr.u0, gr.u1 - gr.u0, grp_windows[g], st),
+                     "finalize launch");
+        continue;
+      }
+      // spectra mode: one unit; its delay spectra to HBM, then the rate kernels
+      const int ui = gr.u0;
       const Unit& u = z.units[ui];
       const ScanInfo& si = z.scans[u.scan];
       const CallScan& c = p->call[u.scan];
-      if (grp_windows[g] == 0) continue;
+      const int64_t stride = int64_t(z.streaming ? si.stage_len : si.d.n_ap) * si.F;
       DelayArgs da{};
-      da.vis = hfus[ui].vis;
-      da.gains = hfus[ui].gains;
-      da.shifts = hfus[ui].shifts;
-      da.vis_stride = hfus[ui].vis_stride;
+      da.vis = data[u.scan] + int64_t(u.b0) * stride;
+      da.gains = p->gains[u.scan] ? p->gains[u.scan] + int64_t(u.b0) * si.F : nullptr;
+      da.shifts = p->shifts[u.scan];
+      da.vis_stride = stride;
       da.X = p->X;
       da.e = p->e + u.e_off;
       da.tw = p->tw[si.log_m];
@@ -988,43 +1029,42 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       da.log_m = si.log_m;
       da.pad_f = p->params.pad_freq;
       FRINGE_TIMED(0, launch_delay_fft(da, st), "delay transform launch");
-
-      // the windows of at most kFusedMaxWindow APs: the fused kernel, on the
-      // same slab (its own delay transform; same window numbering and
-      // partials); only the longer ones read the spectra written above
-      int l0 = 0;
-      while (l0 < z.lv.n && z.lv.W[l0] <= kFusedMaxWindow) ++l0;
       if (l0 > 0 && hfus[ui].n_pairs > 0) {
+        // the windows of at most kFusedMaxWindow APs: from the spectra, or
+        // (a baseline's spectra of 4 GiB or more) by the kernel's own delay
+        // transform of the visibilities; same numbering and partials
         FRINGE_TIMED(1, launch_fused(d_fus + ui, 1, fused_blocks(hfus[ui]), kernel_pad_t,
-                                     z.lv.W[l0 - 1], hfus[ui].hf, p->grid != nullptr, st),
+                                     z.lv.W[l0 - 1], si.x_short ? kFoldSpectra : hfus[ui].hf,
+                                     p->grid != nullptr, st),
                      "fused search launch (short windows)");
       }
-
-      RateArgs ra{};
-      ra.X = p->X;
-      ra.part = p->part + u.part_off;
-      ra.dump = p->grid;
-      ra.slab_windows = int64_t(u.nb) * c.nwb;
-      ra.dump_base = si.grid_off + int64_t(u.b0) * si.grid_per_bl;
-      ra.grid_per_bl = si.grid_per_bl;
-      for (int l = 0; l < kMaxLevels; ++l) ra.lvl_goff[l] = si.lvl_goff[l];
-      ra.nb = u.nb;
-      ra.T = c.T;
-      ra.M = si.M;
-      ra.log_m = si.log_m;
-      ra.n_kb = si.n_kb;
-      ra.chunk = si.chunk;
-      ra.n_chunks = (c.T + si.chunk - 1) / si.chunk;
-      ra.w_max = z.w_max;
-      ra.buf_slots = rate_buffer_slots(z.w_max);
-      ra.pad_t = si.pad_t;
-      ra.nwb = int(c.nwb);
-      ra.t_emit = c.t_emit;
-      ra.l0 = l0;
-      for (int l = 0; l <= kMaxLevels; ++l) ra.lvl_off[l] = int(c.lvl_off[l]);
-      for (int l = 0; l < kMaxLevels; ++l) ra.lvl_j0[l] = c.lvl_j0[l];
-      ra.lv = z.lv;
-      FRINGE_TIMED(1, launch_rate_peak(ra, st), "rate transform launch");
+      if (l0 < z.lv.n) {
+        RateArgs ra{};
+        ra.X = p->X;
+        ra.part = p->part + u.part_off;
+        ra.dump = p->grid;
+        ra.slab_windows = int64_t(u.nb) * c.nwb;
+        ra.dump_base = si.grid_off + int64_t(u.b0) * si.grid_per_bl;
+        ra.grid_per_bl = si.grid_per_bl;
+        for (int l = 0; l < kMaxLevels; ++l) ra.lvl_goff[l] = si.lvl_goff[l];
+        ra.nb = u.nb;
+        ra.T = c.T;
+        ra.M = si.M;
+        ra.log_m = si.log_m;
+        ra.n_kb = si.n_kb;
+        ra.chunk = si.chunk;
+        ra.n_chunks = (c.T + si.chunk - 1) / si.chunk;
+        ra.w_max = z.w_max;
+        ra.buf_slots = rate_buffer_slots(z.w_max);
+        ra.pad_t = si.pad_t;
+        ra.nwb = int(c.nwb);
+        ra.t_emit = c.t_emit;
+        ra.l0 = l0;
+        for (int l = 0; l <= kMaxLevels; ++l) ra.lvl_off[l] = int(c.lvl_off[l]);
+        for (int l = 0; l < kMaxLevels; ++l) ra.lvl_j0[l] = c.lvl_j0[l];
+        ra.lv = z.lv;
+        FRINGE_TIMED(1, launch_rate_peak(ra, st), "rate transform launch");
+      }
       FRINGE_TIMED(2, launch_finalize(d_fin + ui, 1, grp_windows[g], st), "finalize launch");
     }
   }

@@ -22,6 +22,13 @@ hipError_t launch_fused_d_w5(const FusedArgs* tab, int n, int64_t blocks, int hf
 hipError_t launch_fused_d_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
                              hipStream_t st, int* occ);
 
+hipError_t launch_fused_x_p1(const FusedArgs* tab, int n, int64_t blocks, int w_max, bool dump,
+                             hipStream_t st, int* occ);
+hipError_t launch_fused_x_p2(const FusedArgs* tab, int n, int64_t blocks, int w_max, bool dump,
+                             hipStream_t st, int* occ);
+hipError_t launch_fused_x_d(const FusedArgs* tab, int n, int64_t blocks, int w_max,
+                            hipStream_t st, int* occ);
+
 // Fold class of a band of F channels: the HFMAX of the instantiation that
 // serves it (64-channel folds per lane, rounded up to 4, 8 or 16).
 int fused_fold_class(int F) {
@@ -42,6 +49,13 @@ int64_t fused_blocks(const FusedArgs& a) {
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
                         int w_max, int hf_max, bool dump, hipStream_t st, int* occ) {
   if (hf_max > 16 || w_max > kFusedMaxWindow) return hipErrorInvalidValue;
+  if (hf_max == kFoldSpectra) {
+    if (pad_t == 0)
+      return dump ? hipErrorInvalidValue : launch_fused_x_d(d_tab, n_tab, n_blocks, w_max, st, occ);
+    if (pad_t == 1) return launch_fused_x_p1(d_tab, n_tab, n_blocks, w_max, dump, st, occ);
+    if (pad_t == 2) return launch_fused_x_p2(d_tab, n_tab, n_blocks, w_max, dump, st, occ);
+    return hipErrorInvalidValue;
+  }
   if (pad_t == 0) {
     if (dump) return hipErrorInvalidValue;
     if (w_max <= 8) return launch_fused_d_w3(d_tab, n_tab, n_blocks, hf_max, st, occ);

@@ -114,7 +114,13 @@ constexpr int site_level(int i, int k) {
 // Two waves per SIMD at least: the 64-AP history with 16 folds sits just
 // above the 256 registers of that occupancy, and holding it there costs a
 // few rematerialisations, not spills.
-template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
+//
+// SRCX: the entry's data are delay spectra X[b][t][k_f] (M bins per AP,
+// written by the delay-transform kernel with calibration and dedispersion
+// applied), not visibilities: the wave of class c owns the contiguous bins
+// 64 c + m and reads its 512-byte segment of each AP, and the kernel only
+// does the rate transforms and peaks (AP energies come with the spectra).
+template <int PT, int LOGWMAX, int HFMAX, bool DUMP, bool SRCX>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DUMP ? 1 : 2)))
 fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   constexpr int WMAX = 1 << LOGWMAX;
@@ -277,11 +283,29 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
     return make_float2(ok ? x.x : 0.f, ok ? x.y : 0.f);
   };
 
-  float2 pre[PD][HFMAX];
-  static_for<0, PD>([&](auto di) {
-    constexpr int d = decltype(di)::value;
-    load_ap(own_lo + d, pre[d]);
-  });
+  float2 pre[SRCX ? 1 : PD][HFMAX];
+  if constexpr (!SRCX) {
+    static_for<0, PD>([&](auto di) {
+      constexpr int d = decltype(di)::value;
+      load_ap(own_lo + d, pre[d]);
+    });
+  }
+  // spectra in: this class's 64 bins of AP t, PDX APs prefetched
+  constexpr int PDX = 4;
+  static_assert(!SRCX || P % PDX == 0, "period");
+  const uint32_t xrow = static_cast<uint32_t>(M) * sizeof(float2);
+  const auto xrs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2*>(xb), static_cast<short>(0),
+      static_cast<int>(static_cast<uint32_t>(T) * xrow), kBufferWord3);
+  auto load_x = [&](int t) {
+    return ld_buffer(xrs, lane8 + static_cast<uint32_t>(min(t, T - 1)) * xrow,
+                     static_cast<uint32_t>(cls) * 64 * sizeof(float2));
+  };
+  float2 prex[SRCX ? PDX : 1];
+  if constexpr (SRCX) {
+#pragma unroll
+    for (int d = 0; d < PDX; ++d) prex[d] = load_x(own_lo + d);
+  }
   // full search: the last 2P APs of this lane's bin.  Delay-only search:
   // instead, per length 2^L the coherent sums of the windows that ended in
   // the last 2P APs (sum[L][P + i] for a window ending at position i of the
@@ -307,7 +331,11 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
                                   : a.epart);
   const int t_emit = a.t_emit;
   const uint32_t own_n = static_cast<uint32_t>(own_hi - own_lo);
-  const uint32_t kf_top = 0xFFFFFFFFu - static_cast<uint32_t>(cls);  // peak_partial's k_f base
+  // bin of lane m: R m + c (visibilities in, bins interleaved over the
+  // classes by the cross-lane transform) or 64 c + m (spectra in)
+  const int kf_step = SRCX ? 1 : R;
+  const int my_bin = SRCX ? 64 * cls + lane : cls + R * lane;
+  const uint32_t kf_top = 0xFFFFFFFFu - static_cast<uint32_t>(SRCX ? 64 * cls : cls);
   int pidx[LOGWMAX + 1];
   bool on[LOGWMAX + 1];
   int64_t gidx[LOGWMAX + 1];
@@ -320,7 +348,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
     if constexpr (DUMP) {
       if (lvl >= 0)
         gidx[L] = a.dump_base + static_cast<int64_t>(b) * a.grid_per_bl + a.lvl_goff[lvl] -
-                  static_cast<int64_t>(a.lvl_j0[lvl]) * (PT << L) * M + (cls + R * lane);
+                  static_cast<int64_t>(a.lvl_j0[lvl]) * (PT << L) * M + my_bin;
     }
   }
 
@@ -348,7 +376,13 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
       // Samples outside the data (past the scan's end, lanes past a band
       // narrower than the fold) are zeroed on a uniform branch, so APs with
       // none spend nothing on it.
-      if constexpr (i % G == 0) {
+      if constexpr (SRCX) {
+        float2 z = prex[i % PDX];
+        if (t >= T) z = make_float2(0.f, 0.f);
+        prex[i % PDX] = load_x(t + PDX);
+        if constexpr (PT > 0) hist[P + i] = z;
+        else sum[0][P + i] = z;
+      } else if constexpr (i % G == 0) {
         float2 z[G];
         static_for<0, G>([&](auto di) {
           constexpr int e = decltype(di)::value;
@@ -424,7 +458,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
           constexpr int d = (i + 1 - W) / s;  // start - p0, in strides
           const int start = t + 1 - W;
           if (on[L] && t_ok && static_cast<uint32_t>(start - own_lo) < own_n) {
-            const uint64_t pk = peak_partial(key[k], mx[k], kf_top, R);
+            const uint64_t pk = peak_partial(key[k], mx[k], kf_top, kf_step);
             if (lane == 0) {
               pb[L][d] = pk;
               epb[L][d] = ps[k];
@@ -448,7 +482,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
               }
               const uint32_t key = window_key<L, PT, DUMP>(
                   [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
-              const uint64_t pk = peak_partial(key, wave_max_u32(key), kf_top, R);
+              const uint64_t pk = peak_partial(key, wave_max_u32(key), kf_top, kf_step);
               if (lane == 0) pb[L][d] = pk;
             }
           }
@@ -466,15 +500,16 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
 
 // Launches the instantiation, or with occ set, stores the work groups (one
 // wave each) it keeps resident per CU and launches nothing.
-template <int PT, int LOGWMAX, int HFMAX, bool DUMP>
+template <int PT, int LOGWMAX, int HFMAX, bool DUMP, bool SRCX = false>
 hipError_t launch_fused_t(const FusedArgs* tab, int n_tab, int64_t blocks, hipStream_t st,
                           int* occ) {
   if (occ)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        occ, reinterpret_cast<const void*>(&fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP>), 64, 0);
+        occ, reinterpret_cast<const void*>(&fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP, SRCX>),
+        64, 0);
   if (blocks == 0 || n_tab == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP>),
+  hipLaunchKernelGGL((fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP, SRCX>),
                      dim3(static_cast<unsigned>(blocks)), dim3(64), 0, st, tab, n_tab);
   return hipGetLastError();
 }

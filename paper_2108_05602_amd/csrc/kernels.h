@@ -136,10 +136,13 @@ int fused_period(int w_max);
 int64_t fused_blocks(const FusedArgs& a);
 // Fold class (4, 8 or 16 folds of 64 channels per lane) serving F channels.
 int fused_fold_class(int F);
-// d_tab: n_tab entries in device memory; hf_max: the largest entry hf;
-// pad_t = 0 selects the delay-only search (rate bin 0 only).  With occ set,
-// nothing is launched: *occ receives the chosen instantiation's resident
-// work groups (of one wave) per CU.
+// The fold class value that selects the kernel reading delay spectra
+// (entries' vis = X[b][t][M], F = M, no gains or shifts).
+constexpr int kFoldSpectra = 0;
+// d_tab: n_tab entries in device memory; hf_max: the largest entry hf, or
+// kFoldSpectra; pad_t = 0 selects the delay-only search (rate bin 0 only).
+// With occ set, nothing is launched: *occ receives the chosen
+// instantiation's resident work groups (of one wave) per CU.
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
                         int w_max, int hf_max, bool dump, hipStream_t st, int* occ = nullptr);
 hipError_t launch_finalize(const FinalizeArgs* d_tab, int n_tab, int64_t n_windows,

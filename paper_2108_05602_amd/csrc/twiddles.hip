@@ -8,7 +8,6 @@
 
 namespace fringe {
 
-namespace {
 
 constexpr int kTwLogMin = 6, kTwLogMax = 12;
 constexpr int kTwTotal = (1 << (kTwLogMax + 1)) - (1 << kTwLogMin);
@@ -26,12 +25,18 @@ struct TwAll {
   }
 };
 
-__device__ const TwAll kTwAll{};
+namespace {
 
 constexpr int kMaxDevices = 64;
 const float2* g_tw_base[kMaxDevices] = {};
 
 }  // namespace
+
+// External linkage: a device variable that no kernel of this file reads is
+// kept in the code object (where the runtime finds it by name) only if it is
+// externally visible (so not const: a const variable at namespace scope
+// has internal linkage).
+__device__ TwAll kTwAll{};
 
 // Device address of the table for M points on the current device (the
 // symbol's address, looked up once per device).
