@@ -60,6 +60,7 @@ __all__ = [
     "search_baseline",
     "search_scan",
     "calibrate",
+    "autospectrum_gains",
     "dedisperse",
     "TABLE_DTYPE",
 ]
@@ -286,6 +287,31 @@ def calibrate(vis: np.ndarray, gains) -> np.ndarray:
     if g.shape != (vis.shape[0], vis.shape[2]):
         raise ValueError("gains must have shape (baselines, channels)")
     return vis * g[:, None, :]
+
+
+def autospectrum_gains(auto, pairs) -> np.ndarray:
+    """Per baseline (i, j) and frequency point f, the amplitude normalisation
+    by the two stations' auto-spectrum dispersions,
+
+        g[b, f] = (abar_i^2[f] * abar_j^2[f]) ** (-1/4),
+
+    abar_i^2[f] being the mean over station i's auto-spectra a_i[k, f] of
+    their squares (0 where either station's is 0: the channel is flagged).
+    Paper: section "Fringe fitting" (each frequency point's amplitude
+    normalised, as in the Mk4 format of HOPS, by the auto-spectrum
+    dispersion of the two stations).  auto has shape (n_stations,
+    n_spectra, F), real; pairs gives (i, j) per baseline.  The result, shape
+    (B, F), serves as the gains of calibrate / search_scan."""
+    a = np.asarray(auto, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("auto must have shape (stations, spectra, channels)")
+    disp = np.mean(a * a, axis=1)                    # abar^2, (n_stations, F)
+    out = np.zeros((len(pairs), a.shape[2]))
+    for b, (i, j) in enumerate(pairs):
+        prod = disp[i] * disp[j]
+        pos = prod > 0.0
+        out[b, pos] = prod[pos] ** -0.25
+    return out
 
 
 def dedisperse(vis: np.ndarray, shifts) -> np.ndarray:

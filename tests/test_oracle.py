@@ -224,6 +224,53 @@ def check_calibration(mod):
     assert np.array_equal(t_1, t_0)
 
 
+def check_autospectrum_normalization(mod):
+    """A fringe seen through the stations' bandpasses B_i(f) (cross
+    spectrum B_i B_j x, auto-spectra a_i = B_i^2) is flattened by the
+    normalisation, so the closed form of an on-grid fringe holds again:
+    amp = W*F, SNR = sqrt(W*F) on every baseline (the raw search falls
+    short of that SNR).  Auto-spectra that vary over time enter through the
+    mean of their squares: uniform ones scale amp by
+    (abar_i^2 abar_j^2)^(-1/4) and leave the SNR and the bins.  A station
+    with a zero auto-spectrum channel flags that channel."""
+    w, f, pf, pt, kt, kf = 4, 32, 4, 2, 3, 17
+    mt, mf = pt * w, pf * f
+    rng = np.random.default_rng(41)
+    pairs = [(0, 1), (0, 2), (1, 2)]
+    bp = rng.uniform(0.3, 2.0, (3, f))
+    u = np.arange(w)[:, None]
+    ff = np.arange(f)[None, :]
+    fr = np.exp(2j * np.pi * (kt * u / mt + kf * ff / mf))
+    vis = np.stack([bp[i] * bp[j] * fr for i, j in pairs])
+    auto = np.repeat((bp ** 2)[:, None, :], 5, axis=1)
+    g = mod.autospectrum_gains(auto, pairs)
+    t, _ = mod.search_scan(vis, [w], pf, pt, 1.0, 1.0, 1.0, gains=g)
+    t_raw, _ = mod.search_scan(vis, [w], pf, pt, 1.0, 1.0, 1.0)
+    for b in range(3):
+        assert (t["k_rate"][b], t["k_delay"][b]) == (kt, kf)
+        assert t["amp"][b] == pytest.approx(w * f, rel=1e-12)
+        assert t["snr"][b] == pytest.approx(math.sqrt(w * f), rel=1e-12)
+        assert t_raw["snr"][b] < 0.99 * math.sqrt(w * f)
+    # uniform auto-spectra varying over time: station 0 alternates c1, c2
+    c1, c2, d = 0.5, 2.0, 1.5
+    a2 = np.empty((2, 4, f))
+    a2[0, 0::2], a2[0, 1::2], a2[1] = c1, c2, d
+    xr = _rand_x(rng, 8, f)[None]
+    g2 = mod.autospectrum_gains(a2, [(0, 1)])
+    want = (((c1 ** 2 + c2 ** 2) / 2) * d ** 2) ** -0.25
+    assert np.allclose(g2, want, rtol=1e-14)
+    t2, _ = mod.search_scan(xr, [2, 4], pf, pt, 1.0, 1.0, 1.0, gains=g2)
+    t0_, _ = mod.search_scan(xr, [2, 4], pf, pt, 1.0, 1.0, 1.0)
+    assert np.array_equal(t2["k_rate"], t0_["k_rate"]) and np.array_equal(t2["k_delay"], t0_["k_delay"])
+    assert np.allclose(t2["amp"], want * t0_["amp"], rtol=1e-12)
+    assert np.allclose(t2["snr"], t0_["snr"], rtol=1e-12)
+    # a zero auto-spectrum channel of either station flags it on the baseline
+    a3 = np.ones((2, 3, f))
+    a3[1, :, 7] = 0.0
+    g3 = mod.autospectrum_gains(a3, [(0, 1), (0, 0)])
+    assert g3[0, 7] == 0.0 and np.all(np.delete(g3[0], 7) == 1.0) and np.all(g3[1] == 1.0)
+
+
 def check_dedispersion(mod):
     """A unit pulse that reaches channel f at AP t0 + d_f (dispersed) is
     restored by the shifts d_f: the one-AP window at t0 then holds every
@@ -252,7 +299,7 @@ def check_dedispersion(mod):
 ALL_CHECKS = [check_c1_closed_form, check_library_fft, check_parseval_and_energy,
               check_on_grid_fringe, check_ties_and_zero, check_window_counts,
               check_delay_only_closed_form, check_delay_only_library, check_delay_only_on_grid,
-              check_calibration, check_dedispersion]
+              check_calibration, check_autospectrum_normalization, check_dedispersion]
 
 
 @pytest.mark.parametrize("check", ALL_CHECKS, ids=lambda c: c.__name__)
@@ -394,7 +441,8 @@ def _mutant(**overrides):
     # rebind functions so their globals see the overrides
     for name in ("delay_spectra", "window_grid", "search_window", "search_baseline",
                  "search_scan", "window_starts", "grid_peak", "delay_only_row",
-                 "search_window_delay_only", "calibrate", "dedisperse"):
+                 "search_window_delay_only", "calibrate", "dedisperse",
+                 "autospectrum_gains"):
         f = getattr(fo, name)
         if name in overrides:
             continue
@@ -479,7 +527,27 @@ def _calibrate_conjugate(vis, gains):
     return fo.calibrate(vis, np.conj(np.asarray(gains)))
 
 
+def _auto_half_power(auto, pairs):
+    # (abar_i^2 abar_j^2)^(-1/2): the exponent of a power, not an amplitude
+    return fo.autospectrum_gains(auto, pairs) ** 2
+
+
+def _auto_mean_then_square(auto, pairs):
+    # the square of the mean auto-spectrum instead of the mean of its squares
+    a = np.asarray(auto, float)
+    m = a.mean(axis=1, keepdims=True)
+    return fo.autospectrum_gains(np.repeat(m, a.shape[1], axis=1), pairs)
+
+
+def _auto_one_station(auto, pairs):
+    # the first station's dispersion taken twice
+    return fo.autospectrum_gains(auto, [(i, i) for i, _ in pairs])
+
+
 @pytest.mark.parametrize("overrides", [
+    dict(autospectrum_gains=_auto_half_power),
+    dict(autospectrum_gains=_auto_mean_then_square),
+    dict(autospectrum_gains=_auto_one_station),
     dict(calibrate=_calibrate_conjugate),
     dict(dedisperse=_dedisperse_backwards),
     dict(delay_only_row=_delay_only_incoherent),
@@ -490,7 +558,8 @@ def _calibrate_conjugate(vis, gains):
     dict(grid_peak=_peak_last_tie),
     dict(window_starts=_starts_full_stride),
     dict(delay_spectra=_transposed_freq),
-], ids=["calibration-conjugate", "dedispersion-backwards", "delay-only-incoherent", "delay-only-grid-energy", "delay-sign", "rate-pad",
+], ids=["autospectrum-half-power", "autospectrum-mean-then-square", "autospectrum-one-station",
+        "calibration-conjugate", "dedispersion-backwards", "delay-only-incoherent", "delay-only-grid-energy", "delay-sign", "rate-pad",
         "energy-sum", "tie-last", "stride", "freq-order"])
 def test_planted_mistake_is_caught(overrides):
     assert _fails(_mutant(**overrides))
