@@ -237,6 +237,30 @@ int fringe_plan_info(fringe_plan_t plan, fringe_plan_summary* out);
  * NULL is ignored. */
 void fringe_plan_destroy(fringe_plan_t plan);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * search of fringe_plan + fringe_search + candidates_get for ONE scan, same
+ * kernels and same results, with no plan and no allocation of any kind:
+ * every work buffer lives in a static device array of the library
+ * (64 MiB per GPU, held by each GPU the library runs on until the process
+ * ends).  scan and params as for fringe_plan (params->window_aps up to 64
+ * APs; hbm_budget_bytes and max_candidates ignored; flags 0 or
+ * FRINGE_DELAY_ONLY).  d_vis: the scan's device cube (layout above);
+ * d_out: device array of capacity records that receives the first
+ * min(capacity, total) candidates in key order; d_total: device int64 that
+ * receives the total count.  The caller owns all three and keeps them valid
+ * until the work on hip_stream (a hipStream_t; NULL = default stream) has
+ * completed.  Asynchronous.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race, so
+ * the caller orders them.  Errors: FRINGE_E_INVALID for null pointers, a
+ * negative capacity or other flags; the errors of fringe_plan for the
+ * shape; FRINGE_E_NOMEM when the scan's work buffers (about 8 B per window
+ * and 64-bin delay class, 16 B per window, 4 B per AP and baseline) exceed
+ * the 64 MiB; FRINGE_E_HIP for a failed launch. */
+int fringe_search_noalloc(const fringe_scan_desc* scan, const fringe_params* params,
+                          const fringe_cf32* d_vis, fringe_candidate* d_out, int64_t capacity,
+                          int64_t* d_total, void* hip_stream);
+
 /* Static description of an error code. */
 const char* fringe_strerror(int code);
 

@@ -46,7 +46,7 @@ ENTRY_POINTS = (
     "fringe_plan_info", "fringe_set_gains", "fringe_set_shifts", "fringe_dedisperse",
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
     "fringe_match", "fringe_localize", "fringe_delay_partials",
-    "fringe_probe_fma", "fringe_probe_copy",
+    "fringe_probe_fma", "fringe_probe_copy", "fringe_search_noalloc",
 )
 
 
@@ -148,6 +148,8 @@ def load(path: Optional[str] = None):
                                       c_void_p]
     lib.fringe_probe_fma.argtypes = [c_int64, c_int32, c_void_p, dp, c_void_p]
     lib.fringe_probe_copy.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
+    lib.fringe_search_noalloc.argtypes = [POINTER(fringe_scan_desc), POINTER(fringe_params),
+                                          c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
     for name in ENTRY_POINTS:
         if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error"):
             getattr(lib, name).restype = c_int
@@ -306,6 +308,22 @@ def fringe_set_shifts(plan: int, scan: int, d_shifts) -> None:
     lib = load()
     _check(lib.fringe_set_shifts(c_void_p(plan), c_int32(int(scan)), c_void_p(d_shifts or None)),
            "fringe_set_shifts")
+
+
+def fringe_search_noalloc(scan: dict, window_aps, d_vis: int, d_out: int, capacity: int,
+                          d_total: int, pad_freq=4, pad_time=2, snr_threshold=4.5, flags=0,
+                          stream: int = 0) -> None:
+    """Enqueue the allocation-free search of one scan: candidates into the
+    device array d_out (capacity records), the total into the device int64
+    d_total."""
+    lib = load()
+    sa = _scan_array([scan])
+    p, keep = _params(window_aps, pad_freq, pad_time, snr_threshold, 0, 0, flags)
+    _check(lib.fringe_search_noalloc(sa, ctypes.byref(p), c_void_p(int(d_vis)),
+                                     c_void_p(int(d_out) if d_out else None), int(capacity),
+                                     c_void_p(int(d_total)),
+                                     c_void_p(int(stream) if stream else None)),
+           "fringe_search_noalloc")
 
 
 def fringe_plan_destroy(plan: int) -> None:

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -169,7 +170,7 @@ uint64_t per_baseline_scratch(const ScanInfo& s, bool streaming, bool delay_only
 }
 
 int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* p,
-                      Sizing* out) {
+                      Sizing* out, bool allow_spectra = true) {
   if (!scans || !p || !out) return fail(FRINGE_E_INVALID, "null argument");
   if (n_scans < 1) return fail(FRINGE_E_INVALID, "n_scans must be >= 1 (got %d)", n_scans);
   if (!p->window_aps) return fail(FRINGE_E_INVALID, "window_aps is null");
@@ -287,8 +288,8 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     // are one window each)
     const bool x_fits =
         (int64_t(data_len(si, sz.streaming)) + 1) * M * int64_t(sizeof(float2)) < (int64_t(1) << 32);
-    si.spectra = !sz.fused || (!sz.delay_only && !(p->flags & FRINGE_PLAIN) && x_fits &&
-                               fused_fold_class(si.F) >= kSpectraMinFold);
+    si.spectra = !sz.fused || (allow_spectra && !sz.delay_only && !(p->flags & FRINGE_PLAIN) &&
+                               x_fits && fused_fold_class(si.F) >= kSpectraMinFold);
     si.x_short = si.spectra && x_fits;
     if (sz.streaming)
       sz.stage_bytes += 2 * uint64_t(d.n_baselines) * si.stage_len * F * sizeof(float2);
@@ -622,20 +623,45 @@ int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, Ca
   return FRINGE_OK;
 }
 
-FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan& c,
+// The device buffers a search's descriptor tables point into.
+struct WorkBufs {
+  float2* X = nullptr;                // delay spectra of the slab (spectra mode)
+  float* e = nullptr;                 // AP energies
+  uint64_t* part = nullptr;           // per-class partial peaks
+  float* epart = nullptr;             // per-class power sums (delay-only)
+  WindowRec* table = nullptr;         // window records
+  float2* grid = nullptr;             // grid dump
+  const float2* tw = nullptr;         // twiddles of the scan's M_f
+  const float2* gains = nullptr;      // the scan's [n_baselines][F] gains
+  const int32_t* shifts = nullptr;    // the scan's [F] shifts
+};
+
+WorkBufs plan_bufs(const fringe_plan_s* p, int scan) {
+  WorkBufs w;
+  w.X = p->X;
+  w.e = p->e;
+  w.part = p->part;
+  w.epart = p->epart;
+  w.table = p->table;
+  w.grid = p->grid;
+  w.tw = p->tw[p->sz.scans[size_t(scan)].log_m];
+  w.gains = p->gains.empty() ? nullptr : p->gains[size_t(scan)];
+  w.shifts = p->shifts.empty() ? nullptr : p->shifts[size_t(scan)];
+  return w;
+}
+
+FusedArgs fused_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& si, const CallScan& c,
                       const Unit& u, const float2* data, int64_t vis_stride) {
-  const Sizing& z = p->sz;
   FusedArgs fu{};
   fu.vis = data ? data + int64_t(u.b0) * vis_stride : nullptr;
-  const float2* g = p->gains.empty() ? nullptr : p->gains[u.scan];
-  fu.gains = g ? g + int64_t(u.b0) * si.F : nullptr;
-  fu.shifts = p->shifts.empty() ? nullptr : p->shifts[u.scan];
+  fu.gains = w.gains ? w.gains + int64_t(u.b0) * si.F : nullptr;
+  fu.shifts = w.shifts;
   fu.vis_stride = vis_stride;
-  fu.part = p->part + u.part_off;
-  fu.epart = p->epart ? p->epart + u.part_off : nullptr;
-  fu.e = p->e + u.e_off;
-  fu.dump = p->grid;
-  fu.tw = p->tw[si.log_m];
+  fu.part = w.part + u.part_off;
+  fu.epart = w.epart ? w.epart + u.part_off : nullptr;
+  fu.e = w.e + u.e_off;
+  fu.dump = w.grid;
+  fu.tw = w.tw;
   fu.slab_windows = int64_t(u.nb) * c.nwb;
   fu.dump_base = si.grid_off + int64_t(u.b0) * si.grid_per_bl;
   fu.grid_per_bl = si.grid_per_bl;
@@ -658,7 +684,7 @@ FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan
   if (si.x_short) {
     // the short windows read the slab's delay spectra, into which the
     // delay-transform kernel has applied gains and shifts
-    fu.vis = p->X;
+    fu.vis = w.X;
     fu.vis_stride = int64_t(c.T) * si.M;
     fu.F = si.M;
     fu.gains = nullptr;
@@ -667,13 +693,13 @@ FusedArgs fused_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan
   return fu;
 }
 
-FinalizeArgs finalize_entry(const fringe_plan_s* p, const ScanInfo& si, const CallScan& c,
-                            const Unit& u) {
+FinalizeArgs finalize_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& si,
+                            const CallScan& c, const Unit& u) {
   FinalizeArgs fa{};
-  fa.part = p->part + u.part_off;
-  fa.epart = p->epart ? p->epart + u.part_off : nullptr;
-  fa.e = p->e + u.e_off;
-  fa.table = p->table + c.win_off + int64_t(u.b0) * c.nwb;
+  fa.part = w.part + u.part_off;
+  fa.epart = w.epart ? w.epart + u.part_off : nullptr;
+  fa.e = w.e + u.e_off;
+  fa.table = w.table + c.win_off + int64_t(u.b0) * c.nwb;
   fa.slab_windows = int64_t(u.nb) * c.nwb;
   fa.n_kb = si.n_kb;
   fa.nb = u.nb;
@@ -683,7 +709,7 @@ FinalizeArgs finalize_entry(const fringe_plan_s* p, const ScanInfo& si, const Ca
   fa.M = si.M;
   for (int l = 0; l <= kMaxLevels; ++l) fa.lvl_off[l] = int(c.lvl_off[l]);
   for (int l = 0; l < kMaxLevels; ++l) fa.lvl_j0[l] = c.lvl_j0[l];
-  fa.lv = p->sz.lv;
+  fa.lv = z.lv;
   return fa;
 }
 
@@ -748,20 +774,72 @@ int plain_tables(fringe_plan_s* p, const std::vector<const float2*>& data) {
           for (int l = 0; l <= kMaxLevels; ++l) one.lvl_off[l] = l <= li ? 0 : 1;
           Unit u{int(s), 0, 1, 0, 0};
           const float2* base = data[s] + (int64_t(b) * si.d.n_ap + j * stride) * si.F;
-          fus[i] = fused_entry(p, si, one, u, base, int64_t(si.d.n_ap) * si.F);
+          fus[i] = fused_entry(z, plan_bufs(p, int(s)), si, one, u, base,
+                               int64_t(si.d.n_ap) * si.F);
           fus[i].gains = p->gains[s] ? p->gains[s] + int64_t(b) * si.F : nullptr;
           fus[i].block_off = 0;
           // only this length: the shorter windows inside these W APs are
           // other entries' work
           for (int L = 0; L < 8; ++L) fus[i].lvl_of_log[L] = -1;
           fus[i].lvl_of_log[z.lv.logW[li]] = li;
-          fin[i] = finalize_entry(p, si, one, u);
+          fin[i] = finalize_entry(z, plan_bufs(p, int(s)), si, one, u);
           fin[i].table = p->table + c.win_off + int64_t(b) * c.nwb + c.lvl_off[li] + j;
           fin[i].win_begin = 0;
         }
       }
     }
   }
+  return FRINGE_OK;
+}
+
+// ---- the allocation-free search (fringe_search_noalloc) ----------------
+//
+// Every work buffer of the search (descriptors, per-class partial peaks, AP
+// energies, window records, compaction counts) lives in one static device
+// array per GPU, reached through the address hipGetSymbolAddress gives for
+// it on that device (the array's name is a host-side stand-in).
+
+constexpr uint64_t kNoAllocScratchBytes = uint64_t(64) << 20;
+constexpr int kMaxScratchDevices = 64;
+
+// The descriptors of one search, written into the scratch by a kernel that
+// takes them as its argument (no host-to-device copy).
+struct NoAllocDesc {
+  ScanDev sd;
+  FusedArgs fa;
+  FinalizeArgs fi;
+};
+
+__global__ void put_desc_kernel(NoAllocDesc d, NoAllocDesc* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The scratch's device address on the current device, looked up the first
+// time this device calls.
+int scratch_base(char** out) {
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(FRINGE_E_UNSUPPORTED, "device %d: the no-alloc scratch serves devices 0-%d", dev,
+                kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (he != hipSuccess || !ptr) return hip_fail(he, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
   return FRINGE_OK;
 }
 
@@ -958,11 +1036,11 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
         const ScanInfo& si = z.scans[u.scan];
         const CallScan& c = p->call[u.scan];
         const int64_t stride = int64_t(z.streaming ? si.stage_len : si.d.n_ap) * si.F;
-        fus[ui] = fused_entry(p, si, c, u, data[u.scan], stride);
+        fus[ui] = fused_entry(z, plan_bufs(p, u.scan), si, c, u, data[u.scan], stride);
         if (!p->call_present[u.scan]) fus[ui].n_pairs = 0;
         fus[ui].block_off = grp_blocks[g];
         grp_blocks[g] += fused_blocks(fus[ui]);
-        fin[ui] = finalize_entry(p, si, c, u);
+        fin[ui] = finalize_entry(z, plan_bufs(p, u.scan), si, c, u);
         if (!p->call_present[u.scan]) fin[ui].slab_windows = 0;
         fin[ui].win_begin = grp_windows[g];
         grp_windows[g] += fin[ui].slab_windows;
@@ -1307,6 +1385,102 @@ int fringe_plan_info(fringe_plan_t p, fringe_plan_summary* out) {
 }
 
 void fringe_plan_destroy(fringe_plan_t p) { release(p); }
+
+int fringe_search_noalloc(const fringe_scan_desc* scan, const fringe_params* params,
+                          const fringe_cf32* d_vis, fringe_candidate* d_out, int64_t capacity,
+                          int64_t* d_total, void* hip_stream) {
+  if (!scan || !params || !d_vis || !d_total)
+    return fail(FRINGE_E_INVALID, "null scan, params, visibility or count pointer");
+  if (capacity < 0 || (capacity > 0 && !d_out))
+    return fail(FRINGE_E_INVALID, "bad candidate buffer (capacity %lld)", (long long)capacity);
+  if (params->flags & ~uint32_t(FRINGE_DELAY_ONLY))
+    return fail(FRINGE_E_INVALID, "fringe_search_noalloc takes no flags but FRINGE_DELAY_ONLY");
+  fringe_params q = *params;
+  q.hbm_budget_bytes = 0;
+  q.max_candidates = 0;
+  Sizing z;
+  int rc = validate_and_size(scan, 1, &q, &z, /*allow_spectra=*/false);
+  if (rc != FRINGE_OK) return rc;
+  if (!z.fused)
+    return fail(FRINGE_E_UNSUPPORTED, "fringe_search_noalloc: windows of at most %d APs",
+                kFusedMaxWindow);
+  const ScanInfo& si0 = z.scans[0];
+  // work buffers, 256-byte aligned, in the scratch
+  const uint64_t n_win = uint64_t(z.n_windows);
+  const uint64_t n_blk = uint64_t(z.n_blocks);
+  const uint64_t b_desc = align_up(sizeof(NoAllocDesc));
+  const uint64_t b_part = align_up(size_t(si0.n_kb) * n_win * sizeof(uint64_t));
+  const uint64_t b_epart = z.delay_only ? align_up(size_t(si0.n_kb) * n_win * sizeof(float)) : 0;
+  const uint64_t b_e = align_up(size_t(si0.d.n_baselines) * si0.d.n_ap * sizeof(float));
+  const uint64_t b_table = align_up(n_win * sizeof(WindowRec));
+  const uint64_t b_cnt = align_up(n_blk * sizeof(int32_t));
+  const uint64_t b_off = align_up(n_blk * sizeof(int64_t));
+  const uint64_t need = b_desc + b_part + b_epart + b_e + b_table + b_cnt + b_off;
+  if (z.units.size() != 1 || need > kNoAllocScratchBytes)
+    return fail(FRINGE_E_NOMEM, "fringe_search_noalloc: the scan needs %llu bytes of work "
+                "buffers, the static scratch holds %llu",
+                (unsigned long long)need, (unsigned long long)kNoAllocScratchBytes);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int dev = 0, n_cu = 0;
+  hipError_t he;
+  if ((he = hipGetDevice(&dev)) != hipSuccess ||
+      (he = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(he, "device attributes");
+  const int pad_t_kernel = z.delay_only ? 0 : params->pad_time;
+  if ((rc = tune_chunks(&z, std::max(1, n_cu), pad_t_kernel)) != FRINGE_OK) return rc;
+  char* base = nullptr;
+  if ((rc = scratch_base(&base)) != FRINGE_OK) return rc;
+  const ScanInfo& si = z.scans[0];
+  WorkBufs w;
+  char* cur = base + b_desc;
+  w.part = reinterpret_cast<uint64_t*>(cur);
+  cur += b_part;
+  w.epart = z.delay_only ? reinterpret_cast<float*>(cur) : nullptr;
+  cur += b_epart;
+  w.e = reinterpret_cast<float*>(cur);
+  cur += b_e;
+  w.table = reinterpret_cast<WindowRec*>(cur);
+  cur += b_table;
+  int32_t* blk_counts = reinterpret_cast<int32_t*>(cur);
+  cur += b_cnt;
+  int64_t* blk_offsets = reinterpret_cast<int64_t*>(cur);
+  if ((he = twiddles_for(si.M, &w.tw)) != hipSuccess) return hip_fail(he, "twiddle table");
+  CallScan c = si.full;
+  c.win_off = 0;
+  const Unit& u = z.units[0];
+  NoAllocDesc d{};
+  d.sd = make_scan_dev(si, c);
+  d.fa = fused_entry(z, w, si, c, u, reinterpret_cast<const float2*>(d_vis),
+                     int64_t(si.d.n_ap) * si.F);
+  d.fa.block_off = 0;
+  d.fi = finalize_entry(z, w, si, c, u);
+  d.fi.win_begin = 0;
+  NoAllocDesc* dd = reinterpret_cast<NoAllocDesc*>(base);
+  hipLaunchKernelGGL(put_desc_kernel, dim3(1), dim3(64), 0, st, d, dd);
+  if ((he = hipGetLastError()) != hipSuccess) return hip_fail(he, "descriptor launch");
+  if (n_win > 0) {
+    if ((he = launch_fused(&dd->fa, 1, fused_blocks(d.fa), pad_t_kernel, z.w_max, u.fc, false,
+                           st)) != hipSuccess)
+      return hip_fail(he, "fused search launch");
+    if ((he = launch_finalize(&dd->fi, 1, int64_t(n_win), st)) != hipSuccess)
+      return hip_fail(he, "finalize launch");
+  }
+  CompactArgs ca{};
+  ca.table = w.table;
+  ca.n_windows = int64_t(n_win);
+  ca.threshold = params->snr_threshold;
+  ca.blk_counts = blk_counts;
+  ca.blk_offsets = blk_offsets;
+  ca.n_blocks = int64_t(n_blk);
+  ca.out = d_out;
+  ca.max_out = capacity;
+  ca.total = d_total;
+  ca.scans = &dd->sd;
+  ca.n_scans = 1;
+  ca.lv = z.lv;
+  if ((he = launch_compact(ca, st)) != hipSuccess) return hip_fail(he, "compaction launch");
+  return FRINGE_OK;
+}
 
 }  // extern "C"
 
