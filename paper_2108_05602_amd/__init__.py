@@ -12,7 +12,7 @@ from .binding import (CANDIDATE_DTYPE, PULSE_DTYPE, FRINGE_DELAY_ONLY, FRINGE_DU
                       candidates_get, fringe_grid_get, fringe_last_error, fringe_plan,
                       fringe_plan_check, fringe_plan_destroy, fringe_plan_info, fringe_profile_get, fringe_search,
                       fringe_set_gains, fringe_set_shifts, fringe_dedisperse, fringe_match, fringe_localize,
-                      fringe_delay_partials,
+                      fringe_delay_partials, fringe_autospectrum_gains, fringe_search_noalloc,
                       fringe_strerror, fringe_window_id, fringe_windows_get, load)
 
 __all__ = [
@@ -20,6 +20,6 @@ __all__ = [
     "candidates_get", "fringe_grid_get", "fringe_last_error", "fringe_plan",
     "fringe_plan_check", "fringe_plan_destroy", "fringe_plan_info", "fringe_profile_get", "fringe_search",
     "fringe_set_gains", "fringe_set_shifts", "fringe_dedisperse", "fringe_match", "fringe_localize",
-    "fringe_delay_partials",
+    "fringe_delay_partials", "fringe_autospectrum_gains", "fringe_search_noalloc",
     "fringe_strerror", "fringe_window_id", "fringe_windows_get", "load",
 ]

@@ -1,5 +1,5 @@
-"""ctypes binding of libfringe (include/fringe.h, include/fringe_match.h,
-include/fringe_probe.h): argument marshalling only.
+"""ctypes binding of libfringe (include/fringe.h, include/fringe_calib.h,
+include/fringe_match.h, include/fringe_probe.h): argument marshalling only.
 
 Every function here has the name of the C entry point it calls and does no
 computation of its own; all search work runs in the library's HIP kernels,
@@ -47,6 +47,7 @@ ENTRY_POINTS = (
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
     "fringe_match", "fringe_localize", "fringe_delay_partials",
     "fringe_probe_fma", "fringe_probe_copy", "fringe_search_noalloc",
+    "fringe_autospectrum_gains",
 )
 
 
@@ -150,6 +151,8 @@ def load(path: Optional[str] = None):
     lib.fringe_probe_copy.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
     lib.fringe_search_noalloc.argtypes = [POINTER(fringe_scan_desc), POINTER(fringe_params),
                                           c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+    lib.fringe_autospectrum_gains.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                              c_int32, c_void_p, c_void_p, c_void_p]
     for name in ENTRY_POINTS:
         if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error"):
             getattr(lib, name).restype = c_int
@@ -324,6 +327,21 @@ def fringe_search_noalloc(scan: dict, window_aps, d_vis: int, d_out: int, capaci
                                      c_void_p(int(d_total)),
                                      c_void_p(int(stream) if stream else None)),
            "fringe_search_noalloc")
+
+
+def fringe_autospectrum_gains(d_auto: int, n_stations: int, n_spectra: int, n_freq: int,
+                              d_pairs: int, n_baselines: int, d_gains_in, d_gains_out: int,
+                              stream: int = 0) -> None:
+    """Enqueue the auto-spectrum normalisation gains (include/fringe_calib.h):
+    d_gains_out[b][f] = g_in[b][f] * (abar_i^2 abar_j^2)^(-1/4); device
+    addresses as integers (d_gains_in 0/None: unit gains)."""
+    _check(load().fringe_autospectrum_gains(c_void_p(int(d_auto)), int(n_stations),
+                                            int(n_spectra), int(n_freq), c_void_p(int(d_pairs)),
+                                            int(n_baselines),
+                                            c_void_p(int(d_gains_in) if d_gains_in else None),
+                                            c_void_p(int(d_gains_out)),
+                                            c_void_p(int(stream) if stream else None)),
+           "fringe_autospectrum_gains")
 
 
 def fringe_plan_destroy(plan: int) -> None:

@@ -221,3 +221,14 @@ def test_dm_shifts():
     assert d[0] == int(round(want)) and d[-1] == 0
     assert np.all(np.diff(d) <= 0) and d.dtype == np.int32
     assert np.all(dm_shifts(0.0, f, 1e-3) == 0)
+
+
+def test_autospectrum_gains_argument_checks():
+    """Refused on the host, before any device work."""
+    g = F.fringe_autospectrum_gains
+    assert _code(lambda: g(0, 3, 2, 64, 0x1000, 3, 0, 0x2000)) == B.FRINGE_E_INVALID
+    assert _code(lambda: g(0x1000, 0, 2, 64, 0x2000, 3, 0, 0x3000)) == B.FRINGE_E_INVALID
+    assert _code(lambda: g(0x1000, 3, 2, 64, 0x2000, 0, 0, 0x3000)) == B.FRINGE_E_INVALID
+    # gains_in overlapping gains_out without being the same array
+    assert _code(lambda: g(0x1000, 3, 2, 64, 0x2000, 3, 0x100000, 0x100008)) == B.FRINGE_E_INVALID
+    assert "overlap" in F.fringe_last_error()
