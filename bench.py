@@ -534,7 +534,8 @@ C3_WORKLOAD = ("Batched uneven: 200 scans of 10-120 s (1.024 ms APs), 3-12 stati
                "the device in HBM-budgeted waves, one plan per wave")
 
 
-def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None):
+def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=True,
+                compare_default=True):
     """The batched uneven workload: per wave, generate its scans on the
     device, build one plan, search it `warmup` times untimed and `steps`
     times timed (each search with its candidate copy, bracketed by device
@@ -551,6 +552,12 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None):
     p = synth.C3_PARAMS
     groups = sd.waves(specs, int(wave_gb * 1e9))
     st = torch.cuda.current_stream()
+    flags = F.FRINGE_PROFILE | (F.FRINGE_AUTOTUNE if autotune else 0)
+    if autotune:
+        F.fringe_tune_clear()
+    plan_s = 0.0
+    entries = {}
+    cmp = None
     step_s = [0.0] * steps
     fused_ms = fin_ms = comp_ms = 0.0
     fused_n = 0
@@ -567,9 +574,14 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None):
         torch.cuda.synchronize()
         gen_s = time.perf_counter() - t0
         descs = [specs[i].desc() for i in idx]
+        t0 = time.perf_counter()
         with F.Plan(descs, p["window_aps"], pad_freq=p["pad_freq"], pad_time=p["pad_time"],
                     snr_threshold=p["snr_threshold"], max_candidates=1 << 22,
-                    flags=F.FRINGE_PROFILE) as plan:
+                    flags=flags) as plan:
+            plan_s += time.perf_counter() - t0
+            if autotune:
+                for e in plan.tuning():
+                    entries[e["n_freq"]] = e
             ptrs = [t.data_ptr() for t in tens]
             for _ in range(warmup):
                 plan.search(ptrs, st.cuda_stream)
@@ -590,6 +602,26 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None):
                 fin_ms += pr["finalize_ms"]
                 comp_ms += pr["compact_ms"]
             nw = plan.info()["n_windows"]
+        if autotune and compare_default and wi == 0:
+            # the same wave with the default configurations, timed alike
+            with F.Plan(descs, p["window_aps"], pad_freq=p["pad_freq"], pad_time=p["pad_time"],
+                        snr_threshold=p["snr_threshold"], max_candidates=1 << 22,
+                        flags=F.FRINGE_PROFILE) as dplan:
+                dplan.search(ptrs, st.cuda_stream)
+                dplan.candidates()
+                dt_def = []
+                for _ in range(max(2, min(steps, 5))):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    dplan.search(ptrs, st.cuda_stream)
+                    dplan.candidates()
+                    torch.cuda.synchronize()
+                    dt_def.append(time.perf_counter() - t1)
+            cmp = {"wave": 0, "scans": len(idx), "default_ms": float(np.median(dt_def)) * 1e3,
+                   "tuned_ms": float(np.median(wt)) * 1e3}
+            cmp["gain"] = cmp["default_ms"] / cmp["tuned_ms"]
+            log(f"C3 wave 0, default configurations: {cmp['default_ms']:.1f} ms vs tuned "
+                f"{cmp['tuned_ms']:.1f} ms")
         n_windows += nw
         n_cands += len(c)
         wb = 0
@@ -647,6 +679,9 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None):
                                "compact_ms": comp_ms / steps},
         "tflops_algorithmic_step": flops_step / (ms / 1e3) / 1e12,
         "hbm_gbs_algorithmic": cube / (ms / 1e3) / 1e9,
+        "autotune": {"enabled": autotune, "plan_s_total": plan_s,
+                     "entries": [entries[k] for k in sorted(entries)],
+                     "tuned_vs_default": cmp},
     }
 
 
@@ -854,6 +889,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="headline plans with the default configurations (no tuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the EVN search, copy a MIB-MiB device buffer once (a plain copy "
                          "kernel of known size for scaling hardware byte counters)")
@@ -878,7 +915,8 @@ def main():
     sample = []
     if args.only != "c2":
         h = c3_headline(args.steps, args.warmup, args.wave_gb, n_scans=args.c3_scans,
-                        cpu_sample=None if args.no_cpu_baseline else sample)
+                        cpu_sample=None if args.no_cpu_baseline else sample,
+                        autotune=not args.no_autotune)
         out["value"] = h["value"]
         out["ms_per_step"] = h["ms_per_step"]
         out["config"] = {"workload": C3_WORKLOAD if args.c3_scans == 200 else
@@ -887,7 +925,7 @@ def main():
                          "waves": len(h["waves"]), "parallelism": "single GPU"}
         out["roofline"] = h["roofline"]
         for k in ("kernel_ms_per_step", "tflops_algorithmic_step", "hbm_gbs_algorithmic",
-                  "candidates", "waves"):
+                  "candidates", "waves", "autotune"):
             out[k] = h[k]
         out["hbm_frac_algorithmic"] = h["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
         log(f"C3 headline: {h['value'] / 1e6:.1f} M windows/s, {h['ms_per_step']:.1f} ms per step, "

@@ -74,6 +74,17 @@ extern "C" {
                                  /* power over those bins; k_rate = 0, rate_hz = 0 */
                                  /* and pad_time unused.  Windows of at most 64    */
                                  /* APs; not with DUMP_GRID.                       */
+#define FRINGE_AUTOTUNE   0x40u  /* plans with windows of at most 64 APs: every    */
+                                 /* class of scans (F, pads, longest window, on    */
+                                 /* this device kind) takes its search mode and    */
+                                 /* time chunk from the library's tune table; a    */
+                                 /* class missing from it is tuned when the plan   */
+                                 /* is made (each candidate timed on a synthetic   */
+                                 /* sample of the class's shape, about a second    */
+                                 /* per class; fringe_tune_load / _save keep the   */
+                                 /* table across processes).  The chunk does not   */
+                                 /* change results; the mode changes the delay     */
+                                 /* transform's rounding only.                     */
 
 /* One complex64 sample, identical in layout to torch.complex64 / numpy.complex64. */
 typedef struct { float re, im; } fringe_cf32;
@@ -232,6 +243,39 @@ int fringe_profile_get(fringe_plan_t plan, fringe_profile* out);
 
 /* Sizes of an existing plan. */
 int fringe_plan_info(fringe_plan_t plan, fringe_plan_summary* out);
+
+/* One entry of the tune table (FRINGE_AUTOTUNE): a class of scans and the
+ * launch configuration chosen for it on this kind of device. */
+typedef struct {
+  int32_t n_freq, pad_freq;    /* F = n_if * n_chan, M_f / F                     */
+  int32_t pad_time;            /* M_t / W; 0 for the delay-only search           */
+  int32_t log2_wmax;           /* longest window, at most 64 APs                 */
+  int32_t spectra;             /* 1: the delay spectra go through HBM and the    */
+                               /* rate kernels read them; 0: one fused kernel    */
+                               /* transforms and searches                        */
+  int32_t chunk;               /* APs per work item (plans on grids too small to */
+                               /* fill the device with it take less)             */
+  float ms_fused, ms_spectra;  /* the tuning sample's best time in each mode      */
+                               /* (ms; < 0: not a candidate)                      */
+} fringe_tune_entry;
+
+/* Merge the tune table stored in the JSON file at path (written by
+ * fringe_tune_save) into the library's; entries for other device kinds are
+ * kept but unused here.  Errors: FRINGE_E_INVALID for an unreadable or
+ * malformed file (the table is then unchanged). */
+int fringe_tune_load(const char* path);
+
+/* Write the library's tune table (every entry, every device kind) as JSON.
+ * Errors: FRINGE_E_INVALID when the file cannot be written. */
+int fringe_tune_save(const char* path);
+
+/* Empty the library's tune table. */
+void fringe_tune_clear(void);
+
+/* The tune entries a plan made with FRINGE_AUTOTUNE uses, one per class of
+ * its scans, into out[0..capacity); *n receives their number
+ * (FRINGE_E_CAPACITY if it exceeds capacity).  0 entries for other plans. */
+int fringe_plan_tuning(fringe_plan_t plan, fringe_tune_entry* out, int32_t capacity, int32_t* n);
 
 /* Release every resource of the plan (waits for its outstanding work).
  * NULL is ignored. */

@@ -39,6 +39,7 @@ FRINGE_PROFILE = 0x4
 FRINGE_PLAIN = 0x8
 FRINGE_GRAPH = 0x10
 FRINGE_DELAY_ONLY = 0x20
+FRINGE_AUTOTUNE = 0x40
 
 ENTRY_POINTS = (
     "fringe_plan_check", "fringe_plan", "fringe_search", "candidates_get",
@@ -47,7 +48,8 @@ ENTRY_POINTS = (
     "fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
     "fringe_match", "fringe_localize", "fringe_delay_partials",
     "fringe_probe_fma", "fringe_probe_copy", "fringe_search_noalloc",
-    "fringe_autospectrum_gains",
+    "fringe_autospectrum_gains", "fringe_tune_load", "fringe_tune_save", "fringe_tune_clear",
+    "fringe_plan_tuning",
 )
 
 
@@ -73,6 +75,12 @@ class fringe_candidate(Structure):
 class fringe_plan_summary(Structure):
     _fields_ = [("n_windows", c_int64), ("device_bytes", c_int64), ("scratch_bytes", c_int64),
                 ("max_window_ap", c_int32), ("slab_baselines", c_int32)]
+
+
+class fringe_tune_entry(Structure):
+    _fields_ = [("n_freq", c_int32), ("pad_freq", c_int32), ("pad_time", c_int32),
+                ("log2_wmax", c_int32), ("spectra", c_int32), ("chunk", c_int32),
+                ("ms_fused", c_float), ("ms_spectra", c_float)]
 
 
 class fringe_profile(Structure):
@@ -153,8 +161,15 @@ def load(path: Optional[str] = None):
                                           c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
     lib.fringe_autospectrum_gains.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p,
                                               c_int32, c_void_p, c_void_p, c_void_p]
+    lib.fringe_tune_load.argtypes = [c_char_p]
+    lib.fringe_tune_save.argtypes = [c_char_p]
+    lib.fringe_tune_clear.argtypes = []
+    lib.fringe_tune_clear.restype = None
+    lib.fringe_plan_tuning.argtypes = [c_void_p, POINTER(fringe_tune_entry), c_int32,
+                                       POINTER(c_int32)]
     for name in ENTRY_POINTS:
-        if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error"):
+        if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
+                        "fringe_tune_clear"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -344,6 +359,31 @@ def fringe_autospectrum_gains(d_auto: int, n_stations: int, n_spectra: int, n_fr
            "fringe_autospectrum_gains")
 
 
+def fringe_tune_load(path: str) -> None:
+    """Merge a JSON tune table (from fringe_tune_save) into the library's."""
+    _check(load().fringe_tune_load(os.fsencode(path)), "fringe_tune_load")
+
+
+def fringe_tune_save(path: str) -> None:
+    """Write the library's tune table as JSON."""
+    _check(load().fringe_tune_save(os.fsencode(path)), "fringe_tune_save")
+
+
+def fringe_tune_clear() -> None:
+    load().fringe_tune_clear()
+
+
+def fringe_plan_tuning(plan: int) -> list:
+    """The tune entries (dicts) a FRINGE_AUTOTUNE plan uses."""
+    lib = load()
+    n = c_int32(0)
+    lib.fringe_plan_tuning(c_void_p(plan), None, 0, ctypes.byref(n))
+    arr = (fringe_tune_entry * max(1, n.value))()
+    _check(lib.fringe_plan_tuning(c_void_p(plan), arr, n.value, ctypes.byref(n)),
+           "fringe_plan_tuning")
+    return [{k: getattr(arr[i], k) for k, _ in fringe_tune_entry._fields_} for i in range(n.value)]
+
+
 def fringe_plan_destroy(plan: int) -> None:
     if plan:
         load().fringe_plan_destroy(c_void_p(plan))
@@ -476,6 +516,9 @@ class Plan:
 
     def profile(self):
         return fringe_profile_get(self.handle)
+
+    def tuning(self):
+        return fringe_plan_tuning(self.handle)
 
     def close(self):
         if self.handle:

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "tune_table.h"
 
 namespace fringe {
 int rate_buffer_slots(int w_max);
@@ -169,15 +170,26 @@ uint64_t per_baseline_scratch(const ScanInfo& s, bool streaming, bool delay_only
   return x + t * sizeof(float) + uint64_t(s.n_kb) * s.nwb_max * part_bytes(delay_only);
 }
 
+// A per-scan choice that overrides the defaults of validate_and_size and
+// tune_chunks (the autotuner's): the search mode (-1: default) and the time
+// chunk (0: default), taken exactly or as an upper bound on the device-sized
+// chunk.
+struct ScanForce {
+  int spectra = -1;
+  int chunk = 0;
+  bool exact = false;
+};
+
 int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* p,
-                      Sizing* out, bool allow_spectra = true) {
+                      Sizing* out, bool allow_spectra = true,
+                      const std::vector<ScanForce>* force = nullptr) {
   if (!scans || !p || !out) return fail(FRINGE_E_INVALID, "null argument");
   if (n_scans < 1) return fail(FRINGE_E_INVALID, "n_scans must be >= 1 (got %d)", n_scans);
   if (!p->window_aps) return fail(FRINGE_E_INVALID, "window_aps is null");
   if (p->n_window_lengths < 1 || p->n_window_lengths > kMaxLevels)
     return fail(FRINGE_E_INVALID, "n_window_lengths must be in [1, %d]", kMaxLevels);
   if (p->flags & ~(FRINGE_STREAMING | FRINGE_DUMP_GRID | FRINGE_PROFILE | FRINGE_PLAIN | FRINGE_GRAPH |
-                   FRINGE_DELAY_ONLY))
+                   FRINGE_DELAY_ONLY | FRINGE_AUTOTUNE))
     return fail(FRINGE_E_INVALID, "unknown flag bits 0x%x", p->flags);
   if ((p->flags & FRINGE_DELAY_ONLY) && (p->flags & FRINGE_DUMP_GRID))
     return fail(FRINGE_E_INVALID, "FRINGE_DELAY_ONLY has no grid to dump");
@@ -290,6 +302,9 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
         (int64_t(data_len(si, sz.streaming)) + 1) * M * int64_t(sizeof(float2)) < (int64_t(1) << 32);
     si.spectra = !sz.fused || (allow_spectra && !sz.delay_only && !(p->flags & FRINGE_PLAIN) &&
                                x_fits && fused_fold_class(si.F) >= kSpectraMinFold);
+    if (sz.fused && force && (*force)[size_t(s)].spectra >= 0)
+      si.spectra = (*force)[size_t(s)].spectra > 0 && allow_spectra && x_fits &&
+                   !(p->flags & FRINGE_PLAIN);
     si.x_short = si.spectra && x_fits;
     if (sz.streaming)
       sz.stage_bytes += 2 * uint64_t(d.n_baselines) * si.stage_len * F * sizeof(float2);
@@ -391,7 +406,8 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
 // the waves that instantiation keeps resident per CU; when even 64 does not,
 // 64 (the latency-bound case of small grids).
 constexpr int kWaveRounds = 16;
-int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel) {
+int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel,
+                const std::vector<ScanForce>* force = nullptr) {
   if (!sz->fused) return FRINGE_OK;  // windows longer than 64 APs: the plan's fixed chunk
   const int period = fused_period(sz->w_max);
   for (int fc : {kFoldSpectra, 4, 8, 16}) {
@@ -415,8 +431,14 @@ int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel) {
         break;
       }
     }
-    for (auto& si : sz->scans)
-      if (unit_class(si) == fc) si.chunk = best;
+    for (size_t k = 0; k < sz->scans.size(); ++k) {
+      ScanInfo& si = sz->scans[k];
+      if (unit_class(si) != fc) continue;
+      si.chunk = best;
+      const ScanForce* f = force ? &(*force)[k] : nullptr;
+      if (f && f->chunk >= 64 && f->chunk % period == 0)
+        si.chunk = f->exact ? f->chunk : std::min(best, f->chunk);
+    }
   }
   return FRINGE_OK;
 }
@@ -502,6 +524,8 @@ struct fringe_plan_s {
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_kind;
   size_t prof_used = 0;
+  // FRINGE_AUTOTUNE: the tune entries of the plan's classes of scans
+  std::vector<std::pair<TuneKey, TuneVal>> tuned;
 };
 
 namespace {
@@ -878,12 +902,16 @@ int fringe_plan_check(const fringe_scan_desc* scans, int32_t n_scans, const frin
   return FRINGE_OK;
 }
 
-int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* params,
-                fringe_plan_t* out) {
-  if (!out) return fail(FRINGE_E_INVALID, "null plan output pointer");
+}  // extern "C"
+
+namespace {
+
+// fringe_plan with per-scan overrides of the search mode and chunk.
+int make_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* params,
+              const std::vector<ScanForce>* force, fringe_plan_t* out) {
   *out = nullptr;
   Sizing sz;
-  int rc = validate_and_size(scans, n_scans, params, &sz);
+  int rc = validate_and_size(scans, n_scans, params, &sz, true, force);
   if (rc != FRINGE_OK) return rc;
   auto* p = new fringe_plan_s();
   p->sz = std::move(sz);
@@ -903,8 +931,8 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
     release(p);
     return hip_fail(he, "hipDeviceGetAttribute");
   }
-  if ((rc = tune_chunks(&p->sz, std::max(1, n_cu),
-                        p->sz.delay_only ? 0 : params->pad_time)) != FRINGE_OK) {
+  if ((rc = tune_chunks(&p->sz, std::max(1, n_cu), p->sz.delay_only ? 0 : params->pad_time,
+                        force)) != FRINGE_OK) {
     release(p);
     return rc;
   }
@@ -967,6 +995,193 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_par
     return hip_fail(he, "plan host resources");
   }
   *out = p;
+  return FRINGE_OK;
+}
+
+// Pseudo-random samples for the tuner's timing runs (their values do not
+// change the kernels' work).
+__global__ void tune_fill_kernel(float* x, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t h = static_cast<uint32_t>(i) * 0x9E3779B1u ^ static_cast<uint32_t>(i >> 32);
+  h ^= h >> 15;
+  h *= 0x85EBCA77u;
+  h ^= h >> 13;
+  x[i] = static_cast<float>(h & 0xFFFFu) * (1.f / 32768.f) - 1.f;
+}
+
+constexpr int kTuneSampleAps = 16384;
+constexpr int kTuneWavesPerCu = 24;
+
+// Time every launch configuration of one class of scans on a synthetic
+// sample of its shape (enough waves for several rounds of the device at the
+// longest chunk) and keep the fastest: search mode x time chunk.
+int tune_class(const TuneKey& key, const fringe_params* params, int w_max, TuneVal* best) {
+  const int F = key.n_freq;
+  const int R = key.pad_freq * F / kBinsPerWave;
+  const int64_t target = int64_t(kTuneWavesPerCu) * key.cus;
+  const int per_bl = (kTuneSampleAps / 1024) * std::max(1, R);
+  fringe_scan_desc d{};
+  d.n_baselines = int32_t(std::max<int64_t>(1, (target + per_bl - 1) / per_bl));
+  d.n_ap = kTuneSampleAps;
+  d.n_chan = std::min(F, 64);
+  d.n_if = F / d.n_chan;
+  d.ap_seconds = 1e-3;
+  d.chan_width_hz = 1e6;
+  fringe_params q = *params;
+  q.flags = (params->flags & FRINGE_DELAY_ONLY) | FRINGE_PROFILE;
+  q.hbm_budget_bytes = 0;
+  q.max_candidates = 1 << 16;
+  const int64_t n_samples = int64_t(d.n_baselines) * d.n_ap * F;
+  float2* cube = nullptr;
+  int rc = dev_alloc(&cube, uint64_t(n_samples) * sizeof(float2), "tuning sample");
+  if (rc != FRINGE_OK) return rc;
+  const int64_t n_fl = 2 * n_samples;
+  hipLaunchKernelGGL(tune_fill_kernel, dim3(static_cast<unsigned>((n_fl + 255) / 256)), dim3(256),
+                     0, nullptr, reinterpret_cast<float*>(cube), n_fl);
+  hipError_t he = hipGetLastError();
+  if (he == hipSuccess) he = hipDeviceSynchronize();
+  if (he != hipSuccess) {
+    (void)hipFree(cube);
+    return hip_fail(he, "tuning sample fill");
+  }
+  const int period = fused_period(w_max);
+  float ms_best[2] = {-1.f, -1.f};
+  int chunk_best[2] = {0, 0};
+  for (int mode = 0; mode < 2; ++mode) {
+    for (int chunk = 128; chunk <= 1024; chunk *= 2) {
+      if (chunk % period) continue;
+      std::vector<ScanForce> f(1);
+      f[0].spectra = mode;
+      f[0].chunk = chunk;
+      f[0].exact = true;
+      fringe_plan_t tp = nullptr;
+      rc = make_plan(&d, 1, &q, &f, &tp);
+      if (rc == FRINGE_E_NOMEM) continue;  // this configuration does not fit now
+      if (rc != FRINGE_OK) {
+        (void)hipFree(cube);
+        return rc;
+      }
+      if (tp->sz.scans[0].spectra != (mode == 1)) {  // the mode is not available here
+        fringe_plan_destroy(tp);
+        break;
+      }
+      const fringe_cf32* vis[1] = {reinterpret_cast<const fringe_cf32*>(cube)};
+      float ms = -1.f;
+      for (int rep = 0; rep < 3 && rc == FRINGE_OK; ++rep) {
+        rc = fringe_search(tp, vis, nullptr);
+        fringe_profile pr{};
+        if (rc == FRINGE_OK) rc = fringe_profile_get(tp, &pr);
+        const float t = float(pr.delay_ms + pr.rate_ms + pr.finalize_ms + pr.compact_ms);
+        if (rc == FRINGE_OK && rep > 0 && (ms < 0.f || t < ms)) ms = t;  // the first warms up
+      }
+      fringe_plan_destroy(tp);
+      if (rc != FRINGE_OK) {
+        (void)hipFree(cube);
+        return rc;
+      }
+      if (ms_best[mode] < 0.f || ms < ms_best[mode]) {
+        ms_best[mode] = ms;
+        chunk_best[mode] = chunk;
+      }
+    }
+  }
+  (void)hipFree(cube);
+  if (ms_best[0] < 0.f && ms_best[1] < 0.f)
+    return fail(FRINGE_E_NOMEM, "autotune: no configuration of class F = %d fits", F);
+  const int m = (ms_best[0] < 0.f || (ms_best[1] >= 0.f && ms_best[1] < ms_best[0])) ? 1 : 0;
+  best->spectra = m;
+  best->chunk = chunk_best[m];
+  best->ms_fused = ms_best[0];
+  best->ms_spectra = ms_best[1];
+  return FRINGE_OK;
+}
+
+// FRINGE_AUTOTUNE: the tune table's configuration of every scan's class,
+// tuning the classes it lacks.
+int autotune_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* params,
+                  const Sizing& z, std::vector<ScanForce>* force,
+                  std::vector<std::pair<TuneKey, TuneVal>>* used) {
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  hipDeviceProp_t prop{};
+  if (he == hipSuccess) he = hipGetDeviceProperties(&prop, dev);
+  if (he != hipSuccess) return hip_fail(he, "device properties");
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  force->assign(size_t(n_scans), ScanForce{});
+  for (int s = 0; s < n_scans; ++s) {
+    TuneKey k;
+    k.arch = arch;
+    k.cus = prop.multiProcessorCount;
+    k.n_freq = z.scans[size_t(s)].F;
+    k.pad_freq = params->pad_freq;
+    k.pad_time = z.delay_only ? 0 : params->pad_time;
+    k.log2_wmax = log2i(z.w_max);
+    TuneVal v;
+    if (!tune_lookup(k, &v)) {
+      const int rc = tune_class(k, params, z.w_max, &v);
+      if (rc != FRINGE_OK) return rc;
+      tune_store(k, v);
+    }
+    (*force)[size_t(s)].spectra = v.spectra;
+    (*force)[size_t(s)].chunk = v.chunk;
+    bool seen = false;
+    for (const auto& e : *used) seen = seen || e.first.n_freq == k.n_freq;
+    if (!seen) used->emplace_back(k, v);
+  }
+  return FRINGE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* params,
+                fringe_plan_t* out) {
+  if (!out) return fail(FRINGE_E_INVALID, "null plan output pointer");
+  *out = nullptr;
+  std::vector<ScanForce> force;
+  std::vector<std::pair<TuneKey, TuneVal>> used;
+  if (params && (params->flags & FRINGE_AUTOTUNE)) {
+    Sizing probe;
+    int rc = validate_and_size(scans, n_scans, params, &probe);
+    if (rc != FRINGE_OK) return rc;
+    if (probe.fused && (rc = autotune_plan(scans, n_scans, params, probe, &force, &used)) != FRINGE_OK)
+      return rc;
+  }
+  const int rc = make_plan(scans, n_scans, params, force.empty() ? nullptr : &force, out);
+  if (rc == FRINGE_OK) (*out)->tuned = std::move(used);
+  return rc;
+}
+
+int fringe_tune_load(const char* path) {
+  if (!path) return fail(FRINGE_E_INVALID, "null path");
+  std::string err;
+  if (tune_load(path, &err) != 0) return fail(FRINGE_E_INVALID, "%s", err.c_str());
+  return FRINGE_OK;
+}
+
+int fringe_tune_save(const char* path) {
+  if (!path) return fail(FRINGE_E_INVALID, "null path");
+  std::string err;
+  if (tune_save(path, &err) != 0) return fail(FRINGE_E_INVALID, "%s", err.c_str());
+  return FRINGE_OK;
+}
+
+void fringe_tune_clear(void) { tune_clear(); }
+
+int fringe_plan_tuning(fringe_plan_t p, fringe_tune_entry* out, int32_t capacity, int32_t* n) {
+  if (!p || !n) return fail(FRINGE_E_INVALID, "null argument");
+  if (capacity < 0 || (capacity > 0 && !out)) return fail(FRINGE_E_INVALID, "bad output buffer");
+  *n = int32_t(p->tuned.size());
+  for (int32_t i = 0; i < std::min(capacity, *n); ++i) {
+    const TuneKey& k = p->tuned[size_t(i)].first;
+    const TuneVal& v = p->tuned[size_t(i)].second;
+    out[i] = fringe_tune_entry{k.n_freq, k.pad_freq, k.pad_time, k.log2_wmax, v.spectra, v.chunk,
+                               v.ms_fused, v.ms_spectra};
+  }
+  if (*n > capacity) return fail(FRINGE_E_CAPACITY, "%d tune entries", int(*n));
   return FRINGE_OK;
 }
 

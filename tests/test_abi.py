@@ -174,7 +174,8 @@ def test_graph_flag_rules():
     assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_GRAPH | B.FRINGE_DUMP_GRID)["n_windows"] == 31
     for other in (B.FRINGE_STREAMING, B.FRINGE_PROFILE, B.FRINGE_PLAIN):
         assert _code(lambda: F.fringe_plan_check([c1], [4], flags=B.FRINGE_GRAPH | other)) == B.FRINGE_E_INVALID
-    assert _code(lambda: F.fringe_plan_check([c1], [4], flags=0x40)) == B.FRINGE_E_INVALID
+    assert _code(lambda: F.fringe_plan_check([c1], [4], flags=0x80)) == B.FRINGE_E_INVALID
+    assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_AUTOTUNE)["n_windows"] == 31
 
 
 def test_delay_only_flag_rules():
@@ -232,3 +233,43 @@ def test_autospectrum_gains_argument_checks():
     # gains_in overlapping gains_out without being the same array
     assert _code(lambda: g(0x1000, 3, 2, 64, 0x2000, 3, 0x100000, 0x100008)) == B.FRINGE_E_INVALID
     assert "overlap" in F.fringe_last_error()
+
+
+def test_tune_table_file_round_trip(tmp_path):
+    """The tune table's JSON form: a written table loads back unchanged,
+    entries merge by class, malformed files are refused and leave the
+    table as it was (host code only, no device)."""
+    import json
+    src = tmp_path / "in.json"
+    entries = [
+        dict(arch="gfx950", cus=256, n_freq=1024, pad_freq=4, pad_time=2, log2_wmax=6,
+             spectra=1, chunk=256, ms_fused=12.5, ms_spectra=10.25),
+        dict(arch="gfx950", cus=256, n_freq=256, pad_freq=4, pad_time=0, log2_wmax=5,
+             spectra=0, chunk=1024, ms_fused=3.0, ms_spectra=-1),
+    ]
+    src.write_text(json.dumps({"fringe_tune_table": 1, "entries": entries}, indent=1))
+    F.fringe_tune_clear()
+    F.fringe_tune_load(str(src))
+    out = tmp_path / "out.json"
+    F.fringe_tune_save(str(out))
+    got = json.loads(out.read_text())
+    assert got["fringe_tune_table"] == 1
+    assert got["entries"] == entries
+    # a later entry of the same class replaces the earlier one
+    e2 = dict(entries[0], chunk=512, spectra=0)
+    src.write_text(json.dumps({"fringe_tune_table": 1, "entries": [e2]}))
+    F.fringe_tune_load(str(src))
+    F.fringe_tune_save(str(out))
+    got = json.loads(out.read_text())["entries"]
+    assert len(got) == 2 and got[0] == e2
+    for bad in ('{"entries": []}', '{"fringe_tune_table": 1, "entries": [{"arch": 3}]}',
+                '{"fringe_tune_table": 1, "entries": [{"arch": "gfx950", "cus": 1}]}',
+                '{"fringe_tune_table": 1, "entries": [', 'not json'):
+        src.write_text(bad)
+        assert _code(lambda: F.fringe_tune_load(str(src))) == B.FRINGE_E_INVALID
+    F.fringe_tune_save(str(out))
+    assert len(json.loads(out.read_text())["entries"]) == 2
+    assert _code(lambda: F.fringe_tune_load(str(tmp_path / "missing.json"))) == B.FRINGE_E_INVALID
+    F.fringe_tune_clear()
+    F.fringe_tune_save(str(out))
+    assert json.loads(out.read_text())["entries"] == []
