@@ -559,8 +559,8 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
     entries = {}
     cmp = None
     step_s = [0.0] * steps
-    fused_ms = fin_ms = comp_ms = 0.0
-    fused_n = 0
+    fused_ms = fin_ms = comp_ms = delay_ms = 0.0
+    fused_n = delay_n = 0
     n_windows = n_cands = cube = 0
     fl = [0.0, 0.0, 0.0]
     part_bytes = e_bytes = 0
@@ -599,6 +599,8 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
                 pr = plan.profile()
                 fused_ms += pr["rate_ms"]
                 fused_n += pr["rate_launches"]
+                delay_ms += pr["delay_ms"]
+                delay_n += pr["delay_launches"]
                 fin_ms += pr["finalize_ms"]
                 comp_ms += pr["compact_ms"]
             nw = plan.info()["n_windows"]
@@ -655,8 +657,12 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
         torch.cuda.empty_cache()
     ms = float(np.mean(step_s)) * 1e3
     flops_step = fl[0] + fl[1] + fl[2]
-    launches_per_step = fused_n / steps
-    avg_launch_s = fused_ms / max(1, fused_n) / 1e3
+    # the search kernels of a step: the fused kernels (delay transform, rate
+    # transform and peak in one) and, for bands in spectra mode, the delay
+    # transform kernel and the fused kernel reading its spectra; their
+    # algorithmic flops over their summed launch time
+    launches_per_step = (fused_n + delay_n) / steps
+    avg_launch_s = (fused_ms + delay_ms) / max(1, fused_n + delay_n) / 1e3
     flops_per_launch = flops_step / launches_per_step
     achieved = flops_per_launch / avg_launch_s / 1e12
     return {
@@ -664,8 +670,9 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
         "candidates": n_cands, "waves": waves_out, "scans": len(specs),
         "roofline": {
             "bound": "alu",
-            "kernel": "fused_search_kernel (delay FFT + rate FFT + |G|^2 peak; one launch per wave "
-                      "and fold class)",
+            "kernel": "search kernels: fused_search_kernel (delay FFT + rate FFT + |G|^2 peak, one "
+                      "launch per wave and fold class) and, in spectra mode, delay_fft_kernel + "
+                      "fused_search_kernel reading the spectra",
             "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": None,
@@ -675,8 +682,8 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
             "avg_launch_ms": avg_launch_s * 1e3,
             "launches_per_step": launches_per_step,
         },
-        "kernel_ms_per_step": {"fused_ms": fused_ms / steps, "finalize_ms": fin_ms / steps,
-                               "compact_ms": comp_ms / steps},
+        "kernel_ms_per_step": {"fused_ms": fused_ms / steps, "delay_fft_ms": delay_ms / steps,
+                               "finalize_ms": fin_ms / steps, "compact_ms": comp_ms / steps},
         "tflops_algorithmic_step": flops_step / (ms / 1e3) / 1e12,
         "hbm_gbs_algorithmic": cube / (ms / 1e3) / 1e9,
         "autotune": {"enabled": autotune, "plan_s_total": plan_s,

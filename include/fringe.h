@@ -152,9 +152,11 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans,
  * caller owns it and keeps it valid and unchanged until the work on the
  * stream has completed.  With FRINGE_STREAMING, d_vis[s] is the next chunk
  * of subarray s (NULL: no chunk this call) and the windows reported are
- * those whose last AP lies in that chunk, windows spanning the previous
- * chunk included; start APs count from the first chunk.  Asynchronous:
- * returns once the kernels are enqueued. */
+ * those whose last AP lies in that chunk (D APs earlier with dedispersion
+ * shifts up to D, fringe_set_shifts), windows spanning the previous chunk
+ * included; start APs count from the first chunk.  A search on another
+ * stream than the plan's previous search first waits for that search.
+ * Asynchronous: returns once the kernels are enqueued. */
 int fringe_search(fringe_plan_t plan, const fringe_cf32* const* d_vis, void* hip_stream);
 
 /* Wait for the plan's last search and copy its candidates, sorted by
@@ -206,10 +208,17 @@ int fringe_set_gains(fringe_plan_t plan, int32_t scan, const fringe_cf32* d_gain
  * are several scans of one plan with the same visibility pointer and their
  * own shifts: one search call, one launch.  The caller owns the shifts and
  * keeps them valid and unchanged while searches that use them may run; NULL
- * removes them.  Errors: FRINGE_E_INVALID for a null plan or a scan out of
- * range; FRINGE_E_UNSUPPORTED for streaming or FRINGE_PLAIN plans (a
- * shifted window reads APs past its own) and for baselines of 1 GiB or more
- * of samples. */
+ * removes them.  With FRINGE_STREAMING (shifts set before the plan's first
+ * search; the library reads them once to size the subarray's stage for the
+ * largest shift D, remaking the plan's buffers), a call reports the windows
+ * whose last AP lies D APs before the end of the data received so far, so a
+ * window is reported once its shifted reads have arrived: over the stream,
+ * exactly the windows of a batch search of the concatenated APs that end
+ * at least D APs before its end, with the same records.  Errors:
+ * FRINGE_E_INVALID for a null plan or a scan out of range; FRINGE_E_STATE
+ * for a streaming plan that has searched; FRINGE_E_UNSUPPORTED for
+ * FRINGE_PLAIN plans, shifts above 2^20 APs and baselines (streaming: stages)
+ * of 1 GiB or more of samples. */
 int fringe_set_shifts(fringe_plan_t plan, int32_t scan, const int32_t* d_shifts);
 
 /* Dedispersion as a pass of its own, for plans without shifts (paper:

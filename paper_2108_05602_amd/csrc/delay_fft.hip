@@ -5,9 +5,12 @@
 // plus the AP energy e_t = sum_f |x_t[f]|^2 that the window SNR divides by
 // (x multiplied first by the slab's calibration gains when it has them).
 //
-// One wavefront per work group.  A wave transforms NAP = max(1, 1024 / M)
-// APs at a time with a self-sorting (Stockham) FFT: radix-16 passes, then
-// one radix-2/4/8 pass if log2(M) is not a multiple of 4.  The first pass
+// Up to M = 1024 one wavefront per work group transforms NAP = 1024 / M
+// APs at a time; above, M / 1024 waves share one AP (one radix-16
+// butterfly per thread and pass, the group's LDS one transform), so the
+// 2048- and 4096-point transforms keep three waves per SIMD instead of one
+// wave holding 64 points per lane.  Self-sorting (Stockham) FFT: radix-16
+// passes, then one radix-2/4/8 pass if log2(M) is not a multiple of 4.  The first pass
 // reads the visibilities straight from HBM (coalesced, the zero half /
 // three quarters of the padded input never loaded or multiplied), middle
 // passes go through LDS, and the last pass writes X to HBM in natural order.
@@ -55,7 +58,8 @@ constexpr int first_radix(int log_m) { return log_m >= 4 ? 16 : (1 << log_m); }
 // Pass p has radix R and NS = product of the earlier radices:
 //   v[r] = in[j + r M/R] * w_{NS R}^{(j mod NS) r},  V = DFT_R(v),
 //   out[(j / NS) NS R + (j mod NS) + k NS] = V[k].
-template <int M, int NAP, int R, int NS, int PF, bool FIRST, bool LAST>
+// NT threads (one to four waves) share the NAP transforms of a work group.
+template <int M, int NAP, int R, int NS, int PF, bool FIRST, bool LAST, int NT>
 __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ xin,
                                               float2* __restrict__ xout,
                                               const float2* __restrict__ tw, int lane,
@@ -65,14 +69,14 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
                                               const float2* __restrict__ xbl = nullptr,
                                               int t_first = 0, int T = 0) {
   constexpr int NBF = NAP * M / R;   // butterflies in this pass
-  constexpr int BPL = NBF / 64;      // per lane
-  static_assert(BPL >= 1 && NBF % 64 == 0, "pass does not fill the wave");
+  constexpr int BPL = NBF / NT;      // per thread
+  static_assert(BPL >= 1 && NBF % NT == 0, "pass does not fill the work group");
   constexpr int SPAN = M / R;        // butterflies per transform
   constexpr int NZ = FIRST ? (R / PF > 0 ? R / PF : 1) : R;
   float2 v[BPL][R];
 #pragma unroll
   for (int i = 0; i < BPL; ++i) {
-    const int jj = lane + 64 * i;
+    const int jj = lane + NT * i;
     const int a = jj / SPAN;
     const int j = jj % SPAN;
     if constexpr (FIRST) {
@@ -85,7 +89,7 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
           if (ok && idx < F) {
             if (shifts) {  // dedispersion: channel idx from AP t + d, 0 past the data
               const int row = t_first + a + min(max(shifts[idx], 0), T);
-              if (row < T) x = xbl[static_cast<int64_t>(row) * F + idx];
+              if (row < T) x = xbl[static_cast<int64_t>(row) * F + idx];  // T: the rows held
             } else {
               x = xin[static_cast<int64_t>(a) * F + idx];
             }
@@ -110,7 +114,7 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
   if constexpr (!FIRST) __syncthreads();  // every read of the pass before any write
 #pragma unroll
   for (int i = 0; i < BPL; ++i) {
-    const int jj = lane + 64 * i;
+    const int jj = lane + NT * i;
     const int a = jj / SPAN;
     const int j = jj % SPAN;
     fft_dif_pruned<R, NZ>(v[i]);
@@ -129,26 +133,34 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
 }
 
 // Passes after the first: radix 16 while at least 4 bits remain, then the rest.
-template <int M, int NAP, int PF, int NS>
+template <int M, int NAP, int PF, int NS, int NT>
 __device__ __forceinline__ void later_passes(float2* lds, float2* xout, const float2* tw,
                                              int lane, int n_valid_ap, int F) {
   if constexpr (NS < M) {
     constexpr int rem = ilog2(M / NS);
     constexpr int R = rem >= 4 ? 16 : (1 << rem);
     constexpr bool LAST = (NS * R == M);
-    stockham_pass<M, NAP, R, NS, PF, false, LAST>(lds, nullptr, xout, tw, lane, n_valid_ap,
-                                                  F, nullptr);
-    later_passes<M, NAP, PF, NS * R>(lds, xout, tw, lane, n_valid_ap, F);
+    stockham_pass<M, NAP, R, NS, PF, false, LAST, NT>(lds, nullptr, xout, tw, lane, n_valid_ap,
+                                                      F, nullptr);
+    later_passes<M, NAP, PF, NS * R, NT>(lds, xout, tw, lane, n_valid_ap, F);
   }
 }
 
+// Threads of the work group: one wave up to M = 1024 (1024 / M transforms
+// at a time), M / 1024 waves on one transform above, so that each thread
+// holds one radix-16 butterfly per pass and the group's LDS is one transform.
+constexpr int fft_threads(int log_m) { return log_m > 10 ? (1 << (log_m - 10)) * 64 : 64; }
+
 template <int LOGM, int PF>
-__global__ void __launch_bounds__(64) delay_fft_kernel(DelayArgs a) {
+__global__ void __launch_bounds__(fft_threads(LOGM)) delay_fft_kernel(DelayArgs a) {
   constexpr int M = 1 << LOGM;
   constexpr int NAP = M >= 1024 ? 1 : 1024 / M;
+  constexpr int NT = fft_threads(LOGM);
+  constexpr int NW = NT / 64;
   constexpr int R0 = first_radix(LOGM);
   constexpr int GROUP = (M / R0) < 64 ? (M / R0) : 64;  // lanes per AP in the first pass
   extern __shared__ float2 lds[];
+  float* lds_e = reinterpret_cast<float*>(lds + NAP * M);  // per-wave energy partials
   const int lane = threadIdx.x;
   const int groups_per_bl = (a.T + NAP - 1) / NAP;
   const int64_t n_groups = static_cast<int64_t>(a.nb) * groups_per_bl;
@@ -164,18 +176,29 @@ __global__ void __launch_bounds__(64) delay_fft_kernel(DelayArgs a) {
     constexpr bool ONE_PASS = (R0 == M);
     const float2* gains = a.gains ? a.gains + static_cast<int64_t>(b) * F : nullptr;
     const float2* xbl = a.vis + static_cast<int64_t>(b) * a.vis_stride;
-    stockham_pass<M, NAP, R0, 1, PF, true, ONE_PASS>(lds, xin, xout, a.tw, lane, n_valid, F,
-                                                     &es, gains, a.shifts, xbl, t0, a.T);
-    // AP energies: lanes of one AP form an aligned group of GROUP lanes.
+    stockham_pass<M, NAP, R0, 1, PF, true, ONE_PASS, NT>(lds, xin, xout, a.tw, lane, n_valid, F,
+                                                         &es, gains, a.shifts, xbl, t0, a.T_rows);
+    // AP energies: lanes of one AP form an aligned group of GROUP lanes
+    // (with several waves on one AP, each wave's sum goes through LDS; the
+    // first pass's closing barrier orders the previous AP's reads of it)
 #pragma unroll
     for (int off = GROUP / 2; off >= 1; off >>= 1) es += __shfl_xor(es, off, 64);
-    if constexpr (NAP == 1) {
+    if constexpr (NW > 1) {
+      if ((lane & 63) == 0) lds_e[lane >> 6] = es;
+      __syncthreads();
+      if (lane == 0) {
+        float t = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += lds_e[w];
+        a.e[ap0] = t;
+      }
+    } else if constexpr (NAP == 1) {
       if (lane == 0) a.e[ap0] = es;
     } else {
       const int ap = lane / GROUP;
       if ((lane % GROUP) == 0 && ap < n_valid) a.e[ap0 + ap] = es;
     }
-    if constexpr (!ONE_PASS) later_passes<M, NAP, PF, R0>(lds, xout, a.tw, lane, n_valid, F);
+    if constexpr (!ONE_PASS) later_passes<M, NAP, PF, R0, NT>(lds, xout, a.tw, lane, n_valid, F);
   }
 }
 
@@ -186,8 +209,9 @@ hipError_t launch_one(const DelayArgs& a, hipStream_t st) {
   const int64_t groups = static_cast<int64_t>(a.nb) * ((a.T + NAP - 1) / NAP);
   if (groups == 0) return hipSuccess;
   const int grid = static_cast<int>(groups < 65536 ? groups : 65536);
-  const size_t lds = static_cast<size_t>(NAP) * M * sizeof(float2);
-  hipLaunchKernelGGL((delay_fft_kernel<LOGM, PF>), dim3(grid), dim3(64), lds, st, a);
+  const size_t lds = static_cast<size_t>(NAP) * M * sizeof(float2) + 16 * sizeof(float);
+  hipLaunchKernelGGL((delay_fft_kernel<LOGM, PF>), dim3(grid), dim3(fft_threads(LOGM)), lds, st,
+                     a);
   return hipGetLastError();
 }
 

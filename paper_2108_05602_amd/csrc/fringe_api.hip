@@ -63,7 +63,8 @@ constexpr int64_t kCandPrefetch = 2048;
 
 // Windows of one scan in one search: their numbering and where their data is.
 struct CallScan {
-  int T = 0;                          // APs of the searched data
+  int T = 0;                          // APs of the searched data: windows end before it
+  int T_rows = 0;                     // APs the data hold (> T: a dedispersion lookahead)
   int t_emit = 0;                     // windows end at or after this AP
   int64_t t_origin = 0;               // absolute AP of the data's AP 0
   int64_t nwb = 0;                    // windows per baseline
@@ -98,6 +99,7 @@ struct ScanInfo {
   int64_t lvl_goff[kMaxLevels];
   int64_t grid_off;                   // first grid element of the scan (dump)
   int stage_len;                      // streaming: APs of halo + chunk
+  int lookahead;                      // streaming with shifts: APs a window's reads run ahead
   int slab_nb;                        // baselines per pass
   int chunk;                          // search-kernel time tiling
   // Spectra mode: each slab's delay spectra X[b][t][k_f] are written to HBM
@@ -182,7 +184,8 @@ struct ScanForce {
 
 int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* p,
                       Sizing* out, bool allow_spectra = true,
-                      const std::vector<ScanForce>* force = nullptr) {
+                      const std::vector<ScanForce>* force = nullptr,
+                      const std::vector<int>* lookahead = nullptr) {
   if (!scans || !p || !out) return fail(FRINGE_E_INVALID, "null argument");
   if (n_scans < 1) return fail(FRINGE_E_INVALID, "n_scans must be >= 1 (got %d)", n_scans);
   if (!p->window_aps) return fail(FRINGE_E_INVALID, "window_aps is null");
@@ -259,7 +262,9 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     si.n_kb = int(M / kBinsPerWave);
     si.pad_t = p->pad_time;
     si.full.T = d.n_ap;
+    si.full.T_rows = d.n_ap;
     enumerate(&si.full, sz.lv);
+    si.lookahead = (sz.streaming && lookahead) ? std::max(0, (*lookahead)[size_t(s)]) : 0;
     int64_t goff = 0;
     for (int l = 0; l < sz.lv.n; ++l) {
       si.lvl_goff[l] = goff;
@@ -268,7 +273,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     si.grid_per_bl = goff;
     if (sz.streaming) {
       // halo: the last W_max - 1 APs, plus up to align - 1 to start aligned
-      si.stage_len = (sz.w_max - 1) + (sz.align - 1) + d.n_ap;
+      si.stage_len = (sz.w_max - 1) + (sz.align - 1) + d.n_ap + si.lookahead;
       int64_t nmax = 0;
       for (int l = 0; l < sz.lv.n; ++l) nmax += (int64_t(d.n_ap) - 1) / sz.lv.s[l] + 1;
       si.nwb_max = nmax;
@@ -526,6 +531,11 @@ struct fringe_plan_s {
   size_t prof_used = 0;
   // FRINGE_AUTOTUNE: the tune entries of the plan's classes of scans
   std::vector<std::pair<TuneKey, TuneVal>> tuned;
+  // what the plan was made from, to make it again (a streaming plan whose
+  // dedispersion shifts need a longer stage)
+  std::vector<fringe_scan_desc> descs;
+  std::vector<ScanForce> force;
+  std::vector<int> lookahead;
 };
 
 namespace {
@@ -616,11 +626,15 @@ int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, Ca
   StreamState& ss = p->streams[s];
   const int64_t A = ss.consumed;
   const int C = si.d.n_ap;
+  const int D = si.lookahead;
   // start APs are reported as int32 (fringe_candidate.t_start)
   if (A + C > int64_t(INT32_MAX))
     return fail(FRINGE_E_UNSUPPORTED,
                 "subarray %d: the stream would pass 2^31 - 1 APs (start APs are int32)", s);
-  const int64_t origin = std::max<int64_t>(0, floor_to(A - (p->sz.w_max - 1), p->sz.align));
+  // windows ending in [A - D, A + C - D) are reported: with dedispersion
+  // shifts up to D, their reads reach AP A + C - 1 at most
+  const int64_t origin =
+      std::max<int64_t>(0, floor_to(A - D - (p->sz.w_max - 1), p->sz.align));
   const int halo = int(A - origin);
   const int nxt = ss.cur ^ 1;
   const size_t row = size_t(si.stage_len) * si.F * sizeof(float2);  // one baseline of a stage
@@ -639,8 +653,9 @@ int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, Ca
   ss.origin = origin;
   ss.len = halo + C;
   ss.consumed = A + C;
-  c->T = halo + C;
-  c->t_emit = halo;
+  c->T_rows = halo + C;
+  c->T = std::max(0, halo + C - D);
+  c->t_emit = int(std::max<int64_t>(0, A - D - origin));
   c->t_origin = origin;
   enumerate(c, p->sz.lv);
   *data = ss.stage[nxt];
@@ -692,6 +707,7 @@ FusedArgs fused_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& si, co
   for (int l = 0; l < kMaxLevels; ++l) fu.lvl_goff[l] = si.lvl_goff[l];
   fu.nb = u.nb;
   fu.T = c.T;
+  fu.T_rows = std::max(c.T, c.T_rows);
   fu.F = si.F;
   fu.M = si.M;
   fu.R = si.n_kb;
@@ -710,6 +726,7 @@ FusedArgs fused_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& si, co
     // delay-transform kernel has applied gains and shifts
     fu.vis = w.X;
     fu.vis_stride = int64_t(c.T) * si.M;
+    fu.T_rows = c.T;
     fu.F = si.M;
     fu.gains = nullptr;
     fu.shifts = nullptr;
@@ -794,6 +811,7 @@ int plain_tables(fringe_plan_s* p, const std::vector<const float2*>& data) {
           // a one-window "scan": W APs of baseline b from AP j * stride
           CallScan one{};
           one.T = w;
+          one.T_rows = w;
           one.nwb = 1;
           for (int l = 0; l <= kMaxLevels; ++l) one.lvl_off[l] = l <= li ? 0 : 1;
           Unit u{int(s), 0, 1, 0, 0};
@@ -908,12 +926,16 @@ namespace {
 
 // fringe_plan with per-scan overrides of the search mode and chunk.
 int make_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* params,
-              const std::vector<ScanForce>* force, fringe_plan_t* out) {
+              const std::vector<ScanForce>* force, fringe_plan_t* out,
+              const std::vector<int>* lookahead = nullptr) {
   *out = nullptr;
   Sizing sz;
-  int rc = validate_and_size(scans, n_scans, params, &sz, true, force);
+  int rc = validate_and_size(scans, n_scans, params, &sz, true, force, lookahead);
   if (rc != FRINGE_OK) return rc;
   auto* p = new fringe_plan_s();
+  p->descs.assign(scans, scans + n_scans);
+  if (force) p->force = *force;
+  p->lookahead = lookahead ? *lookahead : std::vector<int>(size_t(n_scans), 0);
   p->sz = std::move(sz);
   p->params = *params;
   p->gains.assign(size_t(n_scans), nullptr);
@@ -1317,6 +1339,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       da.tw = p->tw[si.log_m];
       da.nb = u.nb;
       da.T = c.T;
+      da.T_rows = std::max(c.T, c.T_rows);
       da.F = si.F;
       da.M = si.M;
       da.log_m = si.log_m;
@@ -1548,12 +1571,43 @@ int fringe_set_shifts(fringe_plan_t p, int32_t scan, const int32_t* d_shifts) {
   if (!p) return fail(FRINGE_E_INVALID, "null plan");
   if (scan < 0 || scan >= int32_t(p->shifts.size()))
     return fail(FRINGE_E_INVALID, "scan %d out of range [0, %d)", scan, int(p->shifts.size()));
+  if (d_shifts && (p->params.flags & FRINGE_PLAIN))
+    return fail(FRINGE_E_UNSUPPORTED, "dedispersion needs the whole scan: not with FRINGE_PLAIN");
+  if (p->sz.streaming) {
+    // the stage must hold the lookahead of the largest shift: set before
+    // the plan's first search, the plan is made again with that stage
+    const size_t k = size_t(scan);
+    if (p->searched)
+      return fail(FRINGE_E_STATE, "streaming plans take shifts before their first search");
+    int d_max = 0;
+    if (d_shifts) {
+      const ScanInfo& si = p->sz.scans[k];
+      std::vector<int32_t> h(size_t(si.F));
+      const hipError_t he =
+          hipMemcpy(h.data(), d_shifts, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+      if (he != hipSuccess) return hip_fail(he, "reading the shifts");
+      for (int32_t v : h) d_max = std::max(d_max, int(v));
+      if (d_max > (1 << 20))
+        return fail(FRINGE_E_UNSUPPORTED, "subarray %d: shifts above 2^20 APs", scan);
+    }
+    if (d_max != p->lookahead[k]) {
+      std::vector<int> la = p->lookahead;
+      la[k] = d_max;
+      fringe_plan_t np = nullptr;
+      int rc = make_plan(p->descs.data(), int32_t(p->descs.size()), &p->params,
+                         p->force.empty() ? nullptr : &p->force, &np, &la);
+      if (rc != FRINGE_OK) return rc;
+      // keep the caller's plan handle: swap the contents, free the old ones
+      std::swap(np->gains, p->gains);
+      std::swap(np->shifts, p->shifts);
+      std::swap(np->tuned, p->tuned);
+      std::swap(*np, *p);
+      fringe_plan_destroy(np);
+    }
+  }
   if (d_shifts) {
-    if (p->params.flags & (FRINGE_STREAMING | FRINGE_PLAIN))
-      return fail(FRINGE_E_UNSUPPORTED,
-                  "dedispersion needs the whole scan: not with FRINGE_STREAMING or FRINGE_PLAIN");
     const ScanInfo& si = p->sz.scans[size_t(scan)];
-    if (int64_t(si.d.n_ap) * si.F * int64_t(sizeof(float2)) >= (int64_t(1) << 30))
+    if (int64_t(data_len(si, p->sz.streaming)) * si.F * int64_t(sizeof(float2)) >= (int64_t(1) << 30))
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: dedispersion needs baselines under 1 GiB", scan);
   }
   p->shifts[size_t(scan)] = d_shifts;

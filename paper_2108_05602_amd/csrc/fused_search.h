@@ -192,16 +192,19 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   const uint32_t row_bytes = static_cast<uint32_t>(F) * sizeof(float2);
   // dedispersion: channel f of AP t is read from AP t + d_f.  The shift is
   // folded into the lane's offset, the AP is added to it (not given as the
-  // scalar offset), and the buffer's record limit, the baseline's T rows,
-  // turns the reads past the data into zeros (with shifts a baseline is
-  // < 1 GiB, so no offset wraps).  Without shifts every read is in range.
+  // scalar offset), and the buffer's record limit, the T_rows APs the data
+  // hold (T, or more in a streaming plan, whose stage holds the lookahead
+  // the shifts need), turns the reads past the data into zeros (with shifts
+  // a baseline is < 1 GiB, so no offset wraps).  Without shifts every read
+  // is in range.
   const bool has_s = a.shifts != nullptr;
   // byte offset of the lane's sample of fold h in an AP row (natural order:
   // each load is one contiguous segment)
   auto shifted_off = [&](int h) -> uint32_t {
     if (!lane_in[h]) return 0u;
     uint32_t o = lane8 + static_cast<uint32_t>(64 * sizeof(float2) * h);
-    if (has_s) o += static_cast<uint32_t>(min(max(a.shifts[lane + 64 * h], 0), T)) * row_bytes;
+    if (has_s)
+      o += static_cast<uint32_t>(min(max(a.shifts[lane + 64 * h], 0), a.T_rows)) * row_bytes;
     return o;
   };
   uint32_t lane_off[TAB_LDS ? 1 : HFMAX];
@@ -215,7 +218,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   }
   const auto vrs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float2*>(xb), static_cast<short>(0),
-      static_cast<int>(static_cast<uint32_t>(T) * row_bytes), kBufferWord3);
+      static_cast<int>(static_cast<uint32_t>(a.T_rows) * row_bytes), kBufferWord3);
   auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
     const uint32_t toff = static_cast<uint32_t>(min(t, T - 1)) * row_bytes;
     if constexpr (TAB_LDS) {

@@ -43,11 +43,12 @@ struct DelayArgs {
   const float2* vis;   // [nb][T][F] visibilities of the slab
   const float2* gains; // [nb][F] calibration gains of the slab, or nullptr
   const int32_t* shifts;  // [F] dedispersion shifts in APs, or nullptr
-  int64_t vis_stride;  // elements between baselines of vis (>= T * F)
+  int64_t vis_stride;  // elements between baselines of vis (>= T_rows * F)
   float2* X;           // [nb][T][M] delay spectra (out)
   float* e;            // [nb][T] per-AP energy sum |x|^2 (out)
   const float2* tw;    // [M] exp(-2 pi i k / M)
   int nb, T, F, M, log_m, pad_f;
+  int T_rows;          // APs of vis a shifted read may reach (>= T; reads past them are 0)
 };
 
 struct RateArgs {
@@ -85,6 +86,7 @@ struct FusedArgs {
   int64_t grid_per_bl;
   int64_t lvl_goff[kMaxLevels];
   int nb, T, F, M, R, hf, chunk, n_chunks, n_pairs, nwb;
+  int T_rows;          // APs of vis a shifted read may reach (>= T; reads past them are 0)
   int t_emit;          // windows must end at or after this AP (streaming)
   int lvl_off[kMaxLevels + 1];
   int lvl_j0[kMaxLevels];
