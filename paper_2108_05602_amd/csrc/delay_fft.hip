@@ -58,16 +58,61 @@ constexpr int first_radix(int log_m) { return log_m >= 4 ? 16 : (1 << log_m); }
 // Pass p has radix R and NS = product of the earlier radices:
 //   v[r] = in[j + r M/R] * w_{NS R}^{(j mod NS) r},  V = DFT_R(v),
 //   out[(j / NS) NS R + (j mod NS) + k NS] = V[k].
+// LDS slot of element i of the group's transforms: one float2 of padding
+// after every 16, so that a pass's strided writes (16 or 256 elements apart
+// across threads) spread over the banks instead of landing on two of them.
+__device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
+constexpr int lds_slots(int n) { return n + n / 16; }
+
+// The first pass's inputs: the NZ nonzero samples of each of the thread's
+// butterflies (the rest of the padded input is zero), calibrated.
+template <int M, int NAP, int R, int PF, int NT>
+struct FirstInputs {
+  static constexpr int BPL = NAP * M / R / NT;
+  static constexpr int NZ = R / PF > 0 ? R / PF : 1;
+  float2 x[BPL][NZ];
+};
+
+template <int M, int NAP, int R, int PF, int NT>
+__device__ __forceinline__ void load_first(FirstInputs<M, NAP, R, PF, NT>& in,
+                                           const float2* __restrict__ xin, int lane,
+                                           int n_valid_ap, int F,
+                                           const float2* __restrict__ gains,
+                                           const int32_t* __restrict__ shifts,
+                                           const float2* __restrict__ xbl, int t_first, int T) {
+  using In = FirstInputs<M, NAP, R, PF, NT>;
+  constexpr int SPAN = M / R;
+#pragma unroll
+  for (int i = 0; i < In::BPL; ++i) {
+    const int jj = lane + NT * i;
+    const int a = jj / SPAN;
+    const int j = jj % SPAN;
+    const bool ok = a < n_valid_ap;
+#pragma unroll
+    for (int r = 0; r < In::NZ; ++r) {
+      const int idx = j + r * SPAN;
+      float2 x = make_float2(0.f, 0.f);
+      if (ok && idx < F) {
+        if (shifts) {  // dedispersion: channel idx from AP t + d, 0 past the data
+          const int row = t_first + a + min(max(shifts[idx], 0), T);
+          if (row < T) x = xbl[static_cast<int64_t>(row) * F + idx];  // T: the rows held
+        } else {
+          x = xin[static_cast<int64_t>(a) * F + idx];
+        }
+        if (gains) x = c_mul(x, gains[idx]);  // calibration
+      }
+      in.x[i][r] = x;
+    }
+  }
+}
+
 // NT threads (one to four waves) share the NAP transforms of a work group.
+// The first pass takes its inputs from `pre` (loaded ahead by load_first).
 template <int M, int NAP, int R, int NS, int PF, bool FIRST, bool LAST, int NT>
-__device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restrict__ xin,
-                                              float2* __restrict__ xout,
+__device__ __forceinline__ void stockham_pass(float2* lds, float2* __restrict__ xout,
                                               const float2* __restrict__ tw, int lane,
-                                              int n_valid_ap, int F, float* esum,
-                                              const float2* __restrict__ gains = nullptr,
-                                              const int32_t* __restrict__ shifts = nullptr,
-                                              const float2* __restrict__ xbl = nullptr,
-                                              int t_first = 0, int T = 0) {
+                                              int n_valid_ap, float* esum,
+                                              const FirstInputs<M, NAP, R, PF, NT>* pre) {
   constexpr int NBF = NAP * M / R;   // butterflies in this pass
   constexpr int BPL = NBF / NT;      // per thread
   static_assert(BPL >= 1 && NBF % NT == 0, "pass does not fill the work group");
@@ -80,32 +125,24 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
     const int a = jj / SPAN;
     const int j = jj % SPAN;
     if constexpr (FIRST) {
-      const bool ok = a < n_valid_ap;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (r < NZ) {
-          const int idx = j + r * SPAN;
-          float2 x = make_float2(0.f, 0.f);
-          if (ok && idx < F) {
-            if (shifts) {  // dedispersion: channel idx from AP t + d, 0 past the data
-              const int row = t_first + a + min(max(shifts[idx], 0), T);
-              if (row < T) x = xbl[static_cast<int64_t>(row) * F + idx];  // T: the rows held
-            } else {
-              x = xin[static_cast<int64_t>(a) * F + idx];
-            }
-            if (gains) x = c_mul(x, gains[idx]);  // calibration
-          }
-          v[i][r] = x;
-          *esum += c_norm(x);
+          v[i][r] = pre->x[i][r];
+          *esum += c_norm(v[i][r]);
         } else {
           v[i][r] = make_float2(0.f, 0.f);
         }
       }
     } else {
       const int jm = j % NS;
+      // SPAN is a multiple of 16, so the padding of element base + r SPAN
+      // is the base's plus r SPAN / 16: one slot computation per butterfly
+      static_assert(SPAN % 16 == 0, "LDS padding assumes 16-element spans");
+      const int sb = lds_slot(a * M + j);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 x = lds[a * M + j + r * SPAN];
+        float2 x = lds[sb + r * (SPAN + SPAN / 16)];
         if (r > 0) x = c_mul(x, tw[(jm * r) * (M / (NS * R))]);
         v[i][r] = x;
       }
@@ -119,13 +156,18 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* __restr
     const int j = jj % SPAN;
     fft_dif_pruned<R, NZ>(v[i]);
     const int idxd = (j / NS) * NS * R + (j % NS);
+    // element base + k NS: with NS = 1 the base is a multiple of 16 (R = 16)
+    // and k < 16; with NS a multiple of 16 the padding grows by NS / 16 per k
+    static_assert(LAST || (NS == 1 && R == 16) || NS % 16 == 0, "LDS padding");
+    const int sb = lds_slot(a * M + idxd);
+    constexpr int KSTEP = NS == 1 ? 1 : NS + NS / 16;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const float2 y = v[i][bitrev(k, ilog2(R))];
       if constexpr (LAST) {
         if (a < n_valid_ap) xout[static_cast<int64_t>(a) * M + idxd + k * NS] = y;
       } else {
-        lds[a * M + idxd + k * NS] = y;
+        lds[sb + k * KSTEP] = y;
       }
     }
   }
@@ -140,8 +182,8 @@ __device__ __forceinline__ void later_passes(float2* lds, float2* xout, const fl
     constexpr int rem = ilog2(M / NS);
     constexpr int R = rem >= 4 ? 16 : (1 << rem);
     constexpr bool LAST = (NS * R == M);
-    stockham_pass<M, NAP, R, NS, PF, false, LAST, NT>(lds, nullptr, xout, tw, lane, n_valid_ap,
-                                                      F, nullptr);
+    stockham_pass<M, NAP, R, NS, PF, false, LAST, NT>(lds, xout, tw, lane, n_valid_ap, nullptr,
+                                                      nullptr);
     later_passes<M, NAP, PF, NS * R, NT>(lds, xout, tw, lane, n_valid_ap, F);
   }
 }
@@ -160,24 +202,38 @@ __global__ void __launch_bounds__(fft_threads(LOGM)) delay_fft_kernel(DelayArgs 
   constexpr int R0 = first_radix(LOGM);
   constexpr int GROUP = (M / R0) < 64 ? (M / R0) : 64;  // lanes per AP in the first pass
   extern __shared__ float2 lds[];
-  float* lds_e = reinterpret_cast<float*>(lds + NAP * M);  // per-wave energy partials
+  float* lds_e = reinterpret_cast<float*>(lds + lds_slots(NAP * M));  // per-wave energy partials
   const int lane = threadIdx.x;
   const int groups_per_bl = (a.T + NAP - 1) / NAP;
   const int64_t n_groups = static_cast<int64_t>(a.nb) * groups_per_bl;
   const int F = a.F;
+  constexpr bool ONE_PASS = (R0 == M);
+  // the first pass's inputs of group g, loaded one group ahead so that the
+  // loads are in flight while the group before is transformed
+  using In = FirstInputs<M, NAP, R0, PF, NT>;
+  auto load_group = [&](int64_t g, In& in) {
+    const int b = static_cast<int>(g / groups_per_bl);
+    const int t0 = static_cast<int>(g % groups_per_bl) * NAP;
+    const int n_valid = min(NAP, a.T - t0);
+    const float2* xin = a.vis + static_cast<int64_t>(b) * a.vis_stride + static_cast<int64_t>(t0) * F;
+    const float2* gains = a.gains ? a.gains + static_cast<int64_t>(b) * F : nullptr;
+    const float2* xbl = a.vis + static_cast<int64_t>(b) * a.vis_stride;
+    load_first<M, NAP, R0, PF, NT>(in, xin, lane, n_valid, F, gains, a.shifts, xbl, t0,
+                                   a.T_rows);
+  };
+  In nxt;
+  if (static_cast<int64_t>(blockIdx.x) < n_groups) load_group(blockIdx.x, nxt);
   for (int64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    const In cur = nxt;
+    if (g + gridDim.x < n_groups) load_group(g + gridDim.x, nxt);
     const int b = static_cast<int>(g / groups_per_bl);
     const int t0 = static_cast<int>(g % groups_per_bl) * NAP;
     const int n_valid = min(NAP, a.T - t0);
     const int64_t ap0 = static_cast<int64_t>(b) * a.T + t0;
-    const float2* xin = a.vis + static_cast<int64_t>(b) * a.vis_stride + static_cast<int64_t>(t0) * F;
     float2* xout = a.X + ap0 * M;
     float es = 0.f;
-    constexpr bool ONE_PASS = (R0 == M);
-    const float2* gains = a.gains ? a.gains + static_cast<int64_t>(b) * F : nullptr;
-    const float2* xbl = a.vis + static_cast<int64_t>(b) * a.vis_stride;
-    stockham_pass<M, NAP, R0, 1, PF, true, ONE_PASS, NT>(lds, xin, xout, a.tw, lane, n_valid, F,
-                                                         &es, gains, a.shifts, xbl, t0, a.T_rows);
+    stockham_pass<M, NAP, R0, 1, PF, true, ONE_PASS, NT>(lds, xout, a.tw, lane, n_valid, &es,
+                                                         &cur);
     // AP energies: lanes of one AP form an aligned group of GROUP lanes
     // (with several waves on one AP, each wave's sum goes through LDS; the
     // first pass's closing barrier orders the previous AP's reads of it)
@@ -209,7 +265,7 @@ hipError_t launch_one(const DelayArgs& a, hipStream_t st) {
   const int64_t groups = static_cast<int64_t>(a.nb) * ((a.T + NAP - 1) / NAP);
   if (groups == 0) return hipSuccess;
   const int grid = static_cast<int>(groups < 65536 ? groups : 65536);
-  const size_t lds = static_cast<size_t>(NAP) * M * sizeof(float2) + 16 * sizeof(float);
+  const size_t lds = static_cast<size_t>(lds_slots(NAP * M)) * sizeof(float2) + 16 * sizeof(float);
   hipLaunchKernelGGL((delay_fft_kernel<LOGM, PF>), dim3(grid), dim3(fft_threads(LOGM)), lds, st,
                      a);
   return hipGetLastError();

@@ -163,7 +163,15 @@ def test_shift_errors():
     print("case: shift errors", flush=True)
     desc = dict(n_baselines=1, n_ap=100, n_if=2, n_chan=32, ap_seconds=1e-3, chan_width_hz=1e6)
     d = torch.zeros(64, dtype=torch.int32, device="cuda")
+    v = torch.zeros((1, 100, 2, 32), dtype=torch.complex64, device="cuda")
+    # streaming plans take shifts before their first search, not after
     with F.Plan([desc], [4], flags=F.FRINGE_STREAMING) as p:
+        p.set_shifts(0, d.data_ptr())
+        p.search([v.data_ptr()], torch.cuda.current_stream().cuda_stream)
+        with pytest.raises(F.FringeError) as e:
+            p.set_shifts(0, d.data_ptr())
+        assert e.value.code == -6
+    with F.Plan([desc], [4], flags=F.FRINGE_PLAIN) as p:
         with pytest.raises(F.FringeError) as e:
             p.set_shifts(0, d.data_ptr())
         assert e.value.code == -2
