@@ -535,14 +535,16 @@ C3_WORKLOAD = ("Batched uneven: 200 scans of 10-120 s (1.024 ms APs), 3-12 stati
 
 
 def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=True,
-                compare_default=True):
+                compare_default=True, tune_load=None, tune_save=None):
     """The batched uneven workload: per wave, generate its scans on the
     device, build one plan, search it `warmup` times untimed and `steps`
     times timed (each search with its candidate copy, bracketed by device
     synchronisations).  Step k's time is the sum over the waves of their
     k-th timed search.  cpu_sample, if a list, receives host copies of a
     few baselines' first APs from one scan of each band width (the CPU
-    reference's sample of this workload)."""
+    reference's sample of this workload).  tune_load: a tune table file
+    read instead of tuning (no timing launches in the run); tune_save: where
+    to write the table afterwards."""
     import torch
 
     import paper_2108_05602_amd as F
@@ -555,6 +557,8 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
     flags = F.FRINGE_PROFILE | (F.FRINGE_AUTOTUNE if autotune else 0)
     if autotune:
         F.fringe_tune_clear()
+        if tune_load:
+            F.fringe_tune_load(tune_load)
     plan_s = 0.0
     entries = {}
     cmp = None
@@ -655,6 +659,8 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
             f"{gen_s:.1f} s, search {np.median(wt) * 1e3:.1f} ms, {len(c)} candidates")
         del tens
         torch.cuda.empty_cache()
+    if autotune and tune_save:
+        F.fringe_tune_save(tune_save)
     ms = float(np.mean(step_s)) * 1e3
     flops_step = fl[0] + fl[1] + fl[2]
     # the search kernels of a step: the fused kernels (delay transform, rate
@@ -686,7 +692,7 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
                                "finalize_ms": fin_ms / steps, "compact_ms": comp_ms / steps},
         "tflops_algorithmic_step": flops_step / (ms / 1e3) / 1e12,
         "hbm_gbs_algorithmic": cube / (ms / 1e3) / 1e9,
-        "autotune": {"enabled": autotune, "plan_s_total": plan_s,
+        "autotune": {"enabled": autotune, "plan_s_total": plan_s, "table_loaded": bool(tune_load),
                      "entries": [entries[k] for k in sorted(entries)],
                      "tuned_vs_default": cmp},
     }
@@ -779,6 +785,21 @@ def large_dense_leg(steps=2):
             if pr["delay_ms"] > 0 else None}
 
 
+def calibration_copy(mib):
+    """One device-to-device copy of `mib` MiB: a plain copy kernel of known
+    size, for scaling hardware byte counters."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {n} bytes read, {n} bytes written")
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def evn_scan_legs(args, out):
     """The EVN-like single scan: its own search (5 steps), then the legs
     that compare paths on it."""
@@ -795,15 +816,8 @@ def evn_scan_legs(args, out):
     dev = torch.from_numpy(v).to("cuda:0")
     del v
     torch.cuda.synchronize()
-    if args.calibrate_copy:
-        n = args.calibrate_copy << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy: {n} bytes read, {n} bytes written")
-        del src, dst
+    if args.calibrate_copy and args.only == "c2":
+        calibration_copy(args.calibrate_copy)
     steps = args.evn_steps
     plan = F.Plan([spec.desc()], params["window_aps"], pad_freq=params["pad_freq"],
                   pad_time=params["pad_time"], snr_threshold=params["snr_threshold"],
@@ -898,9 +912,15 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="headline plans with the default configurations (no tuning)")
+    ap.add_argument("--tune-load", metavar="JSON", default=None,
+                    help="headline: read this tune table instead of tuning")
+    ap.add_argument("--tune-save", metavar="JSON", default=None,
+                    help="headline: write the tune table here afterwards")
+    ap.add_argument("--no-compare-default", action="store_true",
+                    help="headline: skip timing wave 0 with the default configurations")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="before the EVN search, copy a MIB-MiB device buffer once (a plain copy "
-                         "kernel of known size for scaling hardware byte counters)")
+                    help="before the first search, copy a MIB-MiB device buffer once (a plain "
+                         "copy kernel of known size for scaling hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -920,10 +940,14 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic"}
     sample = []
+    if args.calibrate_copy and args.only != "c2":
+        calibration_copy(args.calibrate_copy)
     if args.only != "c2":
         h = c3_headline(args.steps, args.warmup, args.wave_gb, n_scans=args.c3_scans,
                         cpu_sample=None if args.no_cpu_baseline else sample,
-                        autotune=not args.no_autotune)
+                        autotune=not args.no_autotune,
+                        compare_default=not args.no_compare_default,
+                        tune_load=args.tune_load, tune_save=args.tune_save)
         out["value"] = h["value"]
         out["ms_per_step"] = h["ms_per_step"]
         out["config"] = {"workload": C3_WORKLOAD if args.c3_scans == 200 else

@@ -221,6 +221,23 @@ int fringe_set_gains(fringe_plan_t plan, int32_t scan, const fringe_cf32* d_gain
  * of 1 GiB or more of samples. */
 int fringe_set_shifts(fringe_plan_t plan, int32_t scan, const int32_t* d_shifts);
 
+/* Time chunk of scan's search (section "Parallelization": a scan is cut
+ * into time ranges that are searched independently; here the ranges are
+ * the work items of one search).  A work item searches the windows starting in its chunk
+ * of APs and transforms W_max - 1 APs of halo besides, so longer chunks
+ * transform fewer APs twice and shorter ones give more work items.  The
+ * automatic choice (chunk 0, or the tune table's with FRINGE_AUTOTUNE)
+ * fills the device with this plan's work alone; plans searched at the same
+ * time on several streams (one per subarray in a server) share the device
+ * and may do better with longer chunks.  Results are bit-identical for
+ * every chunk.  chunk: 0, or a multiple of the search period (4 APs for
+ * W_max <= 8, 16 up to 32, 32 for 64) in [64, 1024].  Before the plan's
+ * first search (FRINGE_E_STATE after); the plan's device buffers are made
+ * again.  FRINGE_E_UNSUPPORTED for plans with windows longer than 64 APs,
+ * whose chunk is fixed.  fringe_plan_get_chunk reads the chunk in use. */
+int fringe_plan_set_chunk(fringe_plan_t plan, int32_t scan, int32_t chunk);
+int fringe_plan_get_chunk(fringe_plan_t plan, int32_t scan, int32_t* chunk);
+
 /* Dedispersion as a pass of its own, for plans without shifts (paper:
  * section "Code optimization", step 4): d_out[b][t][f] = d_in[b][t + d_f][f],
  * 0 where t + d_f >= n_ap, d_f = d_shifts[f] clamped to [0, n_ap] (the

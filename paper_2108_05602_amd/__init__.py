@@ -14,6 +14,7 @@ from .binding import (CANDIDATE_DTYPE, PULSE_DTYPE, FRINGE_AUTOTUNE, FRINGE_DELA
                       fringe_set_gains, fringe_set_shifts, fringe_dedisperse, fringe_match, fringe_localize,
                       fringe_delay_partials, fringe_autospectrum_gains, fringe_search_noalloc,
                       fringe_tune_load, fringe_tune_save, fringe_tune_clear, fringe_plan_tuning,
+                      fringe_plan_set_chunk, fringe_plan_get_chunk,
                       fringe_strerror, fringe_window_id, fringe_windows_get, load)
 
 __all__ = [
@@ -23,5 +24,6 @@ __all__ = [
     "fringe_set_gains", "fringe_set_shifts", "fringe_dedisperse", "fringe_match", "fringe_localize",
     "fringe_delay_partials", "fringe_autospectrum_gains", "fringe_search_noalloc",
     "fringe_tune_load", "fringe_tune_save", "fringe_tune_clear", "fringe_plan_tuning",
+    "fringe_plan_set_chunk", "fringe_plan_get_chunk",
     "fringe_strerror", "fringe_window_id", "fringe_windows_get", "load",
 ]

@@ -49,7 +49,7 @@ ENTRY_POINTS = (
     "fringe_match", "fringe_localize", "fringe_delay_partials",
     "fringe_probe_fma", "fringe_probe_copy", "fringe_search_noalloc",
     "fringe_autospectrum_gains", "fringe_tune_load", "fringe_tune_save", "fringe_tune_clear",
-    "fringe_plan_tuning",
+    "fringe_plan_tuning", "fringe_plan_set_chunk", "fringe_plan_get_chunk",
 )
 
 
@@ -167,6 +167,8 @@ def load(path: Optional[str] = None):
     lib.fringe_tune_clear.restype = None
     lib.fringe_plan_tuning.argtypes = [c_void_p, POINTER(fringe_tune_entry), c_int32,
                                        POINTER(c_int32)]
+    lib.fringe_plan_set_chunk.argtypes = [c_void_p, c_int32, c_int32]
+    lib.fringe_plan_get_chunk.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
     for name in ENTRY_POINTS:
         if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
                         "fringe_tune_clear"):
@@ -326,6 +328,21 @@ def fringe_set_shifts(plan: int, scan: int, d_shifts) -> None:
     lib = load()
     _check(lib.fringe_set_shifts(c_void_p(plan), c_int32(int(scan)), c_void_p(d_shifts or None)),
            "fringe_set_shifts")
+
+
+def fringe_plan_set_chunk(plan: int, scan: int, chunk: int) -> None:
+    """APs per work item of scan's search (0: automatic); before the first search."""
+    lib = load()
+    _check(lib.fringe_plan_set_chunk(c_void_p(plan), c_int32(int(scan)), c_int32(int(chunk))),
+           "fringe_plan_set_chunk")
+
+
+def fringe_plan_get_chunk(plan: int, scan: int) -> int:
+    lib = load()
+    out = c_int32(0)
+    _check(lib.fringe_plan_get_chunk(c_void_p(plan), c_int32(int(scan)), ctypes.byref(out)),
+           "fringe_plan_get_chunk")
+    return int(out.value)
 
 
 def fringe_search_noalloc(scan: dict, window_aps, d_vis: int, d_out: int, capacity: int,
@@ -513,6 +530,12 @@ class Plan:
 
     def set_shifts(self, scan, d_shifts):
         fringe_set_shifts(self.handle, scan, d_shifts)
+
+    def set_chunk(self, scan, chunk):
+        fringe_plan_set_chunk(self.handle, scan, chunk)
+
+    def chunk(self, scan=0):
+        return fringe_plan_get_chunk(self.handle, scan)
 
     def profile(self):
         return fringe_profile_get(self.handle)

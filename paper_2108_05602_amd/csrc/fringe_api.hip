@@ -1119,6 +1119,23 @@ int tune_class(const TuneKey& key, const fringe_params* params, int w_max, TuneV
   return FRINGE_OK;
 }
 
+// Make an unsearched plan again with other search modes / chunks or
+// dedispersion lookaheads, keeping the caller's handle, its gains, shifts
+// and tune entries; on failure the plan is left as it was.
+int remake_plan(fringe_plan_t p, const std::vector<ScanForce>& force,
+                const std::vector<int>& lookahead) {
+  fringe_plan_t np = nullptr;
+  const int rc = make_plan(p->descs.data(), int32_t(p->descs.size()), &p->params,
+                           force.empty() ? nullptr : &force, &np, &lookahead);
+  if (rc != FRINGE_OK) return rc;
+  std::swap(np->gains, p->gains);
+  std::swap(np->shifts, p->shifts);
+  std::swap(np->tuned, p->tuned);
+  std::swap(*np, *p);
+  fringe_plan_destroy(np);
+  return FRINGE_OK;
+}
+
 // FRINGE_AUTOTUNE: the tune table's configuration of every scan's class,
 // tuning the classes it lacks.
 int autotune_plan(const fringe_scan_desc* scans, int32_t n_scans, const fringe_params* params,
@@ -1593,16 +1610,8 @@ int fringe_set_shifts(fringe_plan_t p, int32_t scan, const int32_t* d_shifts) {
     if (d_max != p->lookahead[k]) {
       std::vector<int> la = p->lookahead;
       la[k] = d_max;
-      fringe_plan_t np = nullptr;
-      int rc = make_plan(p->descs.data(), int32_t(p->descs.size()), &p->params,
-                         p->force.empty() ? nullptr : &p->force, &np, &la);
+      const int rc = remake_plan(p, p->force, la);
       if (rc != FRINGE_OK) return rc;
-      // keep the caller's plan handle: swap the contents, free the old ones
-      std::swap(np->gains, p->gains);
-      std::swap(np->shifts, p->shifts);
-      std::swap(np->tuned, p->tuned);
-      std::swap(*np, *p);
-      fringe_plan_destroy(np);
     }
   }
   if (d_shifts) {
@@ -1611,6 +1620,31 @@ int fringe_set_shifts(fringe_plan_t p, int32_t scan, const int32_t* d_shifts) {
       return fail(FRINGE_E_UNSUPPORTED, "scan %d: dedispersion needs baselines under 1 GiB", scan);
   }
   p->shifts[size_t(scan)] = d_shifts;
+  return FRINGE_OK;
+}
+
+int fringe_plan_set_chunk(fringe_plan_t p, int32_t scan, int32_t chunk) {
+  if (!p) return fail(FRINGE_E_INVALID, "null plan");
+  const int ns = int(p->sz.scans.size());
+  if (scan < 0 || scan >= ns) return fail(FRINGE_E_INVALID, "scan %d out of range [0, %d)", scan, ns);
+  if (!p->sz.fused)
+    return fail(FRINGE_E_UNSUPPORTED, "plans with windows longer than 64 APs have a fixed chunk");
+  const int period = fused_period(p->sz.w_max);
+  if (chunk != 0 && (chunk < 64 || chunk > 1024 || chunk % period != 0))
+    return fail(FRINGE_E_INVALID, "chunk %d: 0, or a multiple of %d in [64, 1024]", chunk, period);
+  if (p->searched) return fail(FRINGE_E_STATE, "the chunk is set before the plan's first search");
+  std::vector<ScanForce> f = p->force;
+  if (f.empty()) f.assign(size_t(ns), ScanForce{});
+  f[size_t(scan)].chunk = chunk;
+  f[size_t(scan)].exact = chunk != 0;
+  return remake_plan(p, f, p->lookahead);
+}
+
+int fringe_plan_get_chunk(fringe_plan_t p, int32_t scan, int32_t* chunk) {
+  if (!p || !chunk) return fail(FRINGE_E_INVALID, "null argument");
+  const int ns = int(p->sz.scans.size());
+  if (scan < 0 || scan >= ns) return fail(FRINGE_E_INVALID, "scan %d out of range [0, %d)", scan, ns);
+  *chunk = p->sz.scans[size_t(scan)].chunk;
   return FRINGE_OK;
 }
 

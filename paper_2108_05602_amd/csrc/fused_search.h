@@ -150,6 +150,10 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   const int b = q / a.n_chunks;
   const int chunk = q - b * a.n_chunks;
   const int T = a.T, F = a.F, M = a.M, hf = a.hf;
+  // read here, outside every lane-dependent branch, so that it stays a
+  // scalar: a copy in a vector register makes the buffer descriptor built
+  // from it non-uniform, and every load then runs in a loop over lanes
+  const int T_rows = __builtin_amdgcn_readfirstlane(a.T_rows);
   const int own_lo = chunk * a.chunk;
   const int own_hi = min(T, own_lo + a.chunk);
   const int t_end = min(T, own_hi + WMAX - 1);
@@ -204,7 +208,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
     if (!lane_in[h]) return 0u;
     uint32_t o = lane8 + static_cast<uint32_t>(64 * sizeof(float2) * h);
     if (has_s)
-      o += static_cast<uint32_t>(min(max(a.shifts[lane + 64 * h], 0), a.T_rows)) * row_bytes;
+      o += static_cast<uint32_t>(min(max(a.shifts[lane + 64 * h], 0), T_rows)) * row_bytes;
     return o;
   };
   uint32_t lane_off[TAB_LDS ? 1 : HFMAX];
@@ -218,7 +222,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   }
   const auto vrs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float2*>(xb), static_cast<short>(0),
-      static_cast<int>(static_cast<uint32_t>(a.T_rows) * row_bytes), kBufferWord3);
+      static_cast<int>(static_cast<uint32_t>(T_rows) * row_bytes), kBufferWord3);
   auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
     const uint32_t toff = static_cast<uint32_t>(min(t, T - 1)) * row_bytes;
     if constexpr (TAB_LDS) {

@@ -87,7 +87,15 @@ class FringeServer:
     def __init__(self, subarrays: Sequence[dict], window_aps, *, pad_freq: int = 4,
                  pad_time: int = 2, snr_threshold: float = 4.5, hbm_budget_bytes: int = 0,
                  max_candidates: int = 1 << 16, max_slots: Optional[int] = None,
+                 time_chunk: int = 0, shifts: Optional[Sequence[object]] = None,
                  device: str = "cuda:0"):
+        """time_chunk: APs per work item of every plan's search (0: each
+        plan's automatic choice, which sizes it to fill the device alone;
+        the plans here share the device, so longer chunks transform fewer
+        halo APs).  shifts: per subarray, a device int32 tensor of F
+        dedispersion shifts (or None): its chunks are searched dedispersed,
+        each call reporting the windows that end max(shift) APs before the
+        chunk's end."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -95,6 +103,12 @@ class FringeServer:
         self.plans = [Plan([s], window_aps, pad_freq=pad_freq, pad_time=pad_time,
                            snr_threshold=snr_threshold, max_candidates=max_candidates,
                            flags=FRINGE_STREAMING) for s in self.subs]
+        self.shifts = list(shifts) if shifts is not None else [None] * len(self.subs)
+        for p, sh in zip(self.plans, self.shifts):
+            if sh is not None:
+                p.set_shifts(0, sh.data_ptr())
+            if time_chunk:
+                p.set_chunk(0, time_chunk)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in self.subs]
         self.chunk_elems = [s["n_baselines"] * s["n_ap"] * s["n_if"] * s["n_chan"] for s in self.subs]
         slot_elems = max(self.chunk_elems)
@@ -238,7 +252,7 @@ class FringeBatchServer:
 
     def __init__(self, subarrays: Sequence[dict], window_aps, *, pad_freq: int = 4,
                  pad_time: int = 2, snr_threshold: float = 4.5, max_candidates: int = 1 << 18,
-                 device: str = "cuda:0"):
+                 time_chunk: int = 0, device: str = "cuda:0"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -247,6 +261,9 @@ class FringeBatchServer:
         self.plan = Plan(self.subs, window_aps, pad_freq=pad_freq, pad_time=pad_time,
                          snr_threshold=snr_threshold, max_candidates=max_candidates,
                          flags=FRINGE_STREAMING)
+        if time_chunk:
+            for s in range(len(self.subs)):
+                self.plan.set_chunk(s, time_chunk)
         self.stream = torch.cuda.Stream(device=self.device)
         self.slots = [torch.empty(s["n_baselines"] * s["n_ap"] * s["n_if"] * s["n_chan"],
                                   dtype=torch.complex64, device=self.device) for s in self.subs]
