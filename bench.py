@@ -60,13 +60,32 @@ MEASURED_TRAFFIC = {
 KERNEL_SOURCES = ("dev_common.h", "window_key.h", "fused_search.h", "kernels.h",
                   "fused_p2_w32.hip", "fused_dispatch.hip", "fringe_api.hip")
 
+# HBM bytes of the batched headline's search kernels (every launch of the
+# fused kernel, the delay transform and the kernel reading the spectra in
+# one step), from the same counters and copy scaling (FETCH_SIZE x 1.99992,
+# WRITE_SIZE x 1.0), with the launch configuration the autotuner chose then
+# (per band: spectra mode, time chunk).  Reported only while the sources
+# below hash alike and the run's tuning and launch count are the same.
+MEASURED_TRAFFIC_C3 = {
+    "kernel_sha256": "8bf6279edd239ce6dfef660e1632aebe42e386ece6999d85d85bfd12b439678b",
+    "fetch_bytes": 5629403430533,
+    "write_bytes": 4100720632416,
+    "launches_per_step": 1112,
+    "tuning": {128: (0, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
+}
+C3_SOURCES = ("csrc/dev_common.h", "csrc/window_key.h", "csrc/fused_search.h", "csrc/kernels.h",
+              "csrc/fused_p2_w64.hip", "csrc/fused_x_p2.hip", "csrc/delay_fft.hip",
+              "csrc/fused_dispatch.hip", "csrc/fringe_api.hip", "csrc/tune_table.cpp",
+              "csrc/twiddles.hip", "../synth/__init__.py", "../synth/device.py")
 
-def kernel_hash():
+
+def kernel_hash(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources or KERNEL_SOURCES:
         h.update(name.encode())
-        with open(os.path.join(ROOT, "paper_2108_05602_amd", "csrc", name), "rb") as fh:
+        path = os.path.join(ROOT, "paper_2108_05602_amd", name if sources else os.path.join("csrc", name))
+        with open(os.path.normpath(path), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -456,26 +475,35 @@ class _Cycle:
 
 
 def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
-                    loads=(0.5, 1.0, 1.5, 2.0)):
+                    loads=(0.5, 1.0, 1.5, 2.0), time_chunks=(0, 128, 256, 512), dm=100.0):
     """Streamed subarrays through the continuous-batching server.
 
     Six subarrays of 3-12 stations (8 IF x 32 chan, 1.024 ms APs), chunks of
     976 APs (1 s) staged in HBM (each subarray's first n_distinct chunks,
-    replayed in order).  R* = chunks/s with every chunk queued at t = 0; then
-    Poisson arrivals per subarray at x * R* / n_sub for each load x, and the
-    p50 / p99 of arrival -> candidates-on-host latency.  A last point feeds
-    the chunks from pinned host memory (H2D copy inside the latency)."""
+    replayed in order).  The plans' time chunk is chosen by the saturated
+    rate (every chunk queued at t = 0) of each candidate; R* = that rate
+    over a run three times as long; then Poisson arrivals per subarray at
+    x * R* / n_sub for each load x, and the p50 / p99 of arrival ->
+    candidates-on-host latency.  `sustained_chunks_per_s` is the largest
+    rate served over all runs, `served_vs_batch` its windows/s over those of
+    one batch search of the same subarrays' staged chunks.  Further points:
+    chunks fed from pinned host memory (H2D copy inside the latency), the
+    subarrays dedispersed at DM `dm` (channels from 1.6 GHz), and the
+    one-launch-per-step server."""
     import torch
 
+    import paper_2108_05602_amd as F
     import synth
+    from paper_2108_05602_amd.dedisp import channel_freqs_hz, dm_shifts
     from paper_2108_05602_amd.serve import (FringeBatchServer, FringeServer, poisson_schedule,
                                             run_schedule)
     specs = synth.c4_subarrays(n_sub, n_chunks=n_distinct, chunk_ap=chunk_ap)
-    dev, host = [], []
+    dev, host, whole = [], [], []
     for s in specs:
         v = s.full(threads=min(16, os.cpu_count() or 1))
         t = torch.from_numpy(v)
-        dev.append([t[:, k * chunk_ap:(k + 1) * chunk_ap].contiguous().to("cuda:0")
+        whole.append(t[:, :n_distinct * chunk_ap].contiguous().to("cuda:0"))
+        dev.append([whole[-1][:, k * chunk_ap:(k + 1) * chunk_ap].contiguous()
                     for k in range(n_distinct)])
         host.append([t[:, k * chunk_ap:(k + 1) * chunk_ap].contiguous().pin_memory()
                      for k in range(min(2, n_distinct))])
@@ -486,8 +514,8 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
            "chunks_per_point": per_sub * n_sub,
            "staging": f"first {n_distinct} chunks of each subarray's stream resident in HBM, replayed"}
 
-    def run(payloads, sched, server=FringeServer):
-        srv = server(subs, WS_C4, snr_threshold=4.5)
+    def run(payloads, sched, server=FringeServer, **kw):
+        srv = server(subs, WS_C4, snr_threshold=4.5, **kw)
         try:
             run_schedule(srv, [(0.0, s, k) for s in range(n_sub) for k in range(2)], payloads)
             st = run_schedule(srv, sched, payloads)
@@ -496,29 +524,78 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
         torch.cuda.synchronize()
         return st.summary()
 
+    def burst(n):
+        return [(0.0, s, k) for s in range(n_sub) for k in range(n)]
+
     pd = [_Cycle(c) for c in dev]
-    sat = run(pd, [(0.0, s, k) for s in range(n_sub) for k in range(per_sub)])
+    sweep = {}
+    for c in time_chunks:
+        sweep[c] = run(pd, burst(per_sub), time_chunk=c)["chunks_per_s"]
+        log(f"serving time chunk {c or 'auto'}: {sweep[c]:.0f} chunks/s saturated")
+    tc = max(sweep, key=sweep.get)
+    out["time_chunk"] = {"chosen": tc, "saturated_chunks_per_s": {str(k): v for k, v in sweep.items()}}
+    sat = run(pd, burst(3 * per_sub), time_chunk=tc)
     r_star = sat["chunks_per_s"]
     out["saturated"] = sat
     out["r_star_chunks_per_s"] = r_star
     out["points"] = []
     for x in loads:
-        s = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)))
+        s = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)),
+                time_chunk=tc)
         s["load"] = x
         out["points"].append(s)
         log(f"serving load {x}: p50 {s['p50_ms']:.3f} ms, p99 {s['p99_ms']:.3f} ms, "
             f"{s['chunks_per_s']:.0f} chunks/s")
+    best = max([sat] + out["points"], key=lambda p: p["windows_per_s"])
+    out["sustained_chunks_per_s"] = best["chunks_per_s"]
+    # the same staged chunks as one batch search (whole streams, one plan)
+    st = torch.cuda.current_stream()
+    bdesc = [dict(s.desc(), n_ap=n_distinct * chunk_ap) for s in specs]
+    with F.Plan(bdesc, WS_C4, snr_threshold=4.5) as bp:
+        ptrs = [w.data_ptr() for w in whole]
+        for _ in range(2):
+            bp.search(ptrs, st.cuda_stream)
+            bp.candidates()
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bp.search(ptrs, st.cuda_stream)
+            bp.candidates()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        b_wps = bp.info()["n_windows"] / float(np.median(ts))
+    out["batch_windows_per_s"] = b_wps
+    out["served_windows_per_s"] = best["windows_per_s"]
+    out["served_vs_batch"] = best["windows_per_s"] / b_wps
+    log(f"serving: sustained {best['chunks_per_s']:.0f} chunks/s, {best['windows_per_s'] / 1e6:.1f} M "
+        f"windows/s = {out['served_vs_batch']:.2f} of batch ({b_wps / 1e6:.1f} M windows/s)")
     ph = [_Cycle(c) for c in host]
-    hs = run(ph, [(0.0, s, k) for s in range(n_sub) for k in range(per_sub)])
-    hp = run(ph, poisson_schedule(n_sub, per_sub, 0.5 * hs["chunks_per_s"] / n_sub, seed=7))
+    hs = run(ph, burst(per_sub), time_chunk=tc)
+    hp = run(ph, poisson_schedule(n_sub, per_sub, 0.5 * hs["chunks_per_s"] / n_sub, seed=7),
+             time_chunk=tc)
     hp["load"] = 0.5
     out["pinned_host"] = {"r_star_chunks_per_s": hs["chunks_per_s"], "point": hp}
+    # dedispersed serving: every subarray at one DM
+    shifts = []
+    for sd in subs:
+        f = channel_freqs_hz(1.6e9, sd["n_if"], sd["n_chan"], sd["chan_width_hz"])
+        shifts.append(torch.from_numpy(dm_shifts(dm, f, sd["ap_seconds"])).to("cuda:0"))
+    dsat = run(pd, burst(per_sub), time_chunk=tc, shifts=shifts)
+    dpt = run(pd, poisson_schedule(n_sub, per_sub, dsat["chunks_per_s"] / n_sub, seed=11),
+              time_chunk=tc, shifts=shifts)
+    dpt["load"] = 1.0
+    out["dedispersed"] = {"dm": dm, "max_shift_ap": int(max(int(x.max()) for x in shifts)),
+                          "r_star_chunks_per_s": dsat["chunks_per_s"], "saturated": dsat,
+                          "point": dpt}
+    log(f"serving at DM {dm}: {dsat['chunks_per_s']:.0f} chunks/s saturated, p50 "
+        f"{dpt['p50_ms']:.3f} ms, p99 {dpt['p99_ms']:.3f} ms at that load")
     # the same loads through one launch per step over all waiting subarrays
-    bsat = run(pd, [(0.0, s, k) for s in range(n_sub) for k in range(per_sub)], FringeBatchServer)
+    bsat = run(pd, burst(per_sub), FringeBatchServer, time_chunk=tc)
     out["batched"] = {"r_star_chunks_per_s": bsat["chunks_per_s"], "saturated": bsat, "points": []}
     for x in loads:
         s = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)),
-                FringeBatchServer)
+                FringeBatchServer, time_chunk=tc)
         s["load"] = x
         out["batched"]["points"].append(s)
         log(f"serving (batched) load {x} of the per-subarray R*: p50 {s['p50_ms']:.3f} ms, "
@@ -671,6 +748,13 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
     avg_launch_s = (fused_ms + delay_ms) / max(1, fused_n + delay_n) / 1e3
     flops_per_launch = flops_step / launches_per_step
     achieved = flops_per_launch / avg_launch_s / 1e12
+    mt = MEASURED_TRAFFIC_C3
+    tuned = {k: (v["spectra"], v["chunk"]) for k, v in entries.items()}
+    traffic = None
+    if (n_scans == 200 and autotune and tuned == mt["tuning"] and
+            launches_per_step == mt["launches_per_step"] and
+            kernel_hash(C3_SOURCES) == mt["kernel_sha256"]):
+        traffic = (mt["fetch_bytes"] + mt["write_bytes"]) / launches_per_step
     return {
         "value": n_windows / (ms / 1e3), "ms_per_step": ms, "windows": n_windows, "cube_bytes": cube,
         "candidates": n_cands, "waves": waves_out, "scans": len(specs),
@@ -681,7 +765,7 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
                       "fused_search_kernel reading the spectra",
             "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "algorithmic_flops_per_launch": flops_per_launch,
             "algorithmic_bytes_per_launch": (cube + part_bytes + e_bytes) / launches_per_step,
@@ -692,6 +776,8 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
                                "finalize_ms": fin_ms / steps, "compact_ms": comp_ms / steps},
         "tflops_algorithmic_step": flops_step / (ms / 1e3) / 1e12,
         "hbm_gbs_algorithmic": cube / (ms / 1e3) / 1e9,
+        "hbm_gbs_measured": (None if traffic is None else
+                             traffic * launches_per_step / (ms / 1e3) / 1e9),
         "autotune": {"enabled": autotune, "plan_s_total": plan_s, "table_loaded": bool(tune_load),
                      "entries": [entries[k] for k in sorted(entries)],
                      "tuned_vs_default": cmp},
@@ -956,6 +1042,7 @@ def main():
                          "waves": len(h["waves"]), "parallelism": "single GPU"}
         out["roofline"] = h["roofline"]
         for k in ("kernel_ms_per_step", "tflops_algorithmic_step", "hbm_gbs_algorithmic",
+                  "hbm_gbs_measured",
                   "candidates", "waves", "autotune"):
             out[k] = h[k]
         out["hbm_frac_algorithmic"] = h["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
