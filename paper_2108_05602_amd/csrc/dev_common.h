@@ -73,6 +73,15 @@ __device__ __forceinline__ float in_vgpr(float v) {
   return r;
 }
 
+// A wave-uniform value (held in a scalar register) copied to a vector
+// register once, so that the FMAs reading it issue at the full rate, not at
+// the half rate of a scalar operand.
+__device__ __forceinline__ float uniform_in_vgpr(float v) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+  return r;
+}
+
 // ---------------------------------------------------------------- complex --
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -54,7 +54,9 @@ rate_peak_kernel(RateArgs a) {
   extern __shared__ float2 ring[];  // [kRing][64], then kWaves uint64 partials
   uint64_t* wave_pk = reinterpret_cast<uint64_t*>(ring + kRing * kBinsPerWave);
   const int lane = threadIdx.x & (kBinsPerWave - 1);
-  const int wv = threadIdx.x / kBinsPerWave;
+  // the wave index, uniform in the wave (a scalar): the sub-transforms it
+  // selects then read their twiddles with scalar loads
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kBinsPerWave);
   const int item = blockIdx.x;
   const int kb = item % a.n_kb;
   const int rest = item / a.n_kb;
@@ -109,7 +111,7 @@ rate_peak_kernel(RateArgs a) {
         // hoisting all 128 samples into registers.
         const int off = (start & (kRing - 1)) * kBinsPerWave;
         const LdsU64* vcol = (const LdsU64*)(mycol);
-        const uint32_t key = window_key<kLogRing, PT, DUMP>(
+        const uint32_t key = window_key<kLogRing, PT, DUMP, true>(
             [&](auto ui) {
               constexpr int u = decltype(ui)::value;
               const uint64_t v = u < kRing / 2 ? vcol[u * kBinsPerWave + off]

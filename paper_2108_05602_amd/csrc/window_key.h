@@ -50,8 +50,11 @@ static __constant__ TwTable kTw256{};
 // X(u) returns the window's u-th sample (compile-time u).  DUMP writes each
 // G[k_t] to dump[k_t * dump_stride].  For long windows (S > 4) the key may
 // cover only the sub-transforms r = r0, r0 + r_step, ... (the rate bins
-// k_t = r mod S), so that several waves can share one window.
-template <int LOGW, int PT, bool DUMP, typename XF>
+// k_t = r mod S), so that several waves can share one window.  VTW: move
+// those windows' twiddles (read into scalar registers) to vector registers
+// before use: the 128-AP ring kernel measured faster so, the 64-AP windows
+// of the fused kernel slower (the moves cost more than the scalar operands).
+template <int LOGW, int PT, bool DUMP, bool VTW = false, typename XF>
 __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump,
                                                int dump_stride, int r0 = 0, int r_step = 1) {
   using Sh = RateShape<LOGW, PT>;
@@ -72,17 +75,39 @@ __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump
     uint32_t key = 0;
     for (int r = r0; r < S; r += r_step) {
       float2 y[N];
-      static_for<0, N>([&](auto vi) {
-        constexpr int v = decltype(vi)::value;
-        float2 acc = X(std::integral_constant<int, v>{});
+      if constexpr (VTW) {
+        auto tw = [](int k) {
+          const float2 w = kTw256.v[k & (kTwN - 1)];
+          return make_float2(uniform_in_vgpr(w.x), uniform_in_vgpr(w.y));
+        };
+        float2 wh[H];
         static_for<1, H>([&](auto hi) {
           constexpr int h = decltype(hi)::value;
-          const float2 w = kTw256.v[((r * h) * (kTwN / S)) & (kTwN - 1)];
-          acc = c_add(acc, c_mul(X(std::integral_constant<int, v + N * h>{}), w));
+          wh[h] = tw((r * h) * (kTwN / S));
         });
-        if constexpr (v == 0) y[v] = acc;
-        else y[v] = c_mul(acc, kTw256.v[((r * v) * (kTwN / MT)) & (kTwN - 1)]);
-      });
+        static_for<0, N>([&](auto vi) {
+          constexpr int v = decltype(vi)::value;
+          float2 acc = X(std::integral_constant<int, v>{});
+          static_for<1, H>([&](auto hi) {
+            constexpr int h = decltype(hi)::value;
+            acc = c_add(acc, c_mul(X(std::integral_constant<int, v + N * h>{}), wh[h]));
+          });
+          if constexpr (v == 0) y[v] = acc;
+          else y[v] = c_mul(acc, tw((r * v) * (kTwN / MT)));
+        });
+      } else {
+        static_for<0, N>([&](auto vi) {
+          constexpr int v = decltype(vi)::value;
+          float2 acc = X(std::integral_constant<int, v>{});
+          static_for<1, H>([&](auto hi) {
+            constexpr int h = decltype(hi)::value;
+            const float2 w = kTw256.v[((r * h) * (kTwN / S)) & (kTwN - 1)];
+            acc = c_add(acc, c_mul(X(std::integral_constant<int, v + N * h>{}), w));
+          });
+          if constexpr (v == 0) y[v] = acc;
+          else y[v] = c_mul(acc, kTw256.v[((r * v) * (kTwN / MT)) & (kTwN - 1)]);
+        });
+      }
       fft_dif<N>(y);
       static_for<0, N>([&](auto pi) {
         constexpr int p = decltype(pi)::value;

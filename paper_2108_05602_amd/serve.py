@@ -123,7 +123,8 @@ class FringeServer:
         self.slots = [torch.empty(slot_elems, dtype=torch.complex64, device=self.device)
                       for _ in range(n_slots)]
         self.free = list(range(n_slots))
-        self.queue: collections.deque = collections.deque()
+        # per subarray, its chunks waiting in arrival order
+        self.queues = [collections.deque() for _ in self.subs]
         self.busy: Dict[int, tuple] = {}   # sub -> (request, slot, event)
         self.clock0 = time.perf_counter()
 
@@ -132,7 +133,7 @@ class FringeServer:
         return time.perf_counter() - self.clock0
 
     def submit(self, req: Request) -> None:
-        self.queue.append(req)
+        self.queues[req.sub].append(req)
 
     def inflight(self) -> int:
         return len(self.busy)
@@ -158,19 +159,17 @@ class FringeServer:
 
     # ---------------------------------------------------------- internals --
     def _admit(self):
-        if not self.queue or not self.free:
+        # idle subarrays with a chunk waiting, oldest head first: the
+        # first-come order across subarrays, each subarray's chunks in turn
+        if not self.free:
             return
-        held = set(self.busy)
-        keep = collections.deque()
-        while self.queue:
-            req = self.queue.popleft()
-            if self.free and req.sub not in held:
-                self._launch(req, self.free.pop())
-                held.add(req.sub)
-            else:
-                keep.append(req)
-                held.add(req.sub)   # later chunks of this subarray wait behind it
-        self.queue = keep
+        ready = [q[0] for sub, q in enumerate(self.queues) if q and sub not in self.busy]
+        ready.sort(key=lambda r: (r.arrival, r.sub))
+        for req in ready:
+            if not self.free:
+                break
+            self.queues[req.sub].popleft()
+            self._launch(req, self.free.pop())
 
     def _launch(self, req: Request, slot: int):
         torch = self.torch
