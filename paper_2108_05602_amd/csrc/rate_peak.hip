@@ -111,15 +111,20 @@ rate_peak_kernel(RateArgs a) {
         // hoisting all 128 samples into registers.
         const int off = (start & (kRing - 1)) * kBinsPerWave;
         const LdsU64* vcol = (const LdsU64*)(mycol);
-        const uint32_t key = window_key<kLogRing, PT, DUMP, true>(
-            [&](auto ui) {
-              constexpr int u = decltype(ui)::value;
-              const uint64_t v = u < kRing / 2 ? vcol[u * kBinsPerWave + off]
-                                               : vcol[u * kBinsPerWave - off];
-              return make_float2(__uint_as_float(static_cast<uint32_t>(v)),
-                                 __uint_as_float(static_cast<uint32_t>(v >> 32)));
-            },
-            dump, M, wv, kWaves);
+        auto sample = [&](auto ui) {
+          constexpr int u = decltype(ui)::value;
+          const uint64_t v = u < kRing / 2 ? vcol[u * kBinsPerWave + off]
+                                           : vcol[u * kBinsPerWave - off];
+          return make_float2(__uint_as_float(static_cast<uint32_t>(v)),
+                             __uint_as_float(static_cast<uint32_t>(v >> 32)));
+        };
+        // S = 2 kWaves sub-transforms (pad_time 2): wave wv takes the pair
+        // r = wv, wv + kWaves in one pass; else one or none each
+        uint32_t key;
+        if constexpr (RateShape<kLogRing, PT>::S == 2 * kWaves)
+          key = window_key_pair<kLogRing, PT, DUMP>(sample, dump, M, wv);
+        else
+          key = window_key<kLogRing, PT, DUMP, true>(sample, dump, M, wv, kWaves);
         const uint64_t pk = wave_peak(key, kb * kBinsPerWave, 1);
         if (lane == 0) wave_pk[wv] = pk;
         __syncthreads();  // every wave's partial is in, and the ring may be refilled

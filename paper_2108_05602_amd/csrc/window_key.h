@@ -147,6 +147,69 @@ __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump
   }
 }
 
+// The sub-transforms r and r + S/2 of a long window together (S >= 8, the
+// twiddles as with VTW).  Since w_S^{(r + S/2) h} = (-1)^h w_S^{r h}, both
+// come from the sums of the same twiddled samples over even and over odd h:
+//   y_r[v]       = w_{M_t}^{r v}            (E[v] + O[v]),
+//   y_{r+S/2}[v] = w_{M_t}^{r v} w_{2N}^{v} (E[v] - O[v]),
+// so each sample is read and twiddled once for the pair.
+template <int LOGW, int PT, bool DUMP, typename XF>
+__device__ __forceinline__ uint32_t window_key_pair(XF&& X, float2* __restrict__ dump,
+                                                    int dump_stride, int r) {
+  using Sh = RateShape<LOGW, PT>;
+  constexpr int MT = Sh::MT, S = Sh::S, N = Sh::N, H = Sh::H;
+  constexpr uint32_t MASK = Sh::MASK;
+  static_assert(S >= 8 && H >= 2, "pairs of a long window's sub-transforms");
+  auto tw = [](int k) {
+    const float2 w = kTw256.v[k & (kTwN - 1)];
+    return make_float2(uniform_in_vgpr(w.x), uniform_in_vgpr(w.y));
+  };
+  float2 wh[H];
+  static_for<1, H>([&](auto hi) {
+    constexpr int h = decltype(hi)::value;
+    wh[h] = tw((r * h) * (kTwN / S));
+  });
+  float2 ya[N], yb[N];
+  static_for<0, N>([&](auto vi) {
+    constexpr int v = decltype(vi)::value;
+    float2 e = X(std::integral_constant<int, v>{});
+    float2 o = make_float2(0.f, 0.f);
+    static_for<1, H>([&](auto hi) {
+      constexpr int h = decltype(hi)::value;
+      const float2 t = c_mul(X(std::integral_constant<int, v + N * h>{}), wh[h]);
+      if constexpr (h % 2 == 0) e = c_add(e, t);
+      else o = c_add(o, t);
+    });
+    if constexpr (v == 0) {
+      ya[v] = c_add(e, o);
+      yb[v] = c_sub(e, o);
+    } else {
+      const float2 w = tw((r * v) * (kTwN / MT));
+      ya[v] = c_mul(c_add(e, o), w);
+      yb[v] = twiddle_mul<2 * N, v>(c_mul(c_sub(e, o), w));
+    }
+  });
+  fft_dif<N>(ya);
+  fft_dif<N>(yb);
+  uint32_t key = 0;
+  static_for<0, N>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    const uint32_t kta = static_cast<uint32_t>(S * p + r);
+    const uint32_t ktb = kta + S / 2;
+    const float2 va = ya[bitrev(p, ilog2(N))];
+    const float2 vb = yb[bitrev(p, ilog2(N))];
+    const uint32_t ka = rate_key(c_norm(va), MASK, kta);
+    const uint32_t kb = rate_key(c_norm(vb), MASK, ktb);
+    key = ka > key ? ka : key;
+    key = kb > key ? kb : key;
+    if constexpr (DUMP) {
+      dump[static_cast<int64_t>(kta) * dump_stride] = va;
+      dump[static_cast<int64_t>(ktb) * dump_stride] = vb;
+    }
+  });
+  return key;
+}
+
 // ------------------------------------------------------ DPP reductions --
 // Full-mask DPP moves with bound_ctrl set: every lane of the patterns used
 // here has a source lane, and the form lets the compiler fold the move into
