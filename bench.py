@@ -476,29 +476,32 @@ class _Cycle:
 
 def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
                     loads=(0.5, 1.0, 1.5, 2.0), time_chunks=(0, 128, 256, 336, 496), dm=100.0):
-    """Streamed subarrays through the continuous-batching server.
+    """Streamed subarrays through the continuous-batching servers.
 
     Six subarrays of 3-12 stations (8 IF x 32 chan, 1.024 ms APs), chunks of
     976 APs (1 s) staged in HBM (each subarray's first n_distinct chunks,
-    replayed in order).  The plans' time chunk is chosen by the saturated
-    rate (every chunk queued at t = 0) of each candidate; R* = the rate
-    served, in a run three times as long, while every subarray still has
-    chunks waiting (up to the first subarray's last result: after it the
-    GPU serves fewer subarrays than it was offered); then Poisson arrivals per subarray at
-    x * R* / n_sub for each load x, and the p50 / p99 of arrival ->
-    candidates-on-host latency.  `sustained_chunks_per_s` is the largest
-    rate served over all runs, `served_vs_batch` its windows/s over those of
-    one batch search of the same subarrays' staged chunks.  Further points:
-    chunks fed from pinned host memory (H2D copy inside the latency), the
+    replayed in order).  Per server: the plans' time chunk is chosen by the
+    saturated rate (every chunk queued at t = 0) of each candidate; R* = the
+    rate served, in a run three times as long, while every subarray still
+    has chunks waiting (up to the first subarray's last result: after it
+    the GPU serves fewer subarrays than it was offered); then Poisson
+    arrivals per subarray at x * R* / n_sub for each load x, and the p50 /
+    p99 of arrival -> candidates-on-host latency.  `sustained_*` is the
+    largest rate served over those runs, `served_vs_batch` its windows/s
+    over those of one batch search of the same staged chunks.  The servers:
+    the library's native one (primary: admission, launches and collection
+    in its worker thread), the Python per-subarray one, and the
+    one-launch-per-step one; further points: the native server with the
     subarrays dedispersed at DM `dm` (channels from 1.6 GHz), and the
-    one-launch-per-step server."""
+    Python server fed from pinned host memory (H2D copy inside the
+    latency)."""
     import torch
 
     import paper_2108_05602_amd as F
     import synth
     from paper_2108_05602_amd.dedisp import channel_freqs_hz, dm_shifts
-    from paper_2108_05602_amd.serve import (FringeBatchServer, FringeServer, poisson_schedule,
-                                            run_schedule)
+    from paper_2108_05602_amd.serve import (FringeBatchServer, FringeNativeServer, FringeServer,
+                                            poisson_schedule, run_schedule)
     specs = synth.c4_subarrays(n_sub, n_chunks=n_distinct, chunk_ap=chunk_ap)
     dev, host, whole = [], [], []
     for s in specs:
@@ -510,13 +513,14 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
         host.append([t[:, k * chunk_ap:(k + 1) * chunk_ap].contiguous().pin_memory()
                      for k in range(min(2, n_distinct))])
         del v, t
+    torch.cuda.synchronize()
     subs = [dict(s.desc(), n_ap=chunk_ap) for s in specs]
     per_sub = max(1, chunks_per_point // n_sub)
     out = {"subarrays": [s["n_baselines"] for s in subs], "chunk_ap": chunk_ap,
            "chunks_per_point": per_sub * n_sub,
            "staging": f"first {n_distinct} chunks of each subarray's stream resident in HBM, replayed"}
 
-    def run(payloads, sched, server=FringeServer, steady=False, **kw):
+    def run(payloads, sched, server, steady=False, **kw):
         srv = server(subs, WS_C4, snr_threshold=4.5, **kw)
         try:
             run_schedule(srv, [(0.0, s, k) for s in range(n_sub) for k in range(2)], payloads)
@@ -524,44 +528,21 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
         finally:
             srv.close()
         torch.cuda.synchronize()
-        out = st.summary()
+        res = st.summary()
         if steady:
             # served while every subarray is busy: up to the first
             # subarray's last result (arrivals all at t = 0)
             t_end = min(max(r.done for r in st.results if r.sub == s) for s in range(n_sub))
             done = [r for r in st.results if r.done <= t_end]
-            out["steady_s"] = t_end
-            out["steady_chunks_per_s"] = len(done) / t_end
-            out["steady_windows_per_s"] = sum(r.n_windows for r in done) / t_end
-        return out
+            res["steady_s"] = t_end
+            res["steady_chunks_per_s"] = len(done) / t_end
+            res["steady_windows_per_s"] = sum(r.n_windows for r in done) / t_end
+        return res
 
     def burst(n):
         return [(0.0, s, k) for s in range(n_sub) for k in range(n)]
 
     pd = [_Cycle(c) for c in dev]
-    sweep = {}
-    for c in time_chunks:
-        sweep[c] = run(pd, burst(per_sub), time_chunk=c)["chunks_per_s"]
-        log(f"serving time chunk {c or 'auto'}: {sweep[c]:.0f} chunks/s saturated")
-    tc = max(sweep, key=sweep.get)
-    out["time_chunk"] = {"chosen": tc, "saturated_chunks_per_s": {str(k): v for k, v in sweep.items()}}
-    sat = run(pd, burst(3 * per_sub), time_chunk=tc, steady=True)
-    r_star = sat["steady_chunks_per_s"]
-    out["saturated"] = sat
-    out["r_star_chunks_per_s"] = r_star
-    out["points"] = []
-    for x in loads:
-        s = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)),
-                time_chunk=tc)
-        s["load"] = x
-        out["points"].append(s)
-        log(f"serving load {x}: p50 {s['p50_ms']:.3f} ms, p99 {s['p99_ms']:.3f} ms, "
-            f"{s['chunks_per_s']:.0f} chunks/s")
-    # the largest rate served: saturated and steady, or at a load point
-    rates = [(sat["steady_chunks_per_s"], sat["steady_windows_per_s"])] + \
-        [(p["chunks_per_s"], p["windows_per_s"]) for p in out["points"]]
-    best = dict(zip(("chunks_per_s", "windows_per_s"), max(rates, key=lambda r: r[1])))
-    out["sustained_chunks_per_s"] = best["chunks_per_s"]
     # the same staged chunks as one batch search (whole streams, one plan)
     st = torch.cuda.current_stream()
     bdesc = [dict(s.desc(), n_ap=n_distinct * chunk_ap) for s in specs]
@@ -580,41 +561,73 @@ def serving_latency(n_sub=6, n_distinct=8, chunk_ap=976, chunks_per_point=600,
             ts.append(time.perf_counter() - t0)
         b_wps = bp.info()["n_windows"] / float(np.median(ts))
     out["batch_windows_per_s"] = b_wps
-    out["served_windows_per_s"] = best["windows_per_s"]
-    out["served_vs_batch"] = best["windows_per_s"] / b_wps
-    log(f"serving: sustained {best['chunks_per_s']:.0f} chunks/s, {best['windows_per_s'] / 1e6:.1f} M "
-        f"windows/s = {out['served_vs_batch']:.2f} of batch ({b_wps / 1e6:.1f} M windows/s)")
-    ph = [_Cycle(c) for c in host]
-    hs = run(ph, burst(per_sub), time_chunk=tc)
-    hp = run(ph, poisson_schedule(n_sub, per_sub, 0.5 * hs["chunks_per_s"] / n_sub, seed=7),
-             time_chunk=tc)
-    hp["load"] = 0.5
-    out["pinned_host"] = {"r_star_chunks_per_s": hs["chunks_per_s"], "point": hp}
-    # dedispersed serving: every subarray at one DM
+
+    def measure(server, label, **kw):
+        sweep = {}
+        for c in time_chunks:
+            sweep[c] = run(pd, burst(per_sub), server, time_chunk=c, **kw)["chunks_per_s"]
+            log(f"serving ({label}) time chunk {c or 'auto'}: {sweep[c]:.0f} chunks/s saturated")
+        tc = max(sweep, key=sweep.get)
+        sat = run(pd, burst(3 * per_sub), server, steady=True, time_chunk=tc, **kw)
+        r_star = sat["steady_chunks_per_s"]
+        m = {"time_chunk": {"chosen": tc,
+                            "saturated_chunks_per_s": {str(k): v for k, v in sweep.items()}},
+             "saturated": sat, "r_star_chunks_per_s": r_star, "points": []}
+        for x in loads:
+            p = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)),
+                    server, time_chunk=tc, **kw)
+            p["load"] = x
+            m["points"].append(p)
+            log(f"serving ({label}) load {x}: p50 {p['p50_ms']:.3f} ms, p99 {p['p99_ms']:.3f} ms, "
+                f"{p['chunks_per_s']:.0f} chunks/s")
+        rates = [(sat["steady_chunks_per_s"], sat["steady_windows_per_s"])] + \
+            [(p["chunks_per_s"], p["windows_per_s"]) for p in m["points"]]
+        best = max(rates, key=lambda r: r[1])
+        m["sustained_chunks_per_s"], m["served_windows_per_s"] = best
+        m["served_vs_batch"] = best[1] / b_wps
+        log(f"serving ({label}): R* {r_star:.0f} chunks/s, sustained {best[0]:.0f} chunks/s, "
+            f"{best[1] / 1e6:.1f} M windows/s = {m['served_vs_batch']:.2f} of batch "
+            f"({b_wps / 1e6:.1f} M windows/s)")
+        return m
+
+    nat = measure(FringeNativeServer, "native")
+    out.update(nat)
+    out["server"] = "FringeNativeServer (library worker thread)"
+    out["python"] = measure(FringeServer, "python")
+    tc = nat["time_chunk"]["chosen"]
+    # dedispersed serving: every subarray at one DM, native server
     shifts = []
     for sd in subs:
         f = channel_freqs_hz(1.6e9, sd["n_if"], sd["n_chan"], sd["chan_width_hz"])
         shifts.append(torch.from_numpy(dm_shifts(dm, f, sd["ap_seconds"])).to("cuda:0"))
-    dsat = run(pd, burst(3 * per_sub), time_chunk=tc, shifts=shifts, steady=True)
+    dsat = run(pd, burst(3 * per_sub), FringeNativeServer, steady=True, time_chunk=tc, shifts=shifts)
     dpt = run(pd, poisson_schedule(n_sub, per_sub, dsat["steady_chunks_per_s"] / n_sub, seed=11),
-              time_chunk=tc, shifts=shifts)
+              FringeNativeServer, time_chunk=tc, shifts=shifts)
     dpt["load"] = 1.0
     out["dedispersed"] = {"dm": dm, "max_shift_ap": int(max(int(x.max()) for x in shifts)),
                           "r_star_chunks_per_s": dsat["steady_chunks_per_s"], "saturated": dsat,
                           "point": dpt}
-    log(f"serving at DM {dm}: {dsat['steady_chunks_per_s']:.0f} chunks/s saturated, p50 "
+    log(f"serving (native) at DM {dm}: R* {dsat['steady_chunks_per_s']:.0f} chunks/s, p50 "
         f"{dpt['p50_ms']:.3f} ms, p99 {dpt['p99_ms']:.3f} ms at that load")
-    # the same loads through one launch per step over all waiting subarrays
-    bsat = run(pd, burst(3 * per_sub), FringeBatchServer, time_chunk=tc, steady=True)
+    # pinned host chunks (H2D copy inside the latency), Python server
+    tcp = out["python"]["time_chunk"]["chosen"]
+    ph = [_Cycle(c) for c in host]
+    hs = run(ph, burst(per_sub), FringeServer, time_chunk=tcp)
+    hp = run(ph, poisson_schedule(n_sub, per_sub, 0.5 * hs["chunks_per_s"] / n_sub, seed=7),
+             FringeServer, time_chunk=tcp)
+    hp["load"] = 0.5
+    out["pinned_host"] = {"r_star_chunks_per_s": hs["chunks_per_s"], "point": hp}
+    # one launch per step over all waiting subarrays
+    bsat = run(pd, burst(3 * per_sub), FringeBatchServer, steady=True, time_chunk=tcp)
     out["batched"] = {"r_star_chunks_per_s": bsat["steady_chunks_per_s"], "saturated": bsat,
                       "points": []}
     for x in loads:
-        s = run(pd, poisson_schedule(n_sub, per_sub, x * r_star / n_sub, seed=int(x * 100)),
-                FringeBatchServer, time_chunk=tc)
-        s["load"] = x
-        out["batched"]["points"].append(s)
-        log(f"serving (batched) load {x} of the per-subarray R*: p50 {s['p50_ms']:.3f} ms, "
-            f"p99 {s['p99_ms']:.3f} ms, {s['chunks_per_s']:.0f} chunks/s")
+        p = run(pd, poisson_schedule(n_sub, per_sub, x * nat["r_star_chunks_per_s"] / n_sub,
+                                     seed=int(x * 100)), FringeBatchServer, time_chunk=tcp)
+        p["load"] = x
+        out["batched"]["points"].append(p)
+        log(f"serving (batched) load {x} of the native R*: p50 {p['p50_ms']:.3f} ms, "
+            f"p99 {p['p99_ms']:.3f} ms, {p['chunks_per_s']:.0f} chunks/s")
     return out
 
 

@@ -50,7 +50,16 @@ ENTRY_POINTS = (
     "fringe_probe_fma", "fringe_probe_copy", "fringe_search_noalloc",
     "fringe_autospectrum_gains", "fringe_tune_load", "fringe_tune_save", "fringe_tune_clear",
     "fringe_plan_tuning", "fringe_plan_set_chunk", "fringe_plan_get_chunk",
+    "fringe_monotonic_ns", "fringe_server_create", "fringe_server_set_shifts",
+    "fringe_server_submit", "fringe_server_poll", "fringe_server_pending",
+    "fringe_server_destroy",
 )
+
+
+class fringe_serve_result(Structure):
+    _fields_ = [("sub", c_int32), ("status", c_int32), ("tag", c_int64),
+                ("n_candidates", c_int64), ("n_total", c_int64), ("n_windows", c_int64),
+                ("t_submit_ns", c_int64), ("t_launch_ns", c_int64), ("t_done_ns", c_int64)]
 
 
 class fringe_scan_desc(Structure):
@@ -167,11 +176,21 @@ def load(path: Optional[str] = None):
     lib.fringe_tune_clear.restype = None
     lib.fringe_plan_tuning.argtypes = [c_void_p, POINTER(fringe_tune_entry), c_int32,
                                        POINTER(c_int32)]
+    lib.fringe_monotonic_ns.argtypes = []
+    lib.fringe_monotonic_ns.restype = c_int64
+    lib.fringe_server_create.argtypes = [POINTER(fringe_scan_desc), c_int32, POINTER(fringe_params),
+                                         c_int32, c_int32, POINTER(c_void_p)]
+    lib.fringe_server_set_shifts.argtypes = [c_void_p, c_int32, c_void_p]
+    lib.fringe_server_submit.argtypes = [c_void_p, c_int32, c_int64, c_void_p]
+    lib.fringe_server_poll.argtypes = [c_void_p, POINTER(fringe_serve_result), c_int32,
+                                       POINTER(c_int32), c_void_p, c_int64, POINTER(c_int64)]
+    lib.fringe_server_pending.argtypes = [c_void_p, POINTER(c_int64)]
+    lib.fringe_server_destroy.argtypes = [c_void_p]
     lib.fringe_plan_set_chunk.argtypes = [c_void_p, c_int32, c_int32]
     lib.fringe_plan_get_chunk.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
     for name in ENTRY_POINTS:
         if name not in ("fringe_plan_destroy", "fringe_strerror", "fringe_last_error",
-                        "fringe_tune_clear"):
+                        "fringe_tune_clear", "fringe_monotonic_ns"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -343,6 +362,64 @@ def fringe_plan_get_chunk(plan: int, scan: int) -> int:
     _check(lib.fringe_plan_get_chunk(c_void_p(plan), c_int32(int(scan)), ctypes.byref(out)),
            "fringe_plan_get_chunk")
     return int(out.value)
+
+
+def fringe_monotonic_ns() -> int:
+    """The library's clock (CLOCK_MONOTONIC, ns): time.perf_counter()'s on Linux."""
+    return int(load().fringe_monotonic_ns())
+
+
+def fringe_server_create(subs, window_aps, *, pad_freq=4, pad_time=2, snr_threshold=4.5,
+                         max_candidates=1 << 16, flags=0, time_chunk=0, max_inflight=0) -> int:
+    """A native continuous-batching server (fringe_serve.h); returns its handle."""
+    lib = load()
+    sa = _scan_array(subs)
+    p, _keep = _params(window_aps, pad_freq, pad_time, snr_threshold, 0, max_candidates, flags)
+    out = c_void_p()
+    _check(lib.fringe_server_create(sa, len(subs), ctypes.byref(p), int(time_chunk),
+                                    int(max_inflight), ctypes.byref(out)), "fringe_server_create")
+    return out.value
+
+
+def fringe_server_set_shifts(server: int, sub: int, d_shifts) -> None:
+    _check(load().fringe_server_set_shifts(c_void_p(server), c_int32(int(sub)),
+                                           c_void_p(d_shifts or None)), "fringe_server_set_shifts")
+
+
+def fringe_server_submit(server: int, sub: int, tag: int, d_chunk: int) -> None:
+    _check(load().fringe_server_submit(c_void_p(server), c_int32(int(sub)), c_int64(int(tag)),
+                                       c_void_p(int(d_chunk) or None)), "fringe_server_submit")
+
+
+def fringe_server_poll(server: int, res=None, cands=None):
+    """Finished chunks: (list of result dicts, candidate records concatenated
+    in the same order).  res / cands: reusable buffers (a ctypes array of
+    fringe_serve_result, a CANDIDATE_DTYPE array); the candidates returned
+    are a view of cands (a new array when it had to grow)."""
+    lib = load()
+    if res is None:
+        res = (fringe_serve_result * 64)()
+    if cands is None:
+        cands = np.empty(1 << 16, dtype=CANDIDATE_DTYPE)
+    n_out, n_c = c_int32(0), c_int64(0)
+    rc = lib.fringe_server_poll(c_void_p(server), res, len(res), ctypes.byref(n_out),
+                                cands.ctypes.data_as(c_void_p), len(cands), ctypes.byref(n_c))
+    if rc == FRINGE_E_CAPACITY:
+        return fringe_server_poll(server, res, np.empty(int(n_c.value), dtype=CANDIDATE_DTYPE))
+    _check(rc, "fringe_server_poll")
+    out = [{k: getattr(res[i], k) for k, _ in fringe_serve_result._fields_}
+           for i in range(n_out.value)]
+    return out, cands[:n_c.value]
+
+
+def fringe_server_pending(server: int) -> int:
+    n = c_int64(0)
+    _check(load().fringe_server_pending(c_void_p(server), ctypes.byref(n)), "fringe_server_pending")
+    return int(n.value)
+
+
+def fringe_server_destroy(server: int) -> None:
+    _check(load().fringe_server_destroy(c_void_p(server)), "fringe_server_destroy")
 
 
 def fringe_search_noalloc(scan: dict, window_aps, d_vis: int, d_out: int, capacity: int,

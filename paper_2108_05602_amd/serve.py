@@ -33,7 +33,9 @@ from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
-from .binding import FRINGE_STREAMING, Plan
+from .binding import (CANDIDATE_DTYPE, FRINGE_STREAMING, Plan, fringe_serve_result,
+                      fringe_server_create, fringe_server_destroy, fringe_server_pending,
+                      fringe_server_poll, fringe_server_set_shifts, fringe_server_submit)
 
 
 @dataclass
@@ -191,6 +193,72 @@ class FringeServer:
         ev = torch.cuda.Event()
         ev.record(st)
         self.busy[req.sub] = (req, slot, ev)
+
+
+class FringeNativeServer:
+    """The library's native server (fringe_server_*): the same per-subarray
+    plans and streams as FringeServer, admitted, launched and collected by
+    a worker thread in the library instead of this process's Python loop.
+    Chunks must already be in HBM (device tensors); a result's done time is
+    when the worker saw its search finish and copied its candidates (the
+    library's clock is CLOCK_MONOTONIC, which time.perf_counter reads)."""
+
+    def __init__(self, subarrays: Sequence[dict], window_aps, *, pad_freq: int = 4,
+                 pad_time: int = 2, snr_threshold: float = 4.5, max_candidates: int = 1 << 16,
+                 time_chunk: int = 0, max_inflight: int = 0,
+                 shifts: Optional[Sequence[object]] = None, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.subs = [dict(s) for s in subarrays]
+        self.handle = fringe_server_create(self.subs, window_aps, pad_freq=pad_freq,
+                                           pad_time=pad_time, snr_threshold=snr_threshold,
+                                           max_candidates=max_candidates,
+                                           time_chunk=time_chunk, max_inflight=max_inflight)
+        self.shifts = list(shifts) if shifts is not None else [None] * len(self.subs)
+        for i, sh in enumerate(self.shifts):
+            if sh is not None:
+                fringe_server_set_shifts(self.handle, i, sh.data_ptr())
+        self.held: Dict[int, Request] = {}   # tag -> request (its payload stays alive)
+        self.next_tag = 0
+        self._res = (fringe_serve_result * 64)()
+        self._cands = np.empty(max(1, max_candidates) * 4, dtype=CANDIDATE_DTYPE)
+        self.clock0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.clock0
+
+    def submit(self, req: Request) -> None:
+        pay = req.payload
+        if pay.device != self.device or not pay.is_contiguous():
+            raise ValueError("FringeNativeServer takes contiguous chunks already in device memory")
+        tag = self.next_tag
+        self.next_tag += 1
+        self.held[tag] = req
+        fringe_server_submit(self.handle, req.sub, tag, pay.data_ptr())
+
+    def inflight(self) -> int:
+        return fringe_server_pending(self.handle)
+
+    def poll(self) -> List[Result]:
+        res, cands = fringe_server_poll(self.handle, self._res, self._cands)
+        if len(cands) and not np.shares_memory(cands, self._cands):
+            self._cands = cands.base   # the buffer grew for a large result: keep it
+        out, k = [], 0
+        for r in res:
+            req = self.held.pop(r["tag"])
+            if r["status"] != 0:
+                raise RuntimeError(f"chunk {req.sub}/{req.seq}: search failed ({r['status']})")
+            n = r["n_candidates"]
+            out.append(Result(req.sub, req.seq, req.arrival, r["t_done_ns"] * 1e-9 - self.clock0,
+                              cands[k:k + n].copy(), r["n_windows"]))
+            k += n
+        return out
+
+    def close(self):
+        if self.handle:
+            fringe_server_destroy(self.handle)
+            self.handle = None
 
 
 def run_schedule(server: FringeServer, schedule, payloads, idle_sleep: float = 20e-6) -> ServeStats:

@@ -46,6 +46,41 @@ def test_struct_layouts():
     assert ctypes.sizeof(B.fringe_plan_summary) == 32
     assert ctypes.sizeof(B.fringe_match_params) == 8
     assert B.PULSE_DTYPE.itemsize == 72
+    assert ctypes.sizeof(B.fringe_serve_result) == 64
+
+
+def test_monotonic_clock_is_perf_counter():
+    """The server's timestamps share time.perf_counter's clock."""
+    import time
+    for _ in range(3):
+        a = time.perf_counter()
+        b = B.fringe_monotonic_ns() * 1e-9
+        c = time.perf_counter()
+        assert a - 1e-3 <= b <= c + 1e-3
+
+
+def test_server_argument_checks():
+    """Refused on the host, before any device work."""
+    lib = F.load()
+    out = ctypes.c_void_p()
+    sa = B._scan_array([C2])
+    p, keep = B._params(C2_W, 4, 2, 4.5, 0, 1024, 0)
+    assert lib.fringe_server_create(None, 1, ctypes.byref(p), 0, 0, ctypes.byref(out)) == B.FRINGE_E_INVALID
+    assert lib.fringe_server_create(sa, 0, ctypes.byref(p), 0, 0, ctypes.byref(out)) == B.FRINGE_E_INVALID
+    assert lib.fringe_server_create(sa, 1, ctypes.byref(p), 0, 2, ctypes.byref(out)) == B.FRINGE_E_INVALID
+    assert lib.fringe_server_create(sa, 1, ctypes.byref(p), 0, 0, None) == B.FRINGE_E_INVALID
+    for flag in (B.FRINGE_PLAIN, B.FRINGE_GRAPH):
+        q, keep2 = B._params(C2_W, 4, 2, 4.5, 0, 1024, flag)
+        assert lib.fringe_server_create(sa, 1, ctypes.byref(q), 0, 0,
+                                        ctypes.byref(out)) == B.FRINGE_E_UNSUPPORTED
+    n = ctypes.c_int64()
+    n32 = ctypes.c_int32()
+    assert lib.fringe_server_submit(None, 0, 0, ctypes.c_void_p(0x1000)) == B.FRINGE_E_INVALID
+    assert lib.fringe_server_poll(None, None, 0, ctypes.byref(n32), None, 0,
+                                  ctypes.byref(n)) == B.FRINGE_E_INVALID
+    assert lib.fringe_server_pending(None, ctypes.byref(n)) == B.FRINGE_E_INVALID
+    assert lib.fringe_server_set_shifts(None, 0, None) == B.FRINGE_E_INVALID
+    assert lib.fringe_server_destroy(None) == B.FRINGE_E_INVALID
 
 
 def test_dedisperse_argument_checks():
