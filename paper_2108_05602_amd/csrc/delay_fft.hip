@@ -165,7 +165,12 @@ __device__ __forceinline__ void stockham_pass(float2* lds, float2* __restrict__ 
     for (int k = 0; k < R; ++k) {
       const float2 y = v[i][bitrev(k, ilog2(R))];
       if constexpr (LAST) {
-        if (a < n_valid_ap) xout[static_cast<int64_t>(a) * M + idxd + k * NS] = y;
+        // streamed out (non-temporal): the spectra are read back by another
+        // kernel long after this one's caches have turned over
+        typedef float F2 __attribute__((ext_vector_type(2)));
+        if (a < n_valid_ap)
+          __builtin_nontemporal_store(
+              F2{y.x, y.y}, reinterpret_cast<F2*>(xout + static_cast<int64_t>(a) * M + idxd + k * NS));
       } else {
         lds[sb + k * KSTEP] = y;
       }

@@ -487,7 +487,9 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
                 const uint32_t j = static_cast<uint32_t>(start) >> fused::ilog2c(s);
                 dump = a.dump + gidx[L] + static_cast<int64_t>(j) * (PT * W) * M;
               }
-              const uint32_t key = window_key<L, PT, DUMP>(
+              // from spectra (registers to spare at two waves per SIMD): the
+              // 64-AP windows' sub-transforms by pairs
+              const uint32_t key = window_key<L, PT, DUMP, false, SRCX>(
                   [&](auto ui) { return hist[base + decltype(ui)::value]; }, dump, M);
               const uint64_t pk = peak_partial(key, wave_max_u32(key), kf_top, kf_step);
               if (lane == 0) pb[L][d] = pk;

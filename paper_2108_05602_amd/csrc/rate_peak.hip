@@ -122,7 +122,7 @@ rate_peak_kernel(RateArgs a) {
         // r = wv, wv + kWaves in one pass; else one or none each
         uint32_t key;
         if constexpr (RateShape<kLogRing, PT>::S == 2 * kWaves)
-          key = window_key_pair<kLogRing, PT, DUMP>(sample, dump, M, wv);
+          key = window_key_pair<kLogRing, PT, DUMP, true>(sample, dump, M, wv);
         else
           key = window_key<kLogRing, PT, DUMP, true>(sample, dump, M, wv, kWaves);
         const uint64_t pk = wave_peak(key, kb * kBinsPerWave, 1);

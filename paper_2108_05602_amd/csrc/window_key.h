@@ -54,7 +54,11 @@ static __constant__ TwTable kTw256{};
 // those windows' twiddles (read into scalar registers) to vector registers
 // before use: the 128-AP ring kernel measured faster so, the 64-AP windows
 // of the fused kernel slower (the moves cost more than the scalar operands).
-template <int LOGW, int PT, bool DUMP, bool VTW = false, typename XF>
+template <int LOGW, int PT, bool DUMP, bool VTW, typename XF>
+__device__ __forceinline__ uint32_t window_key_pair(XF&& X, float2* __restrict__ dump,
+                                                    int dump_stride, int r);
+
+template <int LOGW, int PT, bool DUMP, bool VTW = false, bool PAIR = false, typename XF>
 __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump,
                                                int dump_stride, int r0 = 0, int r_step = 1) {
   using Sh = RateShape<LOGW, PT>;
@@ -69,6 +73,14 @@ __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump
       });
     }
     return rate_key(c_norm(x0), MASK, 0);
+  } else if constexpr (S > 4 && PAIR) {
+    // long windows, their sub-transforms by pairs (r, r + S/2)
+    uint32_t key = 0;
+    for (int r = r0; r < S / 2; r += r_step) {
+      const uint32_t k = window_key_pair<LOGW, PT, DUMP, VTW>(X, dump, dump_stride, r);
+      key = k > key ? k : key;
+    }
+    return key;
   } else if constexpr (S > 4) {
     // long windows: the sub-transform index r runs at run time, its
     // twiddles w_S^{r h} and w_{M_t}^{r v} come from the uniform table
@@ -147,13 +159,12 @@ __device__ __forceinline__ uint32_t window_key(XF&& X, float2* __restrict__ dump
   }
 }
 
-// The sub-transforms r and r + S/2 of a long window together (S >= 8, the
-// twiddles as with VTW).  Since w_S^{(r + S/2) h} = (-1)^h w_S^{r h}, both
+// The sub-transforms r and r + S/2 of a long window together (S >= 8).  Since w_S^{(r + S/2) h} = (-1)^h w_S^{r h}, both
 // come from the sums of the same twiddled samples over even and over odd h:
 //   y_r[v]       = w_{M_t}^{r v}            (E[v] + O[v]),
 //   y_{r+S/2}[v] = w_{M_t}^{r v} w_{2N}^{v} (E[v] - O[v]),
 // so each sample is read and twiddled once for the pair.
-template <int LOGW, int PT, bool DUMP, typename XF>
+template <int LOGW, int PT, bool DUMP, bool VTW, typename XF>
 __device__ __forceinline__ uint32_t window_key_pair(XF&& X, float2* __restrict__ dump,
                                                     int dump_stride, int r) {
   using Sh = RateShape<LOGW, PT>;
@@ -162,7 +173,8 @@ __device__ __forceinline__ uint32_t window_key_pair(XF&& X, float2* __restrict__
   static_assert(S >= 8 && H >= 2, "pairs of a long window's sub-transforms");
   auto tw = [](int k) {
     const float2 w = kTw256.v[k & (kTwN - 1)];
-    return make_float2(uniform_in_vgpr(w.x), uniform_in_vgpr(w.y));
+    if constexpr (VTW) return make_float2(uniform_in_vgpr(w.x), uniform_in_vgpr(w.y));
+    else return w;
   };
   float2 wh[H];
   static_for<1, H>([&](auto hi) {
