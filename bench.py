@@ -45,14 +45,14 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 
 # HBM bytes of one fused-kernel launch on the full EVN-like scan, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
-# the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99989,
+# the same counter read for a 1 GiB device copy (FETCH_SIZE x 1.99992,
 # WRITE_SIZE x 1.0).  Valid only for the kernel and launch code they were
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "3e87854173e623969e313a29469c17d3cb49753863ed7e914e3f208226df2395",
-    "fetch_bytes": 8757093670,
-    "write_bytes": 2047807898,
+    "kernel_sha256": "e1a7e5ad49e14e98dfcf77a25134d6f579351a9d4875311e907bd90a097e922c",
+    "fetch_bytes": 8371253037,
+    "write_bytes": 2039289574,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
@@ -67,11 +67,11 @@ KERNEL_SOURCES = ("dev_common.h", "window_key.h", "fused_search.h", "kernels.h",
 # (per band: spectra mode, time chunk).  Reported only while the sources
 # below hash alike and the run's tuning and launch count are the same.
 MEASURED_TRAFFIC_C3 = {
-    "kernel_sha256": "8bf6279edd239ce6dfef660e1632aebe42e386ece6999d85d85bfd12b439678b",
-    "fetch_bytes": 5629403430533,
-    "write_bytes": 4100720632416,
-    "launches_per_step": 1112,
-    "tuning": {128: (0, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
+    "kernel_sha256": "6d26f1260a6830e09dfb9d70f3af1dfd3f472e7415a8d97b128c03c458fe1ed3",
+    "fetch_bytes": 5941073550762,
+    "write_bytes": 4383271163840,
+    "launches_per_step": 1230,
+    "tuning": {128: (1, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
 }
 C3_SOURCES = ("csrc/dev_common.h", "csrc/window_key.h", "csrc/fused_search.h", "csrc/kernels.h",
               "csrc/fused_p2_w64.hip", "csrc/fused_x_p2.hip", "csrc/delay_fft.hip",
