@@ -73,6 +73,11 @@ MEASURED_TRAFFIC_C3 = {
     "launches_per_step": 1230,
     "tuning": {128: (1, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
 }
+# The tune table the library's autotuner (FRINGE_AUTOTUNE) wrote on an
+# MI355X for the headline's four classes of scans; plans look their classes
+# up in it, and a device of another kind or size tunes them afresh.
+SHIPPED_TUNE = os.path.join(ROOT, "paper_2108_05602_amd", "tune", "gfx950_256cu.json")
+
 C3_SOURCES = ("csrc/dev_common.h", "csrc/window_key.h", "csrc/fused_search.h", "csrc/kernels.h",
               "csrc/fused_p2_w64.hip", "csrc/fused_x_p2.hip", "csrc/delay_fft.hip",
               "csrc/fused_dispatch.hip", "csrc/fringe_api.hip", "csrc/tune_table.cpp",
@@ -806,7 +811,8 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
         "hbm_gbs_algorithmic": cube / (ms / 1e3) / 1e9,
         "hbm_gbs_measured": (None if traffic is None else
                              traffic * launches_per_step / (ms / 1e3) / 1e9),
-        "autotune": {"enabled": autotune, "plan_s_total": plan_s, "table_loaded": bool(tune_load),
+        "autotune": {"enabled": autotune, "plan_s_total": plan_s,
+                     "table": os.path.relpath(tune_load, ROOT) if tune_load else "tuned in this run",
                      "entries": [entries[k] for k in sorted(entries)],
                      "tuned_vs_default": cmp},
     }
@@ -1029,7 +1035,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="headline plans with the default configurations (no tuning)")
     ap.add_argument("--tune-load", metavar="JSON", default=None,
-                    help="headline: read this tune table instead of tuning")
+                    help="headline: read this tune table instead of tuning (default: the "
+                         "table shipped for MI355X, %s)" % os.path.relpath(SHIPPED_TUNE, ROOT))
+    ap.add_argument("--retune", action="store_true",
+                    help="headline: tune every class afresh instead of reading a table")
     ap.add_argument("--tune-save", metavar="JSON", default=None,
                     help="headline: write the tune table here afterwards")
     ap.add_argument("--no-compare-default", action="store_true",
@@ -1074,7 +1083,8 @@ def main():
                         cpu_sample=None if args.no_cpu_baseline else sample,
                         autotune=not args.no_autotune,
                         compare_default=not args.no_compare_default,
-                        tune_load=args.tune_load, tune_save=args.tune_save)
+                        tune_load=None if args.retune else (args.tune_load or SHIPPED_TUNE),
+                        tune_save=args.tune_save)
         out["value"] = h["value"]
         out["ms_per_step"] = h["ms_per_step"]
         out["config"] = {"workload": C3_WORKLOAD if args.c3_scans == 200 else

@@ -308,3 +308,20 @@ def test_tune_table_file_round_trip(tmp_path):
     F.fringe_tune_clear()
     F.fringe_tune_save(str(out))
     assert json.loads(out.read_text())["entries"] == []
+
+
+def test_shipped_tune_table_loads():
+    """The tune table shipped for MI355X (written by the autotuner there)
+    loads and covers the batched workload's four band classes."""
+    import json
+    path = os.path.join(ROOT, "paper_2108_05602_amd", "tune", "gfx950_256cu.json")
+    data = json.load(open(path))
+    assert data["fringe_tune_table"] == 1
+    got = sorted(e["n_freq"] for e in data["entries"])
+    assert got == [128, 256, 512, 1024]
+    for e in data["entries"]:
+        assert e["arch"] == "gfx950" and e["cus"] == 256 and e["chunk"] in (128, 256, 512, 1024)
+        assert e["spectra"] in (0, 1) and e["pad_freq"] == 4 and e["pad_time"] == 2
+    F.fringe_tune_clear()
+    F.fringe_tune_load(path)
+    F.fringe_tune_clear()
