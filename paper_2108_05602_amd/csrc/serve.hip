@@ -236,11 +236,11 @@ int fringe_server_set_shifts(fringe_server_t s, int32_t sub, const int32_t* d_sh
   if (!s) return serve_fail(FRINGE_E_INVALID, "fringe_server_set_shifts: null server");
   if (sub < 0 || sub >= s->n_subs)
     return serve_fail(FRINGE_E_INVALID, "fringe_server_set_shifts: subarray out of range");
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->submitted)
-      return serve_fail(FRINGE_E_STATE, "fringe_server_set_shifts: chunks were already submitted");
-  }
+  // under the lock: a submission (which the worker needs before it touches
+  // a plan) cannot slip in while the plan is made again
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->submitted)
+    return serve_fail(FRINGE_E_STATE, "fringe_server_set_shifts: chunks were already submitted");
   return fringe_set_shifts(s->plans[size_t(sub)], 0, d_shifts);
 }
 
