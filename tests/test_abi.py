@@ -325,3 +325,12 @@ def test_shipped_tune_table_loads():
     F.fringe_tune_clear()
     F.fringe_tune_load(path)
     F.fringe_tune_clear()
+
+
+def test_chunk_argument_checks():
+    """fringe_plan_set_chunk / _get_chunk refuse a null plan or output on
+    the host (the rules that need a plan run on the GPU)."""
+    lib = F.load()
+    out = ctypes.c_int32()
+    assert lib.fringe_plan_set_chunk(None, 0, 256) == B.FRINGE_E_INVALID
+    assert lib.fringe_plan_get_chunk(None, 0, ctypes.byref(out)) == B.FRINGE_E_INVALID
