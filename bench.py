@@ -50,9 +50,9 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "e1a7e5ad49e14e98dfcf77a25134d6f579351a9d4875311e907bd90a097e922c",
-    "fetch_bytes": 8371253037,
-    "write_bytes": 2039289574,
+    "kernel_sha256": "8a5fcf11150564b92b7c0aab251d9679c7a6a1cee74cb809ae3dc5f6ccc070fb",
+    "fetch_bytes": 8398183593,
+    "write_bytes": 2040329760,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
@@ -60,19 +60,24 @@ MEASURED_TRAFFIC = {
 KERNEL_SOURCES = ("dev_common.h", "window_key.h", "fused_search.h", "kernels.h",
                   "fused_p2_w32.hip", "fused_dispatch.hip", "fringe_api.hip")
 
-# HBM bytes of the batched headline's search kernels (every launch of the
-# fused kernel, the delay transform and the kernel reading the spectra in
-# one step), from the same counters and copy scaling (FETCH_SIZE x 1.99992,
+# HBM bytes of the batched headline's search kernels in one step (every
+# launch of the fused kernel, in both modes, and of the delay transform),
+# from the same counters and copy scaling (FETCH_SIZE x 1.99992,
 # WRITE_SIZE x 1.0), with the launch configuration the autotuner chose then
 # (per band: spectra mode, time chunk).  Reported only while the sources
 # below hash alike and the run's tuning and launch count are the same.
 MEASURED_TRAFFIC_C3 = {
-    "kernel_sha256": "6d26f1260a6830e09dfb9d70f3af1dfd3f472e7415a8d97b128c03c458fe1ed3",
-    "fetch_bytes": 5941073550762,
-    "write_bytes": 4383271163840,
-    "launches_per_step": 1230,
+    "kernel_sha256": "97324f8d3ec241ee4b3cb5d32e084c5714865d29923f84a6355531f2dc4d4d79",
+    "fused_fetch_bytes": 4959179623410,
+    "fused_write_bytes": 321905776992,
+    "delay_fetch_bytes": 1013305729929,
+    "delay_write_bytes": 4058854364288,
+    "fused_launches_per_step": 620,
+    "delay_launches_per_step": 610,
     "tuning": {128: (1, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
 }
+
+
 # The tune table the library's autotuner (FRINGE_AUTOTUNE) wrote on an
 # MI355X for the headline's four classes of scans; plans look their classes
 # up in it, and a device of another kind or size tunes them afresh.
@@ -678,6 +683,10 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
     n_windows = n_cands = cube = 0
     fl = [0.0, 0.0, 0.0]
     part_bytes = e_bytes = 0
+    # per kernel: the fused search kernel (all its instantiations) and the
+    # delay transform of bands in spectra mode: algorithmic flops and bytes
+    k_fl = {"fused": 0.0, "delay": 0.0}
+    k_by = {"fused": 0.0, "delay": 0.0}
     sampled_f = set()
     waves_out = []
     log(f"C3: {len(specs)} scans, {sum(s.nbytes() for s in specs) / 1e12:.3f} TB in "
@@ -753,6 +762,19 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
             nw_s = sum(n for _, _, n in window_levels(sp.n_ap, p["window_aps"])) * sp.n_baselines
             part_bytes += nw_s * n_cls * 8
             e_bytes += sp.n_baselines * sp.n_ap * 4
+            # the band's search mode: the tuned one, else the default (spectra
+            # for bands of more than 512 channels)
+            spectra = (entries[sp.n_freq]["spectra"] if sp.n_freq in entries
+                       else int(sp.n_freq > 512))
+            x_bytes = sp.n_baselines * sp.n_ap * p["pad_freq"] * sp.n_freq * 8
+            if spectra:
+                k_fl["fused"] += r_ + k_
+                k_fl["delay"] += d_
+                k_by["fused"] += x_bytes + nw_s * n_cls * 8
+                k_by["delay"] += sp.nbytes() + x_bytes + sp.n_baselines * sp.n_ap * 4
+            else:
+                k_fl["fused"] += d_ + r_ + k_
+                k_by["fused"] += sp.nbytes() + nw_s * n_cls * 8 + sp.n_baselines * sp.n_ap * 4
         cube += wb
         if cpu_sample is not None:
             for j, i in enumerate(idx):
@@ -781,36 +803,67 @@ def c3_headline(steps, warmup, wave_gb, n_scans=200, cpu_sample=None, autotune=T
     avg_launch_s = (fused_ms + delay_ms) / max(1, fused_n + delay_n) / 1e3
     flops_per_launch = flops_step / launches_per_step
     achieved = flops_per_launch / avg_launch_s / 1e12
+    # the dominant kernel: the fused search kernel, every instantiation
+    # (fused-mode bands: delay + rate transforms + peaks; spectra-mode bands:
+    # rate transforms + peaks from the spectra)
+    fk_n = fused_n / steps
+    fk_s = fused_ms / max(1, fused_n) / 1e3
+    fk_achieved = k_fl["fused"] / fk_n / fk_s / 1e12
+    dk_n = delay_n / steps
+    dk_s = delay_ms / max(1, delay_n) / 1e3 if delay_n else None
     mt = MEASURED_TRAFFIC_C3
     tuned = {k: (v["spectra"], v["chunk"]) for k, v in entries.items()}
-    traffic = None
-    if (n_scans == 200 and autotune and tuned == mt["tuning"] and
-            launches_per_step == mt["launches_per_step"] and
-            kernel_hash(C3_SOURCES) == mt["kernel_sha256"]):
-        traffic = (mt["fetch_bytes"] + mt["write_bytes"]) / launches_per_step
+    valid = (n_scans == 200 and autotune and tuned == mt["tuning"] and
+             fk_n == mt["fused_launches_per_step"] and dk_n == mt["delay_launches_per_step"] and
+             kernel_hash(C3_SOURCES) == mt["kernel_sha256"])
+    traffic = traffic_all = traffic_delay = None
+    if valid:
+        traffic = (mt["fused_fetch_bytes"] + mt["fused_write_bytes"]) / fk_n
+        traffic_delay = (mt["delay_fetch_bytes"] + mt["delay_write_bytes"]) / dk_n
+        traffic_all = (mt["fused_fetch_bytes"] + mt["fused_write_bytes"] + mt["delay_fetch_bytes"] +
+                       mt["delay_write_bytes"]) / launches_per_step
     return {
         "value": n_windows / (ms / 1e3), "ms_per_step": ms, "windows": n_windows, "cube_bytes": cube,
         "candidates": n_cands, "waves": waves_out, "scans": len(specs),
         "roofline": {
             "bound": "alu",
-            "kernel": "search kernels: fused_search_kernel (delay FFT + rate FFT + |G|^2 peak, one "
-                      "launch per wave and fold class) and, in spectra mode, delay_fft_kernel + "
-                      "fused_search_kernel reading the spectra",
-            "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
+            "kernel": "fused_search_kernel, every instantiation: delay FFT + rate FFT + |G|^2 peak "
+                      "for bands in fused mode (one launch per wave and fold class), rate FFT + "
+                      "|G|^2 peak from the delay spectra for bands in spectra mode (one launch "
+                      "per baseline slab)",
+            "achieved": fk_achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": fk_achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "algorithmic_flops_per_launch": k_fl["fused"] / fk_n,
+            "algorithmic_bytes_per_launch": k_by["fused"] / fk_n,
+            "avg_launch_ms": fk_s * 1e3,
+            "launches_per_step": fk_n,
+        },
+        "roofline_delay_fft": None if not delay_n else {
+            "bound": "hbm",
+            "kernel": "delay_fft_kernel (bands in spectra mode: visibilities in, delay spectra out)",
+            "achieved": k_by["delay"] / dk_n / dk_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": k_by["delay"] / dk_n / dk_s / 1e9 / PEAK_HBM_GBS,
+            "traffic": traffic_delay,
+            "algorithmic_bytes_per_launch": k_by["delay"] / dk_n,
+            "algorithmic_flops_per_launch": k_fl["delay"] / dk_n,
+            "avg_launch_ms": dk_s * 1e3, "launches_per_step": dk_n,
+        },
+        "search_kernels": {
+            "kernels": "fused_search_kernel and delay_fft_kernel together",
+            "achieved_tflops": achieved, "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic_per_launch": traffic_all,
             "algorithmic_flops_per_launch": flops_per_launch,
             "algorithmic_bytes_per_launch": (cube + part_bytes + e_bytes) / launches_per_step,
-            "avg_launch_ms": avg_launch_s * 1e3,
-            "launches_per_step": launches_per_step,
+            "avg_launch_ms": avg_launch_s * 1e3, "launches_per_step": launches_per_step,
         },
         "kernel_ms_per_step": {"fused_ms": fused_ms / steps, "delay_fft_ms": delay_ms / steps,
                                "finalize_ms": fin_ms / steps, "compact_ms": comp_ms / steps},
         "tflops_algorithmic_step": flops_step / (ms / 1e3) / 1e12,
         "hbm_gbs_algorithmic": cube / (ms / 1e3) / 1e9,
-        "hbm_gbs_measured": (None if traffic is None else
-                             traffic * launches_per_step / (ms / 1e3) / 1e9),
+        "hbm_gbs_measured": (None if traffic_all is None else
+                             traffic_all * launches_per_step / (ms / 1e3) / 1e9),
         "autotune": {"enabled": autotune, "plan_s_total": plan_s,
                      "table": os.path.relpath(tune_load, ROOT) if tune_load else "tuned in this run",
                      "entries": [entries[k] for k in sorted(entries)],
@@ -1092,8 +1145,8 @@ def main():
                          "scans": h["scans"], "windows": h["windows"], "cube_bytes": h["cube_bytes"],
                          "waves": len(h["waves"]), "parallelism": "single GPU"}
         out["roofline"] = h["roofline"]
-        for k in ("kernel_ms_per_step", "tflops_algorithmic_step", "hbm_gbs_algorithmic",
-                  "hbm_gbs_measured",
+        for k in ("roofline_delay_fft", "search_kernels", "kernel_ms_per_step",
+                  "tflops_algorithmic_step", "hbm_gbs_algorithmic", "hbm_gbs_measured",
                   "candidates", "waves", "autotune"):
             out[k] = h[k]
         out["hbm_frac_algorithmic"] = h["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
