@@ -154,7 +154,11 @@ int fringe_plan(const fringe_scan_desc* scans, int32_t n_scans,
  * of subarray s (NULL: no chunk this call) and the windows reported are
  * those whose last AP lies in that chunk (D APs earlier with dedispersion
  * shifts up to D, fringe_set_shifts), windows spanning the previous chunk
- * included; start APs count from the first chunk.  A search on another
+ * included; start APs count from the first chunk.  The kernels read a chunk
+ * where the caller holds it (with dedispersion shifts, from a copy); the
+ * APs of it that the next call's windows reach back to are copied on the
+ * stream during the call, so once the search has completed the chunk's
+ * memory may be reused for the next one.  A search on another
  * stream than the plan's previous search first waits for that search.
  * Asynchronous: returns once the kernels are enqueued. */
 int fringe_search(fringe_plan_t plan, const fringe_cf32* const* d_vis, void* hip_stream);

@@ -79,7 +79,8 @@ __device__ __forceinline__ void load_first(FirstInputs<M, NAP, R, PF, NT>& in,
                                            int n_valid_ap, int F,
                                            const float2* __restrict__ gains,
                                            const int32_t* __restrict__ shifts,
-                                           const float2* __restrict__ xbl, int t_first, int T) {
+                                           const float2* __restrict__ xbl, int t_first, int T,
+                                           const float2* __restrict__ xbl2, int halo) {
   using In = FirstInputs<M, NAP, R, PF, NT>;
   constexpr int SPAN = M / R;
 #pragma unroll
@@ -96,6 +97,11 @@ __device__ __forceinline__ void load_first(FirstInputs<M, NAP, R, PF, NT>& in,
         if (shifts) {  // dedispersion: channel idx from AP t + d, 0 past the data
           const int row = t_first + a + min(max(shifts[idx], 0), T);
           if (row < T) x = xbl[static_cast<int64_t>(row) * F + idx];  // T: the rows held
+        } else if (xbl2) {  // a streamed chunk read in place: rows from halo on in xbl2
+          const int row = t_first + a;
+          const float2* src = row < halo ? xbl + static_cast<int64_t>(row) * F
+                                         : xbl2 + static_cast<int64_t>(row - halo) * F;
+          x = src[idx];
         } else {
           x = xin[static_cast<int64_t>(a) * F + idx];
         }
@@ -223,8 +229,9 @@ __global__ void __launch_bounds__(fft_threads(LOGM)) delay_fft_kernel(DelayArgs 
     const float2* xin = a.vis + static_cast<int64_t>(b) * a.vis_stride + static_cast<int64_t>(t0) * F;
     const float2* gains = a.gains ? a.gains + static_cast<int64_t>(b) * F : nullptr;
     const float2* xbl = a.vis + static_cast<int64_t>(b) * a.vis_stride;
+    const float2* xbl2 = a.vis2 ? a.vis2 + static_cast<int64_t>(b) * a.vis2_stride : nullptr;
     load_first<M, NAP, R0, PF, NT>(in, xin, lane, n_valid, F, gains, a.shifts, xbl, t0,
-                                   a.T_rows);
+                                   a.T_rows, xbl2, a.halo);
   };
   In nxt;
   if (static_cast<int64_t>(blockIdx.x) < n_groups) load_group(blockIdx.x, nxt);

@@ -71,6 +71,14 @@ struct CallScan {
   int64_t lvl_off[kMaxLevels + 1] = {};
   int lvl_j0[kMaxLevels] = {};
   int64_t win_off = 0;                // first window id
+  // where the kernels read the data: rows [0, split) at the call's data
+  // pointer with `stride` elements between baselines; with data2 set (a
+  // streamed chunk read in place), rows [split, T_rows) at data2 with
+  // stride2 between baselines
+  int64_t stride = 0;
+  const float2* data2 = nullptr;
+  int64_t stride2 = 0;
+  int split = 0;
 };
 
 // Windows of every length in the data [0, T) that end at or after t_emit.
@@ -421,7 +429,8 @@ int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel,
     if (n_class == 0) continue;
     int occ = 0;
     const hipError_t he =
-        launch_fused(nullptr, 0, 0, pad_t_kernel, sz->w_max, fc, false, nullptr, &occ);
+        launch_fused(nullptr, 0, 0, pad_t_kernel, sz->w_max, fc, false, nullptr, &occ,
+                     sz->streaming);
     if (he != hipSuccess) return hip_fail(he, "fused kernel occupancy");
     const int64_t target = int64_t(kWaveRounds) * n_cu * std::max(1, occ);
     int best = 64;
@@ -618,8 +627,15 @@ int decode_id(const fringe_plan_s* p, int64_t id, int* scan, int* b, int* li, in
   return FRINGE_OK;
 }
 
-// Stream subarray s's next chunk into a stage: [halo | chunk], the stage
-// starting on an aligned absolute AP.  Fills the call's numbering.
+// Subarray s's next chunk: the data the call's kernels read and the call's
+// numbering.  The halo (the APs before the chunk that the chunk's windows
+// reach back to, from an aligned absolute AP on) is in a stage buffer.
+// Without dedispersion shifts the kernels read the chunk where the caller
+// holds it, and the APs the next call's halo needs are copied from the
+// halo and the chunk into the other stage buffer now, on the call's
+// stream, so the caller may reuse the chunk's memory once the search has
+// finished.  With shifts (a lane's row depends on its channel) the chunk is
+// copied after the halo and the stage is read as one buffer.
 int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, CallScan* c,
                 const float2** data) {
   const ScanInfo& si = p->sz.scans[s];
@@ -640,6 +656,44 @@ int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, Ca
   const size_t row = size_t(si.stage_len) * si.F * sizeof(float2);  // one baseline of a stage
   const size_t ap_bytes = size_t(si.F) * sizeof(float2);
   hipError_t he;
+  if (!p->shifts[size_t(s)]) {
+    // stage[cur] holds APs [ss.origin, ss.origin + ss.len) ⊇ [origin, A)
+    const float2* held = ss.stage[ss.cur];
+    const int64_t o2 = std::max<int64_t>(0, floor_to(A + C - D - (p->sz.w_max - 1), p->sz.align));
+    if (o2 < A) {
+      he = hipMemcpy2DAsync(ss.stage[nxt], row, held + (o2 - ss.origin) * si.F, row,
+                            size_t(A - o2) * ap_bytes, si.d.n_baselines,
+                            hipMemcpyDeviceToDevice, st);
+      if (he != hipSuccess) return hip_fail(he, "stream halo copy");
+    }
+    const int64_t c0 = std::max(o2, A);
+    if (A + C > c0) {
+      he = hipMemcpy2DAsync(ss.stage[nxt] + (c0 - o2) * si.F, row, chunk + (c0 - A) * si.F,
+                            C * ap_bytes, size_t(A + C - c0) * ap_bytes, si.d.n_baselines,
+                            hipMemcpyDeviceToDevice, st);
+      if (he != hipSuccess) return hip_fail(he, "stream halo copy from the chunk");
+    }
+    if (halo > 0) {
+      *data = held + (origin - ss.origin) * si.F;
+      c->stride = int64_t(si.stage_len) * si.F;
+      c->data2 = chunk;
+      c->stride2 = int64_t(C) * si.F;
+      c->split = halo;
+    } else {
+      *data = chunk;
+      c->stride = int64_t(C) * si.F;
+    }
+    ss.cur = nxt;
+    ss.origin = o2;
+    ss.len = int(A + C - o2);
+    ss.consumed = A + C;
+    c->T_rows = halo + C;
+    c->T = std::max(0, halo + C - D);
+    c->t_emit = int(std::max<int64_t>(0, A - D - origin));
+    c->t_origin = origin;
+    enumerate(c, p->sz.lv);
+    return FRINGE_OK;
+  }
   if (halo > 0) {
     const float2* src = ss.stage[ss.cur] + (origin - ss.origin) * si.F;
     he = hipMemcpy2DAsync(ss.stage[nxt], row, src, row, halo * ap_bytes, si.d.n_baselines,
@@ -657,6 +711,7 @@ int stage_chunk(fringe_plan_s* p, int s, const float2* chunk, hipStream_t st, Ca
   c->T = std::max(0, halo + C - D);
   c->t_emit = int(std::max<int64_t>(0, A - D - origin));
   c->t_origin = origin;
+  c->stride = int64_t(si.stage_len) * si.F;
   enumerate(c, p->sz.lv);
   *data = ss.stage[nxt];
   return FRINGE_OK;
@@ -696,6 +751,11 @@ FusedArgs fused_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& si, co
   fu.gains = w.gains ? w.gains + int64_t(u.b0) * si.F : nullptr;
   fu.shifts = w.shifts;
   fu.vis_stride = vis_stride;
+  if (c.data2) {
+    fu.vis2 = c.data2 + int64_t(u.b0) * c.stride2;
+    fu.vis2_stride = c.stride2;
+    fu.halo = c.split;
+  }
   fu.part = w.part + u.part_off;
   fu.epart = w.epart ? w.epart + u.part_off : nullptr;
   fu.e = w.e + u.e_off;
@@ -726,6 +786,7 @@ FusedArgs fused_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& si, co
     // delay-transform kernel has applied gains and shifts
     fu.vis = w.X;
     fu.vis_stride = int64_t(c.T) * si.M;
+    fu.vis2 = nullptr;
     fu.T_rows = c.T;
     fu.F = si.M;
     fu.gains = nullptr;
@@ -1263,6 +1324,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       if (rc != FRINGE_OK) return rc;
     } else {
       c = z.scans[s].full;
+      c.stride = int64_t(z.scans[s].d.n_ap) * z.scans[s].F;
       data[s] = reinterpret_cast<const float2*>(d_vis[s]);
     }
     c.win_off = win_off;
@@ -1289,8 +1351,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
         const Unit& u = z.units[ui];
         const ScanInfo& si = z.scans[u.scan];
         const CallScan& c = p->call[u.scan];
-        const int64_t stride = int64_t(z.streaming ? si.stage_len : si.d.n_ap) * si.F;
-        fus[ui] = fused_entry(z, plan_bufs(p, u.scan), si, c, u, data[u.scan], stride);
+        fus[ui] = fused_entry(z, plan_bufs(p, u.scan), si, c, u, data[u.scan], c.stride);
         if (!p->call_present[u.scan]) fus[ui].n_pairs = 0;
         fus[ui].block_off = grp_blocks[g];
         grp_blocks[g] += fused_blocks(fus[ui]);
@@ -1334,7 +1395,8 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       if (grp_windows[g] == 0) continue;
       if (!gr.spectra) {
         FRINGE_TIMED(1, launch_fused(d_fus + gr.u0, gr.u1 - gr.u0, grp_blocks[g], kernel_pad_t,
-                                     z.w_max, gr.fc, p->grid != nullptr, st),
+                                     z.w_max, gr.fc, p->grid != nullptr, st, nullptr,
+                                     z.streaming),
                      "fused search launch");
         FRINGE_TIMED(2, launch_finalize(d_fin + gr.u0, gr.u1 - gr.u0, grp_windows[g], st),
                      "finalize launch");
@@ -1345,12 +1407,16 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
       const Unit& u = z.units[ui];
       const ScanInfo& si = z.scans[u.scan];
       const CallScan& c = p->call[u.scan];
-      const int64_t stride = int64_t(z.streaming ? si.stage_len : si.d.n_ap) * si.F;
       DelayArgs da{};
-      da.vis = data[u.scan] + int64_t(u.b0) * stride;
+      da.vis = data[u.scan] + int64_t(u.b0) * c.stride;
       da.gains = p->gains[u.scan] ? p->gains[u.scan] + int64_t(u.b0) * si.F : nullptr;
       da.shifts = p->shifts[u.scan];
-      da.vis_stride = stride;
+      da.vis_stride = c.stride;
+      if (c.data2) {
+        da.vis2 = c.data2 + int64_t(u.b0) * c.stride2;
+        da.vis2_stride = c.stride2;
+        da.halo = c.split;
+      }
       da.X = p->X;
       da.e = p->e + u.e_off;
       da.tw = p->tw[si.log_m];
@@ -1368,7 +1434,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
         // transform of the visibilities; same numbering and partials
         FRINGE_TIMED(1, launch_fused(d_fus + ui, 1, fused_blocks(hfus[ui]), kernel_pad_t,
                                      z.lv.W[l0 - 1], si.x_short ? kFoldSpectra : hfus[ui].hf,
-                                     p->grid != nullptr, st),
+                                     p->grid != nullptr, st, nullptr, z.streaming),
                      "fused search launch (short windows)");
       }
       if (l0 < z.lv.n) {

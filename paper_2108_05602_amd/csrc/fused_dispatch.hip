@@ -22,6 +22,25 @@ hipError_t launch_fused_d_w5(const FusedArgs* tab, int n, int64_t blocks, int hf
 hipError_t launch_fused_d_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
                              hipStream_t st, int* occ);
 
+hipError_t launch_fused_s_p1_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                                hipStream_t st, int* occ);
+hipError_t launch_fused_s_p1_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                                hipStream_t st, int* occ);
+hipError_t launch_fused_s_p1_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                                hipStream_t st, int* occ);
+hipError_t launch_fused_s_p2_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                                hipStream_t st, int* occ);
+hipError_t launch_fused_s_p2_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                                hipStream_t st, int* occ);
+hipError_t launch_fused_s_p2_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                                hipStream_t st, int* occ);
+hipError_t launch_fused_s_d_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                               hipStream_t st, int* occ);
+hipError_t launch_fused_s_d_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                               hipStream_t st, int* occ);
+hipError_t launch_fused_s_d_w6(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                               hipStream_t st, int* occ);
+
 hipError_t launch_fused_x_p1(const FusedArgs* tab, int n, int64_t blocks, int w_max, bool dump,
                              hipStream_t st, int* occ);
 hipError_t launch_fused_x_p2(const FusedArgs* tab, int n, int64_t blocks, int w_max, bool dump,
@@ -47,8 +66,24 @@ int64_t fused_blocks(const FusedArgs& a) {
 }
 
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
-                        int w_max, int hf_max, bool dump, hipStream_t st, int* occ) {
+                        int w_max, int hf_max, bool dump, hipStream_t st, int* occ,
+                        bool two_bufs) {
   if (hf_max > 16 || w_max > kFusedMaxWindow) return hipErrorInvalidValue;
+  if (two_bufs && hf_max != kFoldSpectra) {
+    if (dump || pad_t < 0 || pad_t > 2) return hipErrorInvalidValue;
+    const int lw = w_max <= 8 ? 3 : (w_max <= 32 ? 5 : 6);
+    if (pad_t == 0)
+      return lw == 3 ? launch_fused_s_d_w3(d_tab, n_tab, n_blocks, hf_max, st, occ)
+           : lw == 5 ? launch_fused_s_d_w5(d_tab, n_tab, n_blocks, hf_max, st, occ)
+                     : launch_fused_s_d_w6(d_tab, n_tab, n_blocks, hf_max, st, occ);
+    if (pad_t == 1)
+      return lw == 3 ? launch_fused_s_p1_w3(d_tab, n_tab, n_blocks, hf_max, st, occ)
+           : lw == 5 ? launch_fused_s_p1_w5(d_tab, n_tab, n_blocks, hf_max, st, occ)
+                     : launch_fused_s_p1_w6(d_tab, n_tab, n_blocks, hf_max, st, occ);
+    return lw == 3 ? launch_fused_s_p2_w3(d_tab, n_tab, n_blocks, hf_max, st, occ)
+         : lw == 5 ? launch_fused_s_p2_w5(d_tab, n_tab, n_blocks, hf_max, st, occ)
+                   : launch_fused_s_p2_w6(d_tab, n_tab, n_blocks, hf_max, st, occ);
+  }
   if (hf_max == kFoldSpectra) {
     if (pad_t == 0)
       return dump ? hipErrorInvalidValue : launch_fused_x_d(d_tab, n_tab, n_blocks, w_max, st, occ);

@@ -1,0 +1,14 @@
+// Instantiations of the fused search kernel for streaming plans (chunks
+// read where the caller holds them): delay-only search (rate bin 0), windows up to 8 APs.
+#include "fused_search.h"
+
+namespace fringe {
+
+hipError_t launch_fused_s_d_w3(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                               hipStream_t st, int* occ) {
+  if (hf_max <= 4) return launch_fused_t<0, 3, 4, false, false, true>(tab, n, blocks, st, occ);
+  if (hf_max <= 8) return launch_fused_t<0, 3, 8, false, false, true>(tab, n, blocks, st, occ);
+  return launch_fused_t<0, 3, 16, false, false, true>(tab, n, blocks, st, occ);
+}
+
+}  // namespace fringe

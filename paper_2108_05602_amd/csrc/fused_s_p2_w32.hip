@@ -1,0 +1,14 @@
+// Instantiations of the fused search kernel for streaming plans (chunks
+// read where the caller holds them): pad_time = 2, windows up to 32 APs.
+#include "fused_search.h"
+
+namespace fringe {
+
+hipError_t launch_fused_s_p2_w5(const FusedArgs* tab, int n, int64_t blocks, int hf_max,
+                                hipStream_t st, int* occ) {
+  if (hf_max <= 4) return launch_fused_t<2, 5, 4, false, false, true>(tab, n, blocks, st, occ);
+  if (hf_max <= 8) return launch_fused_t<2, 5, 8, false, false, true>(tab, n, blocks, st, occ);
+  return launch_fused_t<2, 5, 16, false, false, true>(tab, n, blocks, st, occ);
+}
+
+}  // namespace fringe

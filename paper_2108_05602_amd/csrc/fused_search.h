@@ -120,7 +120,11 @@ constexpr int site_level(int i, int k) {
 // applied), not visibilities: the wave of class c owns the contiguous bins
 // 64 c + m and reads its 512-byte segment of each AP, and the kernel only
 // does the rate transforms and peaks (AP energies come with the spectra).
-template <int PT, int LOGWMAX, int HFMAX, bool DUMP, bool SRCX>
+//
+// TWO (streaming plans): an entry's rows may lie in two buffers, the halo's
+// in vis and the chunk's in vis2, where the caller holds the chunk; the
+// buffer is chosen per AP.  Batch plans run the kernels without the choice.
+template <int PT, int LOGWMAX, int HFMAX, bool DUMP, bool SRCX, bool TWO = false>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DUMP ? 1 : 2)))
 fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   constexpr int WMAX = 1 << LOGWMAX;
@@ -220,24 +224,41 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
       for (int h = 0; h < HFMAX; ++h) s_off[h][lane] = shifted_off(h);
     }
   }
+  // A streamed chunk read where the caller holds it: the halo's rows [0,
+  // halo) in vis, the chunk's rows from vis2 (never with shifts, so the row
+  // is the AP's for every lane and the choice of buffer is wave-uniform).
+  const bool two = TWO && a.vis2 != nullptr;
+  const int halo = two ? __builtin_amdgcn_readfirstlane(a.halo) : T_rows;
   const auto vrs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float2*>(xb), static_cast<short>(0),
-      static_cast<int>(static_cast<uint32_t>(T_rows) * row_bytes), kBufferWord3);
+      static_cast<int>(static_cast<uint32_t>(halo) * row_bytes), kBufferWord3);
+  const auto vrs2 = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2*>(two ? a.vis2 + static_cast<int64_t>(b) * a.vis2_stride : xb),
+      static_cast<short>(0),
+      static_cast<int>(static_cast<uint32_t>(two ? T_rows - halo : 0) * row_bytes), kBufferWord3);
   auto load_ap = [&](int t, float2 (&dst)[HFMAX]) {
-    const uint32_t toff = static_cast<uint32_t>(min(t, T - 1)) * row_bytes;
+    int tr = min(t, T - 1);
+    auto vrs_t = vrs;
+    if constexpr (TWO) {
+      if (tr >= halo) {
+        vrs_t = vrs2;
+        tr -= halo;
+      }
+    }
+    const uint32_t toff = static_cast<uint32_t>(tr) * row_bytes;
     if constexpr (TAB_LDS) {
       if (has_s) {
         const LdsOff so = (LdsOff)(&s_off[0][lane]);
 #pragma unroll
-        for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, so[64 * h] + toff, 0);
+        for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs_t, so[64 * h] + toff, 0);
       } else {
 #pragma unroll
         for (int h = 0; h < HFMAX; ++h)
-          dst[h] = ld_buffer(vrs, lane8 + toff, static_cast<uint32_t>(64 * sizeof(float2) * h));
+          dst[h] = ld_buffer(vrs_t, lane8 + toff, static_cast<uint32_t>(64 * sizeof(float2) * h));
       }
     } else {
 #pragma unroll
-      for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs, lane_off[h] + toff, 0);
+      for (int h = 0; h < HFMAX; ++h) dst[h] = ld_buffer(vrs_t, lane_off[h] + toff, 0);
     }
   };
   const bool band_full = F == 64 * HFMAX;  // every lane in band for every fold
@@ -510,16 +531,17 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
 
 // Launches the instantiation, or with occ set, stores the work groups (one
 // wave each) it keeps resident per CU and launches nothing.
-template <int PT, int LOGWMAX, int HFMAX, bool DUMP, bool SRCX = false>
+template <int PT, int LOGWMAX, int HFMAX, bool DUMP, bool SRCX = false, bool TWO = false>
 hipError_t launch_fused_t(const FusedArgs* tab, int n_tab, int64_t blocks, hipStream_t st,
                           int* occ) {
   if (occ)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        occ, reinterpret_cast<const void*>(&fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP, SRCX>),
+        occ,
+        reinterpret_cast<const void*>(&fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP, SRCX, TWO>),
         64, 0);
   if (blocks == 0 || n_tab == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP, SRCX>),
+  hipLaunchKernelGGL((fused_search_kernel<PT, LOGWMAX, HFMAX, DUMP, SRCX, TWO>),
                      dim3(static_cast<unsigned>(blocks)), dim3(64), 0, st, tab, n_tab);
   return hipGetLastError();
 }

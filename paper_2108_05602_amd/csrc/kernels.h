@@ -44,6 +44,12 @@ struct DelayArgs {
   const float2* gains; // [nb][F] calibration gains of the slab, or nullptr
   const int32_t* shifts;  // [F] dedispersion shifts in APs, or nullptr
   int64_t vis_stride;  // elements between baselines of vis (>= T_rows * F)
+  // a streamed chunk read where the caller holds it: rows [halo, T_rows) of
+  // baseline b at vis2 + b * vis2_stride + (t - halo) * F, rows below halo
+  // in vis; nullptr when vis holds every row
+  const float2* vis2;
+  int64_t vis2_stride;
+  int halo;
   float2* X;           // [nb][T][M] delay spectra (out)
   float* e;            // [nb][T] per-AP energy sum |x|^2 (out)
   const float2* tw;    // [M] exp(-2 pi i k / M)
@@ -91,6 +97,11 @@ struct FusedArgs {
   int lvl_off[kMaxLevels + 1];
   int lvl_j0[kMaxLevels];
   int lvl_of_log[8];   // level index of the length 2^L, -1 if not searched
+  // a streamed chunk read in place: rows [halo, T_rows) in vis2 (as in
+  // DelayArgs), nullptr when vis holds every row
+  const float2* vis2;
+  int64_t vis2_stride;
+  int halo;
 };
 
 // One entry of a finalize launch; entry k owns the launch's windows
@@ -144,9 +155,12 @@ constexpr int kFoldSpectra = 0;
 // d_tab: n_tab entries in device memory; hf_max: the largest entry hf, or
 // kFoldSpectra; pad_t = 0 selects the delay-only search (rate bin 0 only).
 // With occ set, nothing is launched: *occ receives the chosen
-// instantiation's resident work groups (of one wave) per CU.
+// instantiation's resident work groups (of one wave) per CU.  two_bufs:
+// the instantiations whose entries may read their rows from two buffers
+// (vis2; streaming plans), not for spectra or grid dumps.
 hipError_t launch_fused(const FusedArgs* d_tab, int n_tab, int64_t n_blocks, int pad_t,
-                        int w_max, int hf_max, bool dump, hipStream_t st, int* occ = nullptr);
+                        int w_max, int hf_max, bool dump, hipStream_t st, int* occ = nullptr,
+                        bool two_bufs = false);
 hipError_t launch_finalize(const FinalizeArgs* d_tab, int n_tab, int64_t n_windows,
                            hipStream_t st);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t st);

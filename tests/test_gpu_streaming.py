@@ -175,3 +175,49 @@ def test_stream_alternating_streams():
         b = bmap[_key(r)]
         for f in ("k_rate", "k_delay", "amp", "snr", "energy"):
             assert r[f] == b[f], (_key(r), f)
+
+
+@pytest.mark.parametrize("ws,chunk", [([1, 2, 4, 8, 16, 32], 244), ([1, 2, 4, 8, 16, 32], 7),
+                                      ([1, 4, 64, 128], 61)],
+                         ids=["fused", "short-chunk", "two-pass"])
+def test_stream_reused_buffer(ws, chunk):
+    """The chunk is read where the caller holds it: one device buffer serves
+    every chunk, refilled on the search's stream right after each search is
+    enqueued (no host synchronisation in between), and the records still
+    equal the batch search's (the next call's halo is taken during the call)."""
+    import torch
+
+    import paper_2108_05602_amd as F
+    spec = synth.evn_scan(4033, 3, 1464, 8, 32, 1.024e-3, 16e6, 2, width_max=32, n_tones=1)
+    vis = spec.full()
+    desc = spec.desc()
+    thr = 4.5
+    print(f"case: reused chunk buffer, windows {ws}, chunk {chunk}", flush=True)
+    batch, _ = _batch(desc, vis, ws, thr)
+    bmap = {_key(r): r for r in batch}
+    dev = torch.from_numpy(vis).cuda()
+    n_used = (vis.shape[1] // chunk) * chunk
+    st = torch.cuda.current_stream()
+    buf = dev[:, :chunk].clone().contiguous()
+    got = []
+    with F.Plan([dict(desc, n_ap=chunk)], ws, pad_freq=4, pad_time=2, snr_threshold=thr,
+                flags=F.FRINGE_STREAMING) as p:
+        for t0 in range(0, n_used, chunk):
+            p.search([buf.data_ptr()], st.cuda_stream)
+            nxt = t0 + chunk
+            # stream-ordered after the search: the next chunk, or garbage
+            if nxt < n_used:
+                buf.copy_(dev[:, nxt:nxt + chunk])
+            else:
+                buf.fill_(float("nan"))
+            n = p.info()["n_windows"]
+            if n:
+                got.append(p.windows(np.arange(n)))
+    table = np.concatenate(got)
+    keys = [_key(r) for r in table]
+    assert len(keys) == len(set(keys))
+    assert set(keys) == {k for k in bmap if k[3] + k[2] <= n_used}
+    for r in table:
+        b = bmap[_key(r)]
+        for f in ("k_rate", "k_delay", "amp", "snr", "energy"):
+            assert r[f] == b[f], (chunk, _key(r), f, r[f], b[f])
