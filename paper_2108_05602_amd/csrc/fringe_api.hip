@@ -117,6 +117,11 @@ struct ScanInfo {
   // 4 GiB), rather than transforming the visibilities themselves.
   bool spectra;
   bool x_short;
+  // the fused kernel's instantiation class (fold_class, or kFoldSpectra
+  // for x_short) and its waves per (baseline, chunk) = partial peaks per
+  // window (every partial-peak consumer reads n_part of them)
+  int fc;
+  int n_part;
 };
 
 // A slab of baselines of one scan: one entry of a fused (or finalize)
@@ -168,7 +173,7 @@ struct Sizing {
 
 int data_len(const ScanInfo& s, bool streaming) { return streaming ? s.stage_len : s.d.n_ap; }
 
-int unit_class(const ScanInfo& si) { return si.x_short ? kFoldSpectra : fused_fold_class(si.F); }
+int unit_class(const ScanInfo& si) { return si.fc; }
 
 // Bytes per window and delay-bin class: the peak key, and with the
 // delay-only search the class's power sum.
@@ -177,7 +182,7 @@ size_t part_bytes(bool delay_only) { return sizeof(uint64_t) + (delay_only ? siz
 uint64_t per_baseline_scratch(const ScanInfo& s, bool streaming, bool delay_only) {
   const uint64_t t = uint64_t(data_len(s, streaming));
   const uint64_t x = s.spectra ? t * s.M * sizeof(float2) : 0;
-  return x + t * sizeof(float) + uint64_t(s.n_kb) * s.nwb_max * part_bytes(delay_only);
+  return x + t * sizeof(float) + uint64_t(s.n_part) * s.nwb_max * part_bytes(delay_only);
 }
 
 // A per-scan choice that overrides the defaults of validate_and_size and
@@ -319,6 +324,8 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
       si.spectra = (*force)[size_t(s)].spectra > 0 && allow_spectra && x_fits &&
                    !(p->flags & FRINGE_PLAIN);
     si.x_short = si.spectra && x_fits;
+    si.fc = si.x_short ? kFoldSpectra : fold_class(si.F, si.M, sz.delay_only);
+    si.n_part = fused_waves_per_pair(si.fc, si.M, sz.delay_only);
     if (sz.streaming)
       sz.stage_bytes += 2 * uint64_t(d.n_baselines) * si.stage_len * F * sizeof(float2);
     sz.scans.push_back(si);
@@ -380,7 +387,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
     const ScanInfo& si = sz.scans[u.scan];
     const uint64_t t = uint64_t(data_len(si, sz.streaming));
     const uint64_t e_u = uint64_t(u.nb) * t;
-    const uint64_t part_u = uint64_t(si.n_kb) * u.nb * si.nwb_max;
+    const uint64_t part_u = uint64_t(si.n_part) * u.nb * si.nwb_max;
     const bool open = !sz.groups.empty() && !sz.groups.back().spectra && !u.spectra &&
                       sz.groups.back().fc == u.fc;
     if (!open || (g_e + e_u) * sizeof(float) + (g_part + part_u) * part_bytes(sz.delay_only) > cap) {
@@ -439,7 +446,7 @@ int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel,
       int64_t waves = 0;
       for (const auto& si : sz->scans)
         if (unit_class(si) == fc)
-          waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_kb;
+          waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_part;
       if (waves >= target) {
         best = c;
         break;
@@ -770,7 +777,7 @@ FusedArgs fused_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& si, co
   fu.T_rows = std::max(c.T, c.T_rows);
   fu.F = si.F;
   fu.M = si.M;
-  fu.R = si.n_kb;
+  fu.R = si.n_part;
   fu.hf = (si.F + kBinsPerWave - 1) / kBinsPerWave;
   fu.chunk = si.chunk;
   fu.n_chunks = (c.T + si.chunk - 1) / si.chunk;
@@ -803,7 +810,7 @@ FinalizeArgs finalize_entry(const Sizing& z, const WorkBufs& w, const ScanInfo& 
   fa.e = w.e + u.e_off;
   fa.table = w.table + c.win_off + int64_t(u.b0) * c.nwb;
   fa.slab_windows = int64_t(u.nb) * c.nwb;
-  fa.n_kb = si.n_kb;
+  fa.n_kb = si.n_part;
   fa.nb = u.nb;
   fa.T = c.T;
   fa.nwb = int(c.nwb);
@@ -1381,7 +1388,8 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
   if (plain) {
     for (int64_t i = 0; i < p->call_windows; ++i) {
       const FusedArgs& h = reinterpret_cast<const FusedArgs*>(p->tables.data() + L.fused)[i];
-      FRINGE_TIMED(1, launch_fused(d_fus + i, 1, fused_blocks(h), kernel_pad_t, z.w_max, h.hf,
+      FRINGE_TIMED(1, launch_fused(d_fus + i, 1, fused_blocks(h), kernel_pad_t, z.w_max,
+                                   fold_class(h.F, h.M, z.delay_only),
                                    false, st), "plain fused launch");
       FRINGE_TIMED(2, launch_finalize(d_fin + i, 1, 1, st), "plain finalize launch");
     }
@@ -1433,7 +1441,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
         // (a baseline's spectra of 4 GiB or more) by the kernel's own delay
         // transform of the visibilities; same numbering and partials
         FRINGE_TIMED(1, launch_fused(d_fus + ui, 1, fused_blocks(hfus[ui]), kernel_pad_t,
-                                     z.lv.W[l0 - 1], si.x_short ? kFoldSpectra : hfus[ui].hf,
+                                     z.lv.W[l0 - 1], unit_class(si),
                                      p->grid != nullptr, st, nullptr, z.streaming),
                      "fused search launch (short windows)");
       }

@@ -55,6 +55,15 @@ int fused_fold_class(int F) {
   return hf <= 4 ? 4 : (hf <= 8 ? 8 : 16);
 }
 
+int fold_class(int F, int M, bool delay_only) {
+  const int fc = fused_fold_class(F);
+  return (delay_only && fc == 4 && (M / kBinsPerWave) % kDelayOnlyClasses != 0) ? 8 : fc;
+}
+
+int fused_waves_per_pair(int fc, int M, bool delay_only) {
+  return M / kBinsPerWave / ((delay_only && fc == 4) ? kDelayOnlyClasses : 1);
+}
+
 // APs per unrolled period of the kernel that serves w_max.
 int fused_period(int w_max) { return w_max <= 8 ? 4 : (w_max <= 32 ? 16 : 32); }
 

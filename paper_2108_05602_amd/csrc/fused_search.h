@@ -137,6 +137,12 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // delay-only search, which measured faster so (fewer live registers).
   constexpr int G = PT > 0 ? PD : 1;
   static_assert(P % PD == 0 && P % G == 0 && P >= 4, "period");
+  // Delay-bin classes per wave: the delay-only search on bands of at most
+  // 256 channels gives a wave NC classes, c = cls + j R (j < NC, R waves per
+  // (baseline, chunk)), so that an AP's loads, the per-window bookkeeping
+  // and one 64-lane reduction per window serve NC classes; lane m then holds
+  // the bins NC R m + c.  One class per wave otherwise.
+  constexpr int NC = (PT == 0 && HFMAX == 4 && !SRCX) ? kDelayOnlyClasses : 1;
 
   const int lane = threadIdx.x;
   // the entry (scan slab) that owns this block
@@ -270,40 +276,44 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // buffer holds exactly the baseline's F gains, so lanes past the band read
   // zeros.
   const bool has_g = a.gains != nullptr;
-  const float2 wsrc = ld_global(tw + ((cls * lane) & (M - 1)));
+  float2 wsrc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) wsrc[j] = ld_global(tw + (((cls + j * R) * lane) & (M - 1)));
   const auto grs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float2*>(has_g ? a.gains + static_cast<int64_t>(b) * F : a.gains),
       static_cast<short>(0), static_cast<int>(static_cast<uint32_t>(F) * sizeof(float2)),
       kBufferWord3);
-  auto coef = [&](int h) -> float2 {
-    const float2 w = ld_global(tw + (((cls * h) * 64) & (M - 1)));  // w_R^{c h}
-    const float2 ww = c_mul(make_float2(in_vgpr(w.x), in_vgpr(w.y)), wsrc);
+  auto coef = [&](int j, int h) -> float2 {
+    const int c = cls + j * R;
+    const float2 w = ld_global(tw + (((c * h) * 64) & (M - 1)));  // w_R^{c h}
+    const float2 ww = c_mul(make_float2(in_vgpr(w.x), in_vgpr(w.y)), wsrc[j]);
     if (!has_g) return ww;
     return c_mul(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0), ww);
   };
-  float2 gw[TAB_LDS ? 1 : HFMAX];
+  float2 gw[NC][TAB_LDS ? 1 : HFMAX];
   float gn[TAB_LDS ? 1 : HFMAX];
   if constexpr (TAB_LDS) {
 #pragma unroll
     for (int h = 0; h < HFMAX; ++h) {
-      const float2 c = coef(h);
+      const float2 c = coef(0, h);
       s_gw[h][lane] = f32x2_t{c.x, c.y};
     }
   } else {
 #pragma unroll
     for (int h = 0; h < HFMAX; ++h) {
-      gw[h] = coef(h);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) gw[j][h] = coef(j, h);
       gn[h] = has_g ? c_norm(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0)) : 1.f;
     }
   }
   // coefficient h of this lane (from LDS: |g|^2 = |coefficient|^2 up to
   // rounding, the twiddles having unit modulus)
-  auto coef_of = [&](int h) -> float2 {
+  auto coef_of = [&](int j, int h) -> float2 {
     if constexpr (TAB_LDS) {
       const f32x2_t v = ((LdsGw)(&s_gw[0][lane]))[64 * h];
       return make_float2(v.x, v.y);
     } else {
-      return gw[h];
+      return gw[j][h];
     }
   };
   auto sample = [&](float2 x, int h, bool t_in) {
@@ -341,12 +351,14 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // period), each window being the sum of its two halves; only the few
   // sums a later window still needs stay live in registers.
   float2 hist[HS];
-  float2 sum[LOGWMAX + 1][HS];
+  float2 sum[NC][LOGWMAX + 1][HS];
 #pragma unroll
   for (int k = 0; k < HS; ++k) {
     hist[k] = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int L = 0; L <= LOGWMAX; ++L) sum[L][k] = make_float2(0.f, 0.f);
+    for (int L = 0; L <= LOGWMAX; ++L)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) sum[j][L][k] = make_float2(0.f, 0.f);
   }
 
   const auto eb = gptr(a.e + static_cast<int64_t>(b) * T);
@@ -362,9 +374,14 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   const uint32_t own_n = static_cast<uint32_t>(own_hi - own_lo);
   // bin of lane m: R m + c (visibilities in, bins interleaved over the
   // classes by the cross-lane transform) or 64 c + m (spectra in)
-  const int kf_step = SRCX ? 1 : R;
-  const int my_bin = SRCX ? 64 * cls + lane : cls + R * lane;
+  const int kf_step = SRCX ? 1 : NC * R;
+  const int my_bin = SRCX ? 64 * cls + lane : cls + kf_step * lane;
   const uint32_t kf_top = 0xFFFFFFFFu - static_cast<uint32_t>(SRCX ? 64 * cls : cls);
+  // NC classes: 0xFFFFFFFF - k_f of this lane's bin of class j
+  uint32_t lo_j[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j)
+    lo_j[j] = kf_top - static_cast<uint32_t>(kf_step * lane) - static_cast<uint32_t>(j * R);
   int pidx[LOGWMAX + 1];
   bool on[LOGWMAX + 1];
   int64_t gidx[LOGWMAX + 1];
@@ -410,9 +427,9 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
         if (t >= T) z = make_float2(0.f, 0.f);
         prex[i % PDX] = load_x(t + PDX);
         if constexpr (PT > 0) hist[P + i] = z;
-        else sum[0][P + i] = z;
+        else sum[0][0][P + i] = z;
       } else if constexpr (i % G == 0) {
-        float2 z[G];
+        float2 z[G * NC];  // AP t + e, class cls + j R at z[e NC + j]
         static_for<0, G>([&](auto di) {
           constexpr int e = decltype(di)::value;
           constexpr int fs = (i + e) % PD;  // prefetch slot of AP t + e
@@ -422,15 +439,19 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
 #pragma unroll
             for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
           }
-          z[e] = c_mul(pre[fs][0], coef_of(0));
 #pragma unroll
-          for (int h = 1; h < HFMAX; ++h) z[e] = c_add(z[e], c_mul(pre[fs][h], coef_of(h)));
+          for (int j = 0; j < NC; ++j) {
+            float2& zz = z[e * NC + j];
+            zz = c_mul(pre[fs][0], coef_of(j, 0));
+#pragma unroll
+            for (int h = 1; h < HFMAX; ++h) zz = c_add(zz, c_mul(pre[fs][h], coef_of(j, h)));
+          }
           if (PT > 0 && cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
             float es = 0.f;
 #pragma unroll
             for (int h = 0; h < HFMAX; ++h) {
               float gh;
-              if constexpr (TAB_LDS) gh = has_g ? c_norm(coef_of(h)) : 1.f;
+              if constexpr (TAB_LDS) gh = has_g ? c_norm(coef_of(0, h)) : 1.f;
               else gh = gn[h];
               es = fmaf(gh, c_norm(pre[fs][h]), es);
             }
@@ -439,15 +460,23 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
           }
           load_ap(te + PD, pre[fs]);
           // lane l folded f = l; the transform wants f' = bitrev6(l) in lane l
-          z[e] = make_float2(
-              __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z[e].x))),
-              __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(z[e].y))));
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            float2& zz = z[e * NC + j];
+            zz = make_float2(
+                __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(zz.x))),
+                __int_as_float(__builtin_amdgcn_ds_bpermute(rev_addr, __float_as_int(zz.y))));
+          }
         });
         fused::xlane_dit(z, kc);
         static_for<0, G>([&](auto di) {
           constexpr int e = decltype(di)::value;
-          if constexpr (PT > 0) hist[P + i + e] = z[e];
-          else sum[0][P + i + e] = z[e];
+          if constexpr (PT > 0) {
+            hist[P + i + e] = z[e];
+          } else {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) sum[j][0][P + i + e] = z[e * NC + j];
+          }
         });
       }
 
@@ -461,20 +490,38 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
         // (s, 2^(L-1)), which ended 2^(L-1) APs ago, and (s + 2^(L-1),
         // 2^(L-1)), which ends here (every length is summed, searched or
         // not, as the next one's halves).  The windows ending here are
-        // reduced together (independent DPP chains interleaved).
+        // reduced together (independent DPP chains interleaved).  With NC
+        // classes a lane first takes the strongest of its NC bins (the lowest
+        // class on ties: the lower bin) and sums their powers.
         static_for<1, LOGWMAX + 1>([&](auto li) {
           constexpr int L = decltype(li)::value;
-          if constexpr (fused::window_site<P>(i, L))
-            sum[L][P + i] = c_add(sum[L - 1][P + i - (1 << (L - 1))], sum[L - 1][P + i]);
+          if constexpr (fused::window_site<P>(i, L)) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+              sum[j][L][P + i] =
+                  c_add(sum[j][L - 1][P + i - (1 << (L - 1))], sum[j][L - 1][P + i]);
+          }
         });
         constexpr int NS = fused::window_sites<P, LOGWMAX>(i);
-        uint32_t key[NS], mx[NS];
+        uint32_t key[NS], mx[NS], lo[NS];
         float ps[NS];
         static_for<0, NS>([&](auto ki) {
           constexpr int k = decltype(ki)::value;
           constexpr int L = fused::site_level<P, LOGWMAX>(i, k);
-          ps[k] = c_norm(sum[L][P + i]);
+          ps[k] = c_norm(sum[0][L][P + i]);
           key[k] = __float_as_uint(ps[k]);
+          if constexpr (NC > 1) {
+            lo[k] = lo_j[0];
+#pragma unroll
+            for (int j = 1; j < NC; ++j) {
+              const float pj = c_norm(sum[j][L][P + i]);
+              ps[k] += pj;
+              const uint32_t kj = __float_as_uint(pj);
+              const bool up = kj > key[k];
+              key[k] = up ? kj : key[k];
+              lo[k] = up ? lo_j[j] : lo[k];
+            }
+          }
           mx[k] = key[k];
         });
         wave_max_u32_n(mx);
@@ -487,7 +534,9 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
           constexpr int d = (i + 1 - W) / s;  // start - p0, in strides
           const int start = t + 1 - W;
           if (on[L] && t_ok && static_cast<uint32_t>(start - own_lo) < own_n) {
-            const uint64_t pk = peak_partial(key[k], mx[k], kf_top, kf_step);
+            uint64_t pk;
+            if constexpr (NC > 1) pk = peak_partial_at(key[k], mx[k], lo[k]);
+            else pk = peak_partial(key[k], mx[k], kf_top, kf_step);
             if (lane == 0) {
               pb[L][d] = pk;
               epb[L][d] = ps[k];
@@ -524,7 +573,9 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
     for (int k = 0; k < P; ++k) {
       hist[k] = hist[P + k];
 #pragma unroll
-      for (int L = 0; L <= LOGWMAX; ++L) sum[L][k] = sum[L][P + k];
+      for (int L = 0; L <= LOGWMAX; ++L)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) sum[j][L][k] = sum[j][L][P + k];
     }
   }
 }

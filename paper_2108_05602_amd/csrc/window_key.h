@@ -322,6 +322,15 @@ __device__ __forceinline__ uint64_t peak_partial(uint32_t key, uint32_t m, uint3
   return (static_cast<uint64_t>(m) << 32) | (kf_top - static_cast<uint32_t>(kf_step * lane));
 }
 
+// The same partial when each lane offers its own bin: lo is the lane's
+// 0xFFFFFFFF - k_f; the lowest lane holding the maximum gives its k_f.
+__device__ __forceinline__ uint64_t peak_partial_at(uint32_t key, uint32_t m, uint32_t lo) {
+  const uint64_t holders = __ballot(key == m);
+  const int lane = __builtin_ctzll(holders);
+  return (static_cast<uint64_t>(m) << 32) |
+         static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(lo), lane));
+}
+
 // Window key of a wave: the 64-lane max of the lanes' rate keys, and the
 // lowest lane holding it.  Returned as the bin-block partial
 //   (key << 32) | (0xFFFFFFFF - k_f)   with k_f = kf_base + kf_step * lane,
