@@ -255,9 +255,12 @@ def delay_only_leg(dev, spec, params, steps=5):
     for w, s_, n in window_levels(spec.n_ap, params["window_aps"]):
         flops += spec.n_baselines * n * m_f * ((2.0 if w > 1 else 0.0) + 5.0)
     k_ms = kern / steps
+    tf = flops / (k_ms * 1e-3) / 1e12
     return {"windows_per_s": n_win / dt, "ms_per_step": dt * 1e3, "kernel_ms": k_ms,
-            "kernel_tflops_algorithmic": flops / (k_ms * 1e-3) / 1e12,
+            "kernel_tflops_algorithmic": tf,
             "kernel_hbm_gbs_algorithmic": spec.nbytes() / (k_ms * 1e-3) / 1e9,
+            "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS},
             "candidates": int(len(c))}
 
 

@@ -424,7 +424,10 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
 // (a multiple of the kernel period, at least 64 APs) that still gives every
 // wave slot of the device kWaveRounds waves, the slots being the CUs times
 // the waves that instantiation keeps resident per CU; when even 64 does not,
-// 64 (the latency-bound case of small grids).
+// 64 (the latency-bound case of small grids).  Waves are counted in
+// delay-bin classes: a delay-only wave of kDelayOnlyClasses classes counts
+// as that many (with one wave per class the shorter chunk it would get
+// measured 6-20 % slower).
 constexpr int kWaveRounds = 16;
 int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel,
                 const std::vector<ScanForce>* force = nullptr) {
@@ -446,7 +449,7 @@ int tune_chunks(Sizing* sz, int n_cu, int pad_t_kernel,
       int64_t waves = 0;
       for (const auto& si : sz->scans)
         if (unit_class(si) == fc)
-          waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_part;
+          waves += int64_t(si.d.n_baselines) * ((si.d.n_ap + c - 1) / c) * si.n_kb;
       if (waves >= target) {
         best = c;
         break;
