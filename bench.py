@@ -50,9 +50,9 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "8a5fcf11150564b92b7c0aab251d9679c7a6a1cee74cb809ae3dc5f6ccc070fb",
-    "fetch_bytes": 8398183593,
-    "write_bytes": 2040329760,
+    "kernel_sha256": "d625c8f9da0d8cd172cfbb8987a9f55cf6242c617c68001ca606c11b7bbac8f2",
+    "fetch_bytes": 8393154627,
+    "write_bytes": 2037117414,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
@@ -67,11 +67,11 @@ KERNEL_SOURCES = ("dev_common.h", "window_key.h", "fused_search.h", "kernels.h",
 # (per band: spectra mode, time chunk).  Reported only while the sources
 # below hash alike and the run's tuning and launch count are the same.
 MEASURED_TRAFFIC_C3 = {
-    "kernel_sha256": "97324f8d3ec241ee4b3cb5d32e084c5714865d29923f84a6355531f2dc4d4d79",
-    "fused_fetch_bytes": 4959179623410,
-    "fused_write_bytes": 321905776992,
-    "delay_fetch_bytes": 1013305729929,
-    "delay_write_bytes": 4058854364288,
+    "kernel_sha256": "6df9117234a642f1f084d9400248e25355477d47870f9c914eb9a1526a667e7b",
+    "fused_fetch_bytes": 4959492051455,
+    "fused_write_bytes": 321780602240,
+    "delay_fetch_bytes": 1013314634514,
+    "delay_write_bytes": 4058854429536,
     "fused_launches_per_step": 620,
     "delay_launches_per_step": 610,
     "tuning": {128: (1, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
