@@ -215,8 +215,11 @@ def test_graph_flag_rules():
 
 def test_delay_only_flag_rules():
     """FRINGE_DELAY_ONLY: same windows, windows of at most 64 APs, no grid
-    dump; its work buffers hold a power sum per window and class besides
-    the peak key."""
+    dump.  Its work buffers hold per window and wave a peak key (8 B) and a
+    power sum (4 B): on bands of up to 256 channels a wave takes four of the
+    M_f / 64 delay-bin classes (4 waves for the 16 classes at 256 channels,
+    against the full search's 16 keys of 8 B), wider bands one class per
+    wave (32 keys and sums at 512 channels against 32 keys)."""
     c1 = dict(n_baselines=1, n_ap=64, n_if=2, n_chan=16, ap_seconds=1.0, chan_width_hz=1 / 32)
     assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_DELAY_ONLY)["n_windows"] == 31
     for flags in (B.FRINGE_DELAY_ONLY | B.FRINGE_STREAMING, B.FRINGE_DELAY_ONLY | B.FRINGE_PLAIN,
@@ -228,7 +231,11 @@ def test_delay_only_flag_rules():
     full = F.fringe_plan_check([C2], C2_W)
     do = F.fringe_plan_check([C2], C2_W, flags=B.FRINGE_DELAY_ONLY)
     assert do["n_windows"] == full["n_windows"]
-    assert do["scratch_bytes"] > full["scratch_bytes"]
+    assert full["scratch_bytes"] - do["scratch_bytes"] == full["n_windows"] * (16 * 8 - 4 * 12)
+    wide = dict(C2, n_if=16, n_ap=4096)
+    full = F.fringe_plan_check([wide], C2_W)
+    do = F.fringe_plan_check([wide], C2_W, flags=B.FRINGE_DELAY_ONLY)
+    assert do["scratch_bytes"] - full["scratch_bytes"] == full["n_windows"] * 32 * 4
 
 
 def test_streaming_sizing():
