@@ -140,3 +140,27 @@ def test_streamed_and_plain_equal_batch_delay_only():
     _, b300, _ = run_gpu([d300], [sub], ws, 4, 2, 4.5, flags=F.FRINGE_DELAY_ONLY)
     for f in ("baseline", "window_ap", "t_start") + fields:
         assert np.array_equal(plain[f], b300[f]), f
+
+
+@pytest.mark.parametrize("n_if,n_chan,pf", [(4, 16, 4), (8, 16, 4), (8, 32, 4), (8, 32, 2), (16, 32, 4)],
+                         ids=["F64", "F128", "F256", "F256-pad2", "F512"])
+def test_exact_ties_delay_only(n_if, n_chan, pf):
+    """Every delay bin ties exactly: each AP holds one nonzero sample, in
+    channel 0, so its delay spectrum is that sample in every bin (the
+    transform only adds zeros to it), and so is every window's sum.  The
+    peak is then the lowest delay bin, 0, as in the reference, whichever
+    wave, class and lane hold the other bins (four classes per wave for the
+    bands of up to 256 channels, one for 512)."""
+    nb, t, ws = 2, 300, [1, 2, 4, 8, 16, 32]
+    print(f"case: delay-only exact ties, F = {n_if * n_chan}, pad {pf}", flush=True)
+    rng = np.random.default_rng([97, n_if, n_chan, pf])
+    v = np.zeros((nb, t, n_if, n_chan), np.complex64)
+    v[:, :, 0, 0] = (rng.standard_normal((nb, t)) + 1j * rng.standard_normal((nb, t))).astype(np.complex64)
+    d = dict(n_baselines=nb, n_ap=t, n_if=n_if, n_chan=n_chan, ap_seconds=1e-3, chan_width_hz=1e6)
+    plan, table, _ = run_gpu([d], [v], ws, pf, 2, 3.0, flags=_flags())
+    ref = oracle_table([v], [d], ws, pf, 2, 3.0, delay_only=True)
+    assert np.all(ref["k_delay"] == 0)
+    assert np.all(table["k_delay"] == 0) and np.all(table["delay_s"] == 0.0)
+    fv = _flat(v)
+    compare_windows(table, ref, lambda s, b: fv[b], pf, 2, f"ties F={n_if * n_chan} pad {pf}")
+    plan.close()
