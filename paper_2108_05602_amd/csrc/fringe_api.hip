@@ -425,7 +425,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
 // wave slot of the device kWaveRounds waves, the slots being the CUs times
 // the waves that instantiation keeps resident per CU; when even 64 does not,
 // 64 (the latency-bound case of small grids).  Waves are counted in
-// delay-bin classes: a delay-only wave of kDelayOnlyClasses classes counts
+// delay-bin classes: a delay-only wave of delay_only_classes classes counts
 // as that many (with one wave per class the shorter chunk it would get
 // measured 6-20 % slower).
 constexpr int kWaveRounds = 16;

@@ -56,12 +56,13 @@ int fused_fold_class(int F) {
 }
 
 int fold_class(int F, int M, bool delay_only) {
-  const int fc = fused_fold_class(F);
-  return (delay_only && fc == 4 && (M / kBinsPerWave) % kDelayOnlyClasses != 0) ? 8 : fc;
+  int fc = fused_fold_class(F);
+  while (delay_only && fc < 16 && (M / kBinsPerWave) % delay_only_classes(fc) != 0) fc *= 2;
+  return fc;
 }
 
 int fused_waves_per_pair(int fc, int M, bool delay_only) {
-  return M / kBinsPerWave / ((delay_only && fc == 4) ? kDelayOnlyClasses : 1);
+  return M / kBinsPerWave / (delay_only ? delay_only_classes(fc) : 1);
 }
 
 // APs per unrolled period of the kernel that serves w_max.

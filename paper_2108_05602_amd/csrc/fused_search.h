@@ -138,11 +138,12 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   constexpr int G = PT > 0 ? PD : 1;
   static_assert(P % PD == 0 && P % G == 0 && P >= 4, "period");
   // Delay-bin classes per wave: the delay-only search on bands of at most
-  // 256 channels gives a wave NC classes, c = cls + j R (j < NC, R waves per
-  // (baseline, chunk)), so that an AP's loads, the per-window bookkeeping
-  // and one 64-lane reduction per window serve NC classes; lane m then holds
-  // the bins NC R m + c.  One class per wave otherwise.
-  constexpr int NC = (PT == 0 && HFMAX == 4 && !SRCX) ? kDelayOnlyClasses : 1;
+  // 512 channels gives a wave NC classes (4 up to 256 channels, 2 up to
+  // 512), c = cls + j R (j < NC, R waves per (baseline, chunk)), so that an
+  // AP's loads, the per-window bookkeeping and one 64-lane reduction per
+  // window serve NC classes; lane m then holds the bins NC R m + c.  One
+  // class per wave otherwise.
+  constexpr int NC = (PT == 0 && !SRCX) ? delay_only_classes(HFMAX) : 1;
 
   const int lane = threadIdx.x;
   // the entry (scan slab) that owns this block
@@ -188,7 +189,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // in registers they would push the kernel with a 64-AP history to one
   // wave per SIMD.  Narrow bands keep both in registers.
   constexpr bool TAB_LDS = HFMAX > 4;
-  __shared__ f32x2_t s_gw[TAB_LDS ? HFMAX : 1][64];
+  __shared__ f32x2_t s_gw[TAB_LDS ? NC * HFMAX : 1][64];  // [class j][fold h] at j HFMAX + h
   __shared__ uint32_t s_off[TAB_LDS ? HFMAX : 1][64];
   typedef const volatile __attribute__((address_space(3))) f32x2_t* LdsGw;
   typedef const volatile __attribute__((address_space(3))) uint32_t* LdsOff;
@@ -295,8 +296,11 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   if constexpr (TAB_LDS) {
 #pragma unroll
     for (int h = 0; h < HFMAX; ++h) {
-      const float2 c = coef(0, h);
-      s_gw[h][lane] = f32x2_t{c.x, c.y};
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float2 c = coef(j, h);
+        s_gw[j * HFMAX + h][lane] = f32x2_t{c.x, c.y};
+      }
     }
   } else {
 #pragma unroll
@@ -310,7 +314,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // rounding, the twiddles having unit modulus)
   auto coef_of = [&](int j, int h) -> float2 {
     if constexpr (TAB_LDS) {
-      const f32x2_t v = ((LdsGw)(&s_gw[0][lane]))[64 * h];
+      const f32x2_t v = ((LdsGw)(&s_gw[j * HFMAX][lane]))[64 * h];
       return make_float2(v.x, v.y);
     } else {
       return gw[j][h];

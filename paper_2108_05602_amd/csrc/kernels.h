@@ -13,9 +13,10 @@ constexpr int kMaxWindowAp = 128;
 constexpr int kMinMf = 64;
 constexpr int kMaxMf = 4096;
 constexpr int kBinsPerWave = 64;
-// Delay-bin classes per wave of the delay-only search on bands of at most
-// 4 x 64 channels (one class per wave otherwise).
-constexpr int kDelayOnlyClasses = 4;
+// Delay-bin classes per wave of the delay-only search, by the fold class of
+// the instantiation (64-channel folds per lane): 4 for bands of up to 4 x 64
+// channels, 2 for up to 8 x 64, 1 for wider ones and the full search.
+constexpr int delay_only_classes(int fc) { return fc == 4 ? 4 : (fc == 8 ? 2 : 1); }
 
 // Window lengths of a plan, ascending; stride = max(1, W / 2).
 struct LevelTable {
@@ -153,11 +154,11 @@ int64_t fused_blocks(const FusedArgs& a);
 // Fold class (4, 8 or 16 folds of 64 channels per lane) serving F channels.
 int fused_fold_class(int F);
 // The fold class of the instantiation that serves a band of F channels and
-// M delay bins: fused_fold_class(F), except that a delay-only band of class
-// 4 needs M / 64 divisible by kDelayOnlyClasses (else class 8), and the
+// M delay bins: fused_fold_class(F), except that a delay-only band goes up
+// a class until M / 64 is a multiple of its delay_only_classes, and the
 // fused kernel's waves per (baseline, chunk), which is the number of
-// partial peaks per window: M / 64, over kDelayOnlyClasses for delay-only
-// bands of class 4.
+// partial peaks per window: M / 64, over delay_only_classes(fc) for
+// delay-only bands.
 int fold_class(int F, int M, bool delay_only);
 int fused_waves_per_pair(int fc, int M, bool delay_only);
 // The fold class value that selects the kernel reading delay spectra

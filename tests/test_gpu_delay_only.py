@@ -62,6 +62,8 @@ SHAPES = [
     (1, 260, 1, 64, [64], 4),
     (2, 1100, 4, 16, [1, 2, 4, 8, 16, 32, 64], 4),
     (1, 90, 32, 32, [2, 4, 8], 4),
+    (2, 333, 16, 32, [1, 2, 4, 8, 16, 32], 4),
+    (1, 275, 8, 64, [1, 4, 16, 64], 2),
 ]
 
 
