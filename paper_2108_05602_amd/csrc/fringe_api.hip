@@ -117,7 +117,7 @@ struct ScanInfo {
   // 4 GiB), rather than transforming the visibilities themselves.
   bool spectra;
   bool x_short;
-  // the fused kernel's instantiation class (fold_class, or kFoldSpectra
+  // the fused kernel's instantiation class (fused_fold_class(F), or kFoldSpectra
   // for x_short) and its waves per (baseline, chunk) = partial peaks per
   // window (every partial-peak consumer reads n_part of them)
   int fc;
@@ -324,7 +324,7 @@ int validate_and_size(const fringe_scan_desc* scans, int32_t n_scans, const frin
       si.spectra = (*force)[size_t(s)].spectra > 0 && allow_spectra && x_fits &&
                    !(p->flags & FRINGE_PLAIN);
     si.x_short = si.spectra && x_fits;
-    si.fc = si.x_short ? kFoldSpectra : fold_class(si.F, si.M, sz.delay_only);
+    si.fc = si.x_short ? kFoldSpectra : fused_fold_class(si.F);
     si.n_part = fused_waves_per_pair(si.fc, si.M, sz.delay_only);
     if (sz.streaming)
       sz.stage_bytes += 2 * uint64_t(d.n_baselines) * si.stage_len * F * sizeof(float2);
@@ -1392,7 +1392,7 @@ int fringe_search(fringe_plan_t p, const fringe_cf32* const* d_vis, void* hip_st
     for (int64_t i = 0; i < p->call_windows; ++i) {
       const FusedArgs& h = reinterpret_cast<const FusedArgs*>(p->tables.data() + L.fused)[i];
       FRINGE_TIMED(1, launch_fused(d_fus + i, 1, fused_blocks(h), kernel_pad_t, z.w_max,
-                                   fold_class(h.F, h.M, z.delay_only),
+                                   fused_fold_class(h.F),
                                    false, st), "plain fused launch");
       FRINGE_TIMED(2, launch_finalize(d_fin + i, 1, 1, st), "plain finalize launch");
     }

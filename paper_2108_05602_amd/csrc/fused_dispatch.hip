@@ -55,14 +55,9 @@ int fused_fold_class(int F) {
   return hf <= 4 ? 4 : (hf <= 8 ? 8 : 16);
 }
 
-int fold_class(int F, int M, bool delay_only) {
-  int fc = fused_fold_class(F);
-  while (delay_only && fc < 16 && (M / kBinsPerWave) % delay_only_classes(fc) != 0) fc *= 2;
-  return fc;
-}
-
 int fused_waves_per_pair(int fc, int M, bool delay_only) {
-  return M / kBinsPerWave / (delay_only ? delay_only_classes(fc) : 1);
+  const int nc = delay_only ? delay_only_classes(fc) : 1;
+  return (M / kBinsPerWave + nc - 1) / nc;
 }
 
 // APs per unrolled period of the kernel that serves w_max.

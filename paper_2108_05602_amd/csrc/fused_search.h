@@ -137,12 +137,15 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // delay-only search, which measured faster so (fewer live registers).
   constexpr int G = PT > 0 ? PD : 1;
   static_assert(P % PD == 0 && P % G == 0 && P >= 4, "period");
-  // Delay-bin classes per wave: the delay-only search on bands of at most
-  // 512 channels gives a wave NC classes (4 up to 256 channels, 2 up to
-  // 512), c = cls + j R (j < NC, R waves per (baseline, chunk)), so that an
-  // AP's loads, the per-window bookkeeping and one 64-lane reduction per
-  // window serve NC classes; lane m then holds the bins NC R m + c.  One
-  // class per wave otherwise.
+  // Delay-bin classes per wave: the delay-only search gives a wave NC
+  // classes (4 on bands of up to 256 channels, else 2), c = cls + j R (j <
+  // NC, R = ceil(M / 64 / NC) waves per (baseline, chunk)), so that an AP's
+  // loads, the per-window bookkeeping and one 64-lane reduction per window
+  // serve NC classes; lane m then holds the bins (M / 64) m + c.  Classes
+  // c >= M / 64 (when NC does not divide M / 64) are ghosts: their fold
+  // coefficients are zero, so their power is exactly 0, which never beats a
+  // lower class (strictly greater replaces) and adds nothing to the sums.
+  // One class per wave in the full search.
   constexpr int NC = (PT == 0 && !SRCX) ? delay_only_classes(HFMAX) : 1;
 
   const int lane = threadIdx.x;
@@ -286,6 +289,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
       kBufferWord3);
   auto coef = [&](int j, int h) -> float2 {
     const int c = cls + j * R;
+    if (NC > 1 && c >= (M >> 6)) return make_float2(0.f, 0.f);  // a ghost class
     const float2 w = ld_global(tw + (((c * h) * 64) & (M - 1)));  // w_R^{c h}
     const float2 ww = c_mul(make_float2(in_vgpr(w.x), in_vgpr(w.y)), wsrc[j]);
     if (!has_g) return ww;
@@ -378,7 +382,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   const uint32_t own_n = static_cast<uint32_t>(own_hi - own_lo);
   // bin of lane m: R m + c (visibilities in, bins interleaved over the
   // classes by the cross-lane transform) or 64 c + m (spectra in)
-  const int kf_step = SRCX ? 1 : NC * R;
+  const int kf_step = SRCX ? 1 : (NC > 1 ? (M >> 6) : R);
   const int my_bin = SRCX ? 64 * cls + lane : cls + kf_step * lane;
   const uint32_t kf_top = 0xFFFFFFFFu - static_cast<uint32_t>(SRCX ? 64 * cls : cls);
   // NC classes: 0xFFFFFFFF - k_f of this lane's bin of class j

@@ -15,8 +15,8 @@ constexpr int kMaxMf = 4096;
 constexpr int kBinsPerWave = 64;
 // Delay-bin classes per wave of the delay-only search, by the fold class of
 // the instantiation (64-channel folds per lane): 4 for bands of up to 4 x 64
-// channels, 2 for up to 8 x 64, 1 for wider ones and the full search.
-constexpr int delay_only_classes(int fc) { return fc == 4 ? 4 : (fc == 8 ? 2 : 1); }
+// channels, 2 for wider ones (1 in the full search and from spectra).
+constexpr int delay_only_classes(int fc) { return fc == 4 ? 4 : ((fc == 8 || fc == 16) ? 2 : 1); }
 
 // Window lengths of a plan, ascending; stride = max(1, W / 2).
 struct LevelTable {
@@ -153,13 +153,9 @@ int fused_period(int w_max);
 int64_t fused_blocks(const FusedArgs& a);
 // Fold class (4, 8 or 16 folds of 64 channels per lane) serving F channels.
 int fused_fold_class(int F);
-// The fold class of the instantiation that serves a band of F channels and
-// M delay bins: fused_fold_class(F), except that a delay-only band goes up
-// a class until M / 64 is a multiple of its delay_only_classes, and the
-// fused kernel's waves per (baseline, chunk), which is the number of
-// partial peaks per window: M / 64, over delay_only_classes(fc) for
-// delay-only bands.
-int fold_class(int F, int M, bool delay_only);
+// The fused kernel's waves per (baseline, chunk) for a band of fold class
+// fc and M delay bins, which is the number of partial peaks per window:
+// M / 64, over delay_only_classes(fc) rounded up for delay-only bands.
 int fused_waves_per_pair(int fc, int M, bool delay_only);
 // The fold class value that selects the kernel reading delay spectra
 // (entries' vis = X[b][t][M], F = M, no gains or shifts).

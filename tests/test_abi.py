@@ -218,8 +218,8 @@ def test_delay_only_flag_rules():
     dump.  Its work buffers hold per window and wave a peak key (8 B) and a
     power sum (4 B): on bands of up to 256 channels a wave takes four of the
     M_f / 64 delay-bin classes (4 waves for the 16 classes at 256 channels,
-    against the full search's 16 keys of 8 B), wider bands one class per
-    wave (32 keys and sums at 512 channels against 32 keys)."""
+    against the full search's 16 keys of 8 B), on wider bands two (16 waves
+    for the 32 classes at 512 channels, against 32 keys)."""
     c1 = dict(n_baselines=1, n_ap=64, n_if=2, n_chan=16, ap_seconds=1.0, chan_width_hz=1 / 32)
     assert F.fringe_plan_check([c1], [4], flags=B.FRINGE_DELAY_ONLY)["n_windows"] == 31
     for flags in (B.FRINGE_DELAY_ONLY | B.FRINGE_STREAMING, B.FRINGE_DELAY_ONLY | B.FRINGE_PLAIN,
@@ -235,7 +235,7 @@ def test_delay_only_flag_rules():
     wide = dict(C2, n_if=16, n_ap=4096)
     full = F.fringe_plan_check([wide], C2_W)
     do = F.fringe_plan_check([wide], C2_W, flags=B.FRINGE_DELAY_ONLY)
-    assert do["scratch_bytes"] - full["scratch_bytes"] == full["n_windows"] * 32 * 4
+    assert full["scratch_bytes"] - do["scratch_bytes"] == full["n_windows"] * (32 * 8 - 16 * 12)
 
 
 def test_streaming_sizing():

@@ -144,15 +144,18 @@ def test_streamed_and_plain_equal_batch_delay_only():
         assert np.array_equal(plain[f], b300[f]), f
 
 
-@pytest.mark.parametrize("n_if,n_chan,pf", [(4, 16, 4), (8, 16, 4), (8, 32, 4), (8, 32, 2), (16, 32, 4)],
-                         ids=["F64", "F128", "F256", "F256-pad2", "F512"])
+@pytest.mark.parametrize("n_if,n_chan,pf", [(4, 4, 4), (2, 16, 4), (4, 16, 4), (8, 16, 4), (8, 32, 4),
+                                            (8, 32, 2), (16, 32, 4), (16, 64, 4)],
+                         ids=["F16", "F32", "F64", "F128", "F256", "F256-pad2", "F512", "F1024"])
 def test_exact_ties_delay_only(n_if, n_chan, pf):
     """Every delay bin ties exactly: each AP holds one nonzero sample, in
     channel 0, so its delay spectrum is that sample in every bin (the
     transform only adds zeros to it), and so is every window's sum.  The
     peak is then the lowest delay bin, 0, as in the reference, whichever
     wave, class and lane hold the other bins (four classes per wave for the
-    bands of up to 256 channels, one for 512)."""
+    bands of up to 256 channels, two above; with 16 and 32 channels at pad
+    4 the bins make only one and two classes, and the wave's other classes
+    are ghosts that must never win)."""
     nb, t, ws = 2, 300, [1, 2, 4, 8, 16, 32]
     print(f"case: delay-only exact ties, F = {n_if * n_chan}, pad {pf}", flush=True)
     rng = np.random.default_rng([97, n_if, n_chan, pf])
