@@ -50,9 +50,9 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "d625c8f9da0d8cd172cfbb8987a9f55cf6242c617c68001ca606c11b7bbac8f2",
-    "fetch_bytes": 8393154627,
-    "write_bytes": 2037117414,
+    "kernel_sha256": "1cf2e739bd78e6c4a0c1e2183310d643688edb4ce4ee87139d41bfb0807667d6",
+    "fetch_bytes": 8399287508,
+    "write_bytes": 2040175193,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
@@ -67,11 +67,11 @@ KERNEL_SOURCES = ("dev_common.h", "window_key.h", "fused_search.h", "kernels.h",
 # (per band: spectra mode, time chunk).  Reported only while the sources
 # below hash alike and the run's tuning and launch count are the same.
 MEASURED_TRAFFIC_C3 = {
-    "kernel_sha256": "6df9117234a642f1f084d9400248e25355477d47870f9c914eb9a1526a667e7b",
-    "fused_fetch_bytes": 4959492051455,
-    "fused_write_bytes": 321780602240,
-    "delay_fetch_bytes": 1013314634514,
-    "delay_write_bytes": 4058854429536,
+    "kernel_sha256": "7c1f79d858173625469e3da6a2fc6534980a7dc421df59f8f628547bd7a8335c",
+    "fused_fetch_bytes": 4959593913227,
+    "fused_write_bytes": 321957131680,
+    "delay_fetch_bytes": 1013314659658,
+    "delay_write_bytes": 4058857265088,
     "fused_launches_per_step": 620,
     "delay_launches_per_step": 610,
     "tuning": {128: (1, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
