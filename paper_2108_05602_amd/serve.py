@@ -179,8 +179,8 @@ class FringeServer:
         n = self.chunk_elems[req.sub]
         pay = req.payload
         if pay.device == self.device and pay.is_contiguous():
-            # already in HBM: the plan stages it straight from the request
-            # (which the server holds until the chunk is done); the slot only
+            # already in HBM: the plan reads it where it is (the server
+            # holds the request until the chunk is done); the slot only
             # counts against the admission budget
             src = pay
             if torch.cuda.current_stream() != st:
