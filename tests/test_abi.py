@@ -236,6 +236,12 @@ def test_delay_only_flag_rules():
     full = F.fringe_plan_check([wide], C2_W)
     do = F.fringe_plan_check([wide], C2_W, flags=B.FRINGE_DELAY_ONLY)
     assert full["scratch_bytes"] - do["scratch_bytes"] == full["n_windows"] * (32 * 8 - 16 * 12)
+    # 16 channels at pad 4: one class (M_f = 64) in a wave of four, the
+    # other three ghosts: one key and sum per window against one key
+    narrow = dict(C2, n_if=2, n_chan=8, n_ap=4096)
+    full = F.fringe_plan_check([narrow], C2_W)
+    do = F.fringe_plan_check([narrow], C2_W, flags=B.FRINGE_DELAY_ONLY)
+    assert do["scratch_bytes"] - full["scratch_bytes"] == full["n_windows"] * 4
 
 
 def test_streaming_sizing():
