@@ -295,9 +295,29 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
     if (!has_g) return ww;
     return c_mul(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0), ww);
   };
-  float2 gw[NC][TAB_LDS ? 1 : HFMAX];
+  // Four classes of a 4-fold band, factored: c = cls + jR and M / 64 = 4R
+  // make w_R'^{c h} (R' = M / 64) = w_R'^{cls h} w_4^{j h}, so the four folds
+  // are one multiply per h by fa[h] = g_h w_R'^{cls h}, a 4-point DFT over h
+  // (S_j = sum_h u_h (-i)^{j h}: adds and swaps) and one multiply per class
+  // by fb[j] = w_M^{c l}.  With M / 64 = 2R the second class is cls + R,
+  // whose fold takes (-1)^h, the DFT's S_2 (fmid); ghost classes get fb = 0.
+  constexpr bool FACT = NC == 4 && HFMAX == 4 && !TAB_LDS;
+  float2 fa[FACT ? HFMAX : 1], fb[FACT ? NC : 1];
+  const bool fmid = (M >> 6) < 4 * R;
+  float2 gw[FACT ? 1 : NC][TAB_LDS ? 1 : HFMAX];
   float gn[TAB_LDS ? 1 : HFMAX];
-  if constexpr (TAB_LDS) {
+  if constexpr (FACT) {
+#pragma unroll
+    for (int h = 0; h < HFMAX; ++h) {
+      const float2 w = ld_global(tw + (((cls * h) * 64) & (M - 1)));  // w_R'^{cls h}
+      float2 v = make_float2(in_vgpr(w.x), in_vgpr(w.y));
+      if (has_g) v = c_mul(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0), v);
+      fa[h] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      fb[j] = cls + j * R < (M >> 6) ? wsrc[j] : make_float2(0.f, 0.f);
+  } else if constexpr (TAB_LDS) {
 #pragma unroll
     for (int h = 0; h < HFMAX; ++h) {
 #pragma unroll
@@ -447,12 +467,27 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
 #pragma unroll
             for (int h = 0; h < HFMAX; ++h) pre[fs][h] = sample(pre[fs][h], h, t_in);
           }
+          if constexpr (FACT) {
+            float2 u[HFMAX];
 #pragma unroll
-          for (int j = 0; j < NC; ++j) {
-            float2& zz = z[e * NC + j];
-            zz = c_mul(pre[fs][0], coef_of(j, 0));
+            for (int h = 0; h < HFMAX; ++h) u[h] = c_mul(pre[fs][h], fa[h]);
+            const float2 a0 = c_add(u[0], u[2]), a1 = c_sub(u[0], u[2]);
+            const float2 b0 = c_add(u[1], u[3]), b1 = c_sub(u[1], u[3]);
+            const float2 mb1 = make_float2(b1.y, -b1.x);  // -i b1
+            const float2 s0 = c_add(a0, b0), s2 = c_sub(a0, b0);
+            const float2 s1 = c_add(a1, mb1), s3 = c_sub(a1, mb1);
+            z[e * NC + 0] = c_mul(s0, fb[0]);
+            z[e * NC + 1] = c_mul(fmid ? s2 : s1, fb[1]);
+            z[e * NC + 2] = c_mul(s2, fb[2]);
+            z[e * NC + 3] = c_mul(s3, fb[3]);
+          } else {
 #pragma unroll
-            for (int h = 1; h < HFMAX; ++h) zz = c_add(zz, c_mul(pre[fs][h], coef_of(j, h)));
+            for (int j = 0; j < NC; ++j) {
+              float2& zz = z[e * NC + j];
+              zz = c_mul(pre[fs][0], coef_of(j, 0));
+#pragma unroll
+              for (int h = 1; h < HFMAX; ++h) zz = c_add(zz, c_mul(pre[fs][h], coef_of(j, h)));
+            }
           }
           if (PT > 0 && cls == 0) {  // AP energies: one class per (baseline, chunk) stores them
             float es = 0.f;
