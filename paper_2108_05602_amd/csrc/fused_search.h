@@ -147,6 +147,11 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // lower class (strictly greater replaces) and adds nothing to the sums.
   // One class per wave in the full search.
   constexpr int NC = (PT == 0 && !SRCX) ? delay_only_classes(HFMAX) : 1;
+  // Two classes on a band with 8 or 16 folds (M / 64 = 2R there): their fold
+  // twiddles differ by (-1)^h, so the LDS table holds one coefficient per h,
+  // g_h w_R'^{cls h}, and the classes take the sums over even h plus and
+  // minus the sums over odd h, times their w_M^{c l}.
+  constexpr bool FACT2 = NC == 2 && HFMAX > 4;
 
   const int lane = threadIdx.x;
   // the entry (scan slab) that owns this block
@@ -192,7 +197,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // in registers they would push the kernel with a 64-AP history to one
   // wave per SIMD.  Narrow bands keep both in registers.
   constexpr bool TAB_LDS = HFMAX > 4;
-  __shared__ f32x2_t s_gw[TAB_LDS ? NC * HFMAX : 1][64];  // [class j][fold h] at j HFMAX + h
+  __shared__ f32x2_t s_gw[TAB_LDS ? (FACT2 ? 1 : NC) * HFMAX : 1][64];  // [class j][fold h] at j HFMAX + h
   __shared__ uint32_t s_off[TAB_LDS ? HFMAX : 1][64];
   typedef const volatile __attribute__((address_space(3))) f32x2_t* LdsGw;
   typedef const volatile __attribute__((address_space(3))) uint32_t* LdsOff;
@@ -302,7 +307,7 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
   // by fb[j] = w_M^{c l}.  With M / 64 = 2R the second class is cls + R,
   // whose fold takes (-1)^h, the DFT's S_2 (fmid); ghost classes get fb = 0.
   constexpr bool FACT = NC == 4 && HFMAX == 4 && !TAB_LDS;
-  float2 fa[FACT ? HFMAX : 1], fb[FACT ? NC : 1];
+  float2 fa[FACT ? HFMAX : 1], fb[(FACT || FACT2) ? NC : 1];
   const bool fmid = (M >> 6) < 4 * R;
   float2 gw[FACT ? 1 : NC][TAB_LDS ? 1 : HFMAX];
   float gn[TAB_LDS ? 1 : HFMAX];
@@ -313,6 +318,17 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
       float2 v = make_float2(in_vgpr(w.x), in_vgpr(w.y));
       if (has_g) v = c_mul(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0), v);
       fa[h] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      fb[j] = cls + j * R < (M >> 6) ? wsrc[j] : make_float2(0.f, 0.f);
+  } else if constexpr (FACT2) {
+#pragma unroll
+    for (int h = 0; h < HFMAX; ++h) {
+      const float2 w = ld_global(tw + (((cls * h) * 64) & (M - 1)));  // w_R'^{cls h}
+      float2 v = make_float2(in_vgpr(w.x), in_vgpr(w.y));
+      if (has_g) v = c_mul(ld_buffer(grs, lane8 + 64 * sizeof(float2) * h, 0), v);
+      s_gw[h][lane] = f32x2_t{v.x, v.y};
     }
 #pragma unroll
     for (int j = 0; j < NC; ++j)
@@ -480,6 +496,16 @@ fused_search_kernel(const FusedArgs* __restrict__ tab, int n_tab) {
             z[e * NC + 1] = c_mul(fmid ? s2 : s1, fb[1]);
             z[e * NC + 2] = c_mul(s2, fb[2]);
             z[e * NC + 3] = c_mul(s3, fb[3]);
+          } else if constexpr (FACT2) {
+            float2 ev = c_mul(pre[fs][0], coef_of(0, 0)), od = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int h = 1; h < HFMAX; ++h) {
+              const float2 u = c_mul(pre[fs][h], coef_of(0, h));
+              if (h % 2 == 0) ev = c_add(ev, u);
+              else od = c_add(od, u);
+            }
+            z[e * NC + 0] = c_mul(c_add(ev, od), fb[0]);
+            z[e * NC + 1] = c_mul(c_sub(ev, od), fb[1]);
           } else {
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
