@@ -50,9 +50,9 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
 # taken on: `traffic` is reported as null when the hash of those sources
 # (KERNEL_SOURCES) differs.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "ba2a0c93d27d75ebe42707a151e24f0d87e848faf27b7816bb9278d4ba1915b9",
-    "fetch_bytes": 8416284671,
-    "write_bytes": 2042050048,
+    "kernel_sha256": "7628d6b393b81f70bca09f0985786516a4f2f3b139266c821a33a7b0d0d9bafc",
+    "fetch_bytes": 8398317766,
+    "write_bytes": 2042506361,
 }
 
 # The fused search kernel of the EVN-like scan and the host code that sizes
@@ -67,11 +67,11 @@ KERNEL_SOURCES = ("dev_common.h", "window_key.h", "fused_search.h", "kernels.h",
 # (per band: spectra mode, time chunk).  Reported only while the sources
 # below hash alike and the run's tuning and launch count are the same.
 MEASURED_TRAFFIC_C3 = {
-    "kernel_sha256": "61a299973a33a7da384d54ebb17633d35ddcdb813b05c7a950865761cfdaba34",
-    "fused_fetch_bytes": 4958846694192,
-    "fused_write_bytes": 321795231744,
-    "delay_fetch_bytes": 1013315977396,
-    "delay_write_bytes": 4058857123648,
+    "kernel_sha256": "4b90d7d0c7392d72445054985f44d5a3d73224a89b2b5e4e6a98daebda43cbcf",
+    "fused_fetch_bytes": 4959186448060,
+    "fused_write_bytes": 321859739360,
+    "delay_fetch_bytes": 1013316601416,
+    "delay_write_bytes": 4058853977600,
     "fused_launches_per_step": 620,
     "delay_launches_per_step": 610,
     "tuning": {128: (1, 512), 256: (0, 512), 512: (1, 512), 1024: (1, 512)},
